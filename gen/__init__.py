@@ -1,0 +1,197 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side.
+
+This module draws the inputs of every test and benchmark: RSA keys, messages,
+ciphertexts, exponents and, for tests that pin a base explicitly, 32-bit RNS
+channel primes.  It holds none of the modular-exponentiation arithmetic of the
+method itself: primality tests and inverses use CPython's built-in ``pow``.
+
+Key generation follows the paper's description of the RSA layer (Sec. 3.3 and
+Sec. 4.3): uniform odd candidates, trial division by the first 10,000 primes,
+then Miller-Rabin rounds; the private exponent is the inverse of e modulo
+(p-1)(q-1) (Sec. 3.3).  Bignums are drawn with ``random.Random(seed)`` (whose
+``getrandbits`` is deterministic across platforms); all limb arrays are
+little-endian uint32.
+"""
+from __future__ import annotations
+
+import math
+import random
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+
+__all__ = [
+    "first_primes", "is_probable_prime", "random_prime", "RsaKey", "rsa_key",
+    "uniform_below", "random_exponent", "to_limbs", "limbs_needed",
+    "rns_primes", "config_seed",
+]
+
+# Seed streams: config i uses 1000*i + s, s in {1: keys, 2: messages,
+# 3: exponents, 4: RNS primes, 5: traces}.
+def config_seed(config: int, stream: int) -> int:
+    return 1000 * config + stream
+
+
+@lru_cache(maxsize=None)
+def first_primes(count: int = 10000) -> tuple:
+    """The first ``count`` primes by a sieve of Eratosthenes."""
+    limit = 16
+    while True:
+        sieve = bytearray([1]) * (limit + 1)
+        sieve[0:2] = b"\x00\x00"
+        for i in range(2, int(limit ** 0.5) + 1):
+            if sieve[i]:
+                sieve[i * i::i] = bytearray(len(sieve[i * i::i]))
+        primes = [i for i in range(limit + 1) if sieve[i]]
+        if len(primes) >= count:
+            return tuple(primes[:count])
+        limit *= 2
+
+
+def is_probable_prime(n: int, rounds: int, rng: random.Random) -> bool:
+    """Trial division by the first 10,000 primes, then Miller-Rabin."""
+    if n < 2:
+        return False
+    for p in first_primes(10000):
+        if n == p:
+            return True
+        if n % p == 0:
+            return False
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for _ in range(rounds):
+        a = rng.randrange(2, n - 1)
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def random_prime(bits: int, rng: random.Random, e: int = 65537, rounds: int = 40) -> int:
+    """A prime of exactly ``bits`` bits with its top two bits set, p-1 coprime to e."""
+    if bits < 4:
+        raise ValueError("bits must be >= 4")
+    while True:
+        c = rng.getrandbits(bits) | (3 << (bits - 2)) | 1
+        if math.gcd(e, c - 1) != 1:
+            continue
+        if is_probable_prime(c, rounds, rng):
+            return c
+
+
+@dataclass(frozen=True)
+class RsaKey:
+    n: int
+    e: int
+    d: int
+    p: int
+    q: int
+    dp: int
+    dq: int
+    qinv: int          # q^-1 mod p
+
+    @property
+    def bits(self) -> int:
+        return self.n.bit_length()
+
+
+def rsa_key(bits: int, seed: int, e: int = 65537) -> RsaKey:
+    """Seeded RSA key with an exactly ``bits``-bit modulus n = p*q."""
+    rng = random.Random(seed)
+    half = bits // 2
+    p = random_prime(half, rng, e)
+    while True:
+        q = random_prime(bits - half, rng, e)
+        if q != p:
+            break
+    n = p * q
+    phi = (p - 1) * (q - 1)
+    d = pow(e, -1, phi)
+    return RsaKey(n=n, e=e, d=d, p=p, q=q, dp=d % (p - 1), dq=d % (q - 1),
+                  qinv=pow(q, -1, p))
+
+
+def uniform_below(n: int, count: int, seed: int) -> list:
+    """``count`` integers uniform in [0, n) by rejection on getrandbits."""
+    rng = random.Random(seed)
+    b = n.bit_length()
+    out = []
+    while len(out) < count:
+        x = rng.getrandbits(b)
+        if x < n:
+            out.append(x)
+    return out
+
+
+def random_exponent(bits: int, seed: int) -> int:
+    """Uniform random bits with the top bit set."""
+    rng = random.Random(seed)
+    return rng.getrandbits(bits) | (1 << (bits - 1))
+
+
+def limbs_needed(x: int) -> int:
+    return max(1, (x.bit_length() + 31) // 32)
+
+
+def to_limbs(values, nlimbs: int) -> np.ndarray:
+    """Pack non-negative ints into a [len, nlimbs] little-endian uint32 array."""
+    if isinstance(values, int):
+        values = [values]
+    nbytes = 4 * nlimbs
+    buf = bytearray()
+    for v in values:
+        if v < 0 or v.bit_length() > 32 * nlimbs:
+            raise ValueError("value does not fit in %d limbs" % nlimbs)
+        buf += v.to_bytes(nbytes, "little")
+    return np.frombuffer(bytes(buf), dtype="<u4").reshape(len(values), nlimbs).copy()
+
+
+def _is_prime_u32(n: int) -> bool:
+    # Miller-Rabin with bases 2, 7, 61 is deterministic below 4,759,123,141.
+    if n < 2:
+        return False
+    for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61):
+        if n % p == 0:
+            return n == p
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in (2, 7, 61):
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def rns_primes(count: int, seed: int, lo: int = 1 << 31, hi: int = 1 << 32,
+               exclude=()) -> list:
+    """``count`` distinct primes drawn uniformly from [lo, hi) (seeded)."""
+    if hi > (1 << 32) or lo < 3:
+        raise ValueError("channel primes must lie in [3, 2^32)")
+    rng = random.Random(seed)
+    seen = set(exclude)
+    out = []
+    while len(out) < count:
+        c = rng.randrange(lo, hi) | 1
+        if c >= hi or c in seen:
+            continue
+        if _is_prime_u32(c):
+            seen.add(c)
+            out.append(c)
+    return out

@@ -1,0 +1,49 @@
+"""The seeded input generator: keys have the stated structure and are reproducible."""
+import math
+
+import numpy as np
+
+import gen
+
+
+def test_rsa_key_structure():
+    for bits, cfg in ((1024, 1), (2048, 2)):
+        key = gen.rsa_key(bits, seed=gen.config_seed(cfg, 1))
+        assert key.n == key.p * key.q and key.n.bit_length() == bits
+        assert key.p.bit_length() == key.q.bit_length() == bits // 2
+        phi = (key.p - 1) * (key.q - 1)
+        assert key.e * key.d % phi == 1            # inverse modulo (p-1)(q-1)
+        assert key.dp == key.d % (key.p - 1) and key.dq == key.d % (key.q - 1)
+        assert key.q * key.qinv % key.p == 1
+        # Fermat witnesses with CPython pow, independent of the oracle
+        for a in (2, 3, 5, 7):
+            assert pow(a, key.p - 1, key.p) == 1 and pow(a, key.q - 1, key.q) == 1
+        assert gen.rsa_key(bits, seed=gen.config_seed(cfg, 1)) == key
+
+
+def test_arazi_inverse_formula_matches_euclid():
+    # Sec. 3.1: d = (1 + f * (-f^-1 mod e)) / e is e^-1 mod f for coprime e, f
+    for e, f in ((17, 3120), (65537, 2 ** 61 - 2), (3, 1000)):
+        if math.gcd(e, f) != 1:
+            continue
+        t = (-pow(f, -1, e)) % e
+        num = 1 + f * t
+        assert num % e == 0 and num // e == pow(e, -1, f)
+    assert (1 + 3120 * ((-pow(3120, -1, 17)) % 17)) // 17 == 2753
+
+
+def test_uniform_below_and_limbs():
+    n = (1 << 1000) + 12345
+    xs = gen.uniform_below(n, 100, seed=3)
+    assert all(0 <= x < n for x in xs) and xs == gen.uniform_below(n, 100, seed=3)
+    a = gen.to_limbs(xs, 32)
+    assert a.dtype == np.uint32 and a.shape == (100, 32)
+    assert int.from_bytes(a[5].tobytes(), "little") == xs[5]
+
+
+def test_rns_primes():
+    ps = gen.rns_primes(66, seed=9)
+    assert len(set(ps)) == 66 and all((1 << 31) <= p < (1 << 32) for p in ps)
+    assert all(pow(2, p - 1, p) == 1 for p in ps)
+    hi = gen.rns_primes(10, seed=9, lo=(1 << 32) - (1 << 24))
+    assert all(p >= (1 << 32) - (1 << 24) for p in hi)

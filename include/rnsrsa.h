@@ -1,0 +1,194 @@
+/*
+ * rnsrsa.h -- C ABI of librnsrsa: RSA modular exponentiation over bignums held
+ * in the Residue Number System, on AMD MI355X (gfx950).
+ *
+ * The library implements the modular-arithmetic and RSA layers of Chauvet &
+ * Mahe, "Secrets from the GPU" (arXiv:1305.3699):
+ *   - RNS representation and binary <-> RNS conversion (Sec. 3.1),
+ *   - the RNS Montgomery product with R = M = prod(m_i) and its two base
+ *     extensions, constants precomputed and kept on the device (Sec. 3.1),
+ *   - exponentiation by square-and-multiply chaining Montgomery products in
+ *     the Montgomery domain (Sec. 3.1), here with a fixed window,
+ *   - RSA encryption c = m^e mod n and decryption m = c^d mod n with d the
+ *     inverse of e modulo (p-1)(q-1) (Sec. 3.3), and CRT-split decryption
+ *     with p- and q-halves run side by side (the related-work split of
+ *     Sec. 4.1) recombined by Garner's formula.
+ * Every result is exact and canonical: outputs lie in [0, N).
+ *
+ * Conventions
+ *   Bignums are little-endian arrays of uint32 limbs.  A batch of B numbers of
+ *   L limbs is B*L contiguous limbs, number i at limbs [i*L, (i+1)*L).
+ *   Set-up inputs (moduli, keys, options) are HOST pointers, copied during the
+ *   call.  Batch inputs and outputs are DEVICE pointers owned by the caller.
+ *   Batch calls validate on the host, enqueue on hip_stream (NULL = the null
+ *   stream) and return; results are valid once the stream reaches the point of
+ *   the call.  Contexts and keys are immutable after creation and may be used
+ *   from several streams at once; the caller synchronises those streams before
+ *   freeing them.
+ *   Every function returns RNS_OK (0) or a negative status.  On any status
+ *   other than RNS_EDEVICE nothing was enqueued.  rns_last_error() describes
+ *   the last failure of the calling thread.  No exception or abort crosses
+ *   this boundary.
+ *   Exponentiation follows Python's pow: e = 0 gives 1 mod N (0^0 = 1), bases
+ *   of any value representable in L limbs are accepted and reduced mod N.
+ */
+#ifndef RNSRSA_H
+#define RNSRSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rns_status {
+    RNS_OK = 0,
+    RNS_EINVAL = -1,        /* bad argument (null pointer, bad size, bad option) */
+    RNS_ERANGE = -2,        /* modulus < 2, or too large for any supported base */
+    RNS_EFACTOR = -3,       /* a channel prime of an explicit base divides N */
+    RNS_ENOMEM = -4,        /* host or device allocation failed */
+    RNS_EDEVICE = -5,       /* HIP runtime error */
+    RNS_EVERIFY = -6,       /* reserved: a result failed its self-check */
+    RNS_EBUSY = -7,         /* reserved: admission budget exhausted */
+    RNS_EUNSUPPORTED = -8   /* no kernel is built for the requested shape */
+};
+
+/* Prime ranges for the channel moduli. */
+enum rns_prime_range {
+    RNS_PRIMES_HIGH = 0,    /* primes in [2^32 - 2^24, 2^32) */
+    RNS_PRIMES_FULL = 1     /* primes in (2^31, 2^32): any 32-bit prime */
+};
+
+/*
+ * Options for context / key creation.  Pass NULL for defaults; a zeroed struct
+ * means defaults too.
+ *   k           channels per RNS base (0 = the smallest built base size that
+ *               meets the bounds below).
+ *   window      exponent window width w in 1..6 (0 = 5).  The exponent loop
+ *               precomputes 2^w table entries and does w squarings plus one
+ *               multiplication per w-bit digit.
+ *   waves       wavefronts per workgroup, which split the channels of 64
+ *               messages (0 = default for k; needs an explicit k).
+ *   prime_range rns_prime_range; prime_seed seeds the deterministic draw.
+ *   primes      optional explicit bases: n_primes = 2k distinct primes in
+ *               (2^31, 2^32), B first then B'.  Overrides k and prime_range.
+ * Both bases hold k primes; with the redundant channel 2^32 an operand has
+ * 2k+1 residues.  A base pair is accepted for modulus N of L limbs when
+ *   M >= (k+1)^2 N,  M >= 2^(32L+1),  M' >= (k+1) N,  gcd(N, M) = 1,
+ * which keeps every Montgomery product below (k+1) N and makes the second
+ * base extension exact.
+ */
+typedef struct rns_opts {
+    int k;
+    int window;
+    int waves;
+    int prime_range;
+    uint64_t prime_seed;
+    const uint32_t *primes;
+    size_t n_primes;
+} rns_opts;
+
+typedef struct rns_info {
+    int k;              /* channels per base */
+    int waves;          /* wavefronts per workgroup */
+    int window;         /* exponent window width */
+    int mod_limbs;      /* L */
+    int mod_bits;       /* bit length of N */
+} rns_info;
+
+typedef struct rns_ctx rns_ctx;
+typedef struct rsa_key rsa_key;
+
+/* Status text of the calling thread's last failure ("" if none).  The pointer
+ * is valid until the next library call on this thread. */
+const char *rns_last_error(void);
+
+/* ABI version of this header (currently 1). */
+int rns_abi_version(void);
+
+/*
+ * rns_setup -- precompute and upload the constants for modulus N (Sec. 3.1:
+ * constants of base extension and of the Montgomery product are computed at
+ * initialisation and installed in GPU memory).
+ *   mod        host, mod_limbs limbs, N >= 2 (top limbs may be zero; L =
+ *              mod_limbs is the operand width of every batch call)
+ *   opts       host or NULL
+ *   out        receives the context; release it with rns_free.
+ * Errors: RNS_EINVAL, RNS_ERANGE, RNS_EFACTOR, RNS_EUNSUPPORTED, RNS_ENOMEM,
+ * RNS_EDEVICE.  Uses the current HIP device.
+ */
+int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out);
+void rns_free(rns_ctx *ctx);
+int rns_get_info(const rns_ctx *ctx, rns_info *info);
+/* Copies the 2k channel primes (B then B') to host memory primes[0..2k). */
+int rns_get_primes(const rns_ctx *ctx, uint32_t *primes, size_t n);
+
+/*
+ * rns_modexp_batch -- out[i] = base[i]^e_i mod N for i < batch (Sec. 3.1:
+ * square-and-multiply chaining RNS Montgomery products, entered and left
+ * once per exponentiation).
+ *   base       device, batch x L limbs (any value below 2^(32L))
+ *   exp        device, exponent limbs (exp_limbs >= 1 each)
+ *   exp_stride 0: one exponent exp[0..exp_limbs) shared by the batch;
+ *              otherwise element i's exponent starts at exp + i*exp_stride
+ *              (exp_stride >= exp_limbs)
+ *   out        device, batch x L limbs, canonical; may alias base
+ *   batch      0 is allowed (nothing is enqueued)
+ * Scratch: 2^w * (2k+1) * 4 bytes per element, allocated stream-ordered.
+ */
+int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, size_t exp_limbs,
+                     size_t exp_stride, uint32_t *out, size_t batch, void *hip_stream);
+
+/*
+ * rns_mont_mul_batch -- one RNS Montgomery product per element in the residue
+ * domain (Sec. 3.1, the operation the paper times in its Fig. 1):
+ *   r = (X*Y + q^*N) / M,   q^ = sum_i |x_i y_i (-N^-1) M_i^-1|_{m_i} M_i,
+ * so r == X*Y*M^-1 (mod N) and r < (k+1)N when X, Y < (k+1)N.
+ *   x, y, out  device, (2k+1) x batch residues, channel-major ("structure of
+ *              arrays"): channel c of element i at [c*batch + i]; channels
+ *              0..k-1 are B, k..2k-1 are B', 2k is the redundant 2^32 channel.
+ *              Each input must be the residue vector of one integer below
+ *              (k+1)N; out may alias x or y.
+ */
+int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint32_t *out,
+                       size_t batch, void *hip_stream);
+
+/*
+ * rsa_key_load -- load an RSA key and build its contexts (Sec. 3.3).
+ *   n          host, n_limbs limbs; e host, e_limbs limbs
+ *   d          host, n_limbs limbs, or NULL (public-only key)
+ *   p, q, dp, dq, qinv   host, half_limbs limbs each, or all NULL (no CRT);
+ *              qinv = q^-1 mod p, dp = d mod (p-1), dq = d mod (q-1), n = p*q
+ *   opts       host or NULL; applied to every context of the key
+ * The private parts stay in library-owned memory (the paper keeps private keys
+ * on the GPU, Sec. 4.3).  Release with rsa_key_free.
+ */
+int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_limbs,
+                 const uint32_t *d, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
+                 const uint32_t *dq, const uint32_t *qinv, size_t half_limbs, const rns_opts *opts,
+                 rsa_key **out);
+void rsa_key_free(rsa_key *key);
+int rsa_key_info(const rsa_key *key, int which /* 0 n, 1 p, 2 q */, rns_info *info);
+
+/*
+ * rsa_encrypt -- c[i] = m[i]^e mod n (Sec. 3.3).  m, c: device, batch x n_limbs;
+ * inputs should be below n (raw RSA on integers; larger values are reduced).
+ */
+int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch, void *hip_stream);
+
+/*
+ * rsa_decrypt -- m[i] = c[i]^d mod n.  use_crt = 0: one full-size
+ * exponentiation with d (Sec. 3.3).  use_crt = 1: m_p = c^dp mod p and
+ * m_q = c^dq mod q as two half-size exponentiations in one launch, then
+ * h = (m_p - m_q) qinv mod p and m = m_q + h q (Garner).  c, m: device,
+ * batch x n_limbs, c < n.  RNS_EINVAL if the key lacks the needed parts.
+ */
+int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch, int use_crt,
+                void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNSRSA_H */

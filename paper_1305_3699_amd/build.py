@@ -1,0 +1,96 @@
+"""Build librnsrsa.so (HIP, gfx950) in-tree: paper_1305_3699_amd/_lib/librnsrsa.so.
+
+The kernels are instantiated one (K, W) shape per translation unit so the
+compile runs in parallel; host sources are compiled with the same compiler.
+Usage: python -m paper_1305_3699_amd.build [-j N] [-v]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import re
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INC = os.path.join(ROOT, "include")
+BUILD = os.path.join(HERE, "_build")
+LIBDIR = os.path.join(HERE, "_lib")
+LIB = os.path.join(LIBDIR, "librnsrsa.so")
+ARCH = "gfx950"
+
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+          # packed FP32 instructions stay disabled in every HIP compile
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-command-line-argument", "-I", INC, "-I", CSRC]
+HOST_SOURCES = ["capi.cpp", "plan.cpp", "emul.cpp", "kernels_dispatch.cpp"]
+
+
+def shapes() -> list:
+    txt = open(os.path.join(CSRC, "kernel_configs.inc")).read()
+    return [(int(k), int(w)) for k, w in re.findall(r"RNSRSA_SHAPE\((\d+),\s*(\d+)\)", txt)]
+
+
+def _shape_source(k: int, w: int) -> str:
+    return (
+        '#include "kernels_impl.hpp"\n'
+        "namespace rnsrsa {\n"
+        f"template hipError_t launch_modexp_t<{k}, {w}>(const ModexpLaunch &, hipStream_t);\n"
+        f"template hipError_t launch_garner_t<{k}, {w}>(const GarnerLaunch &, hipStream_t);\n"
+        f"template hipError_t launch_montmul_t<{k}, {w}>(const MontMulLaunch &, hipStream_t);\n"
+        "}\n"
+    )
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stdout))
+    return r.stdout
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Compile every source and link the shared library; returns its path."""
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(LIBDIR, exist_ok=True)
+    units = []
+    for k, w in shapes():
+        src = os.path.join(BUILD, "shape_%d_%d.hip" % (k, w))
+        text = _shape_source(k, w)
+        if not os.path.exists(src) or open(src).read() != text:
+            with open(src, "w") as f:
+                f.write(text)
+        units.append((src, os.path.join(BUILD, "shape_%d_%d.o" % (k, w))))
+    for name in HOST_SOURCES:
+        units.append((os.path.join(CSRC, name), os.path.join(BUILD, name.replace(".cpp", ".o"))))
+    # longest compiles first
+    units.sort(key=lambda u: -int(re.search(r"shape_(\d+)", u[0]).group(1)) if "shape_" in u[0] else 0)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_run, [HIPCC] + COMMON + ["-c", src, "-o", obj], verbose) for src, obj in units]
+        for f in futs:
+            f.result()
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [o for _, o in units], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("-v", action="store_true")
+    a = ap.parse_args(argv)
+    print(build(a.j, a.v))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,497 @@
+// The exported C ABI of librnsrsa (include/rnsrsa.h, include/rnsrsa_host.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "emul.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "rnsrsa.h"
+#include "rnsrsa_host.h"
+
+using namespace rnsrsa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return RNS_OK;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(RNS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int window_or_default(const rns_opts *o) { return (o && o->window) ? o->window : 5; }
+
+PlanOptions plan_options(const rns_opts *o) {
+    PlanOptions p;
+    if (!o) return p;
+    p.k = o->k;
+    p.waves = o->waves;
+    p.range = o->prime_range;
+    if (o->prime_seed) p.seed = o->prime_seed;
+    p.primes = o->primes;
+    p.n_primes = o->n_primes;
+    return p;
+}
+
+// Device copies of base tables, one per (base set, device), kept for the life
+// of the process: a handful of distinct base sets exist per process.
+std::mutex g_dev_mu;
+std::map<std::pair<const BaseSet *, int>, std::pair<std::shared_ptr<const BaseSet>, uint32_t *>> g_dev_bases;
+
+int upload(const std::vector<uint32_t> &v, uint32_t **out) {
+    *out = nullptr;
+    if (v.empty()) return RNS_OK;
+    hipError_t e = hipMalloc((void **)out, v.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    e = hipMemcpy(*out, v.data(), v.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(*out);
+        *out = nullptr;
+        return hip_fail(e, "hipMemcpy");
+    }
+    return RNS_OK;
+}
+
+int device_base(const std::shared_ptr<const BaseSet> &bs, uint32_t **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto key = std::make_pair(bs.get(), dev);
+    auto it = g_dev_bases.find(key);
+    if (it != g_dev_bases.end()) {
+        *out = it->second.second;
+        return RNS_OK;
+    }
+    uint32_t *d = nullptr;
+    int rc = upload(bs->blob, &d);
+    if (rc) return rc;
+    g_dev_bases[key] = std::make_pair(bs, d);
+    *out = d;
+    return RNS_OK;
+}
+
+// Stream-ordered allocations keep scratch out of the caller's way; the pool
+// keeps freed blocks so repeated calls do not go back to the driver.
+void configure_pool_once() {
+    static std::once_flag flag;
+    std::call_once(flag, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return;
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+        uint64_t thr = UINT64_MAX;
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    });
+}
+
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~Scratch() {
+        if (p) hipFreeAsync(p, s);
+    }
+};
+
+int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s) {
+    sc.s = s;
+    if (bytes == 0) return RNS_OK;
+    configure_pool_once();
+    hipError_t e = hipMallocAsync(&sc.p, bytes, s);
+    if (e != hipSuccess) {
+        sc.p = nullptr;
+        return fail(RNS_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    return RNS_OK;
+}
+
+}  // namespace
+
+// A modulus with its device tables.
+struct rns_ctx {
+    ModPlan plan;
+    int window = 5;
+    int device = 0;
+    uint32_t *d_base = nullptr;  // shared, owned by the process-wide cache
+    uint32_t *d_mod = nullptr;
+    uint32_t *d_entry = nullptr;  // entry table for L-limb inputs (factor M^2 mod N)
+    ~rns_ctx() {
+        if (d_mod) hipFree(d_mod);
+        if (d_entry) hipFree(d_entry);
+    }
+};
+
+struct rns_plan {
+    ModPlan plan;
+    int window = 5;
+};
+
+struct rsa_key {
+    size_t n_limbs = 0, e_limbs = 0, half = 0;
+    rns_ctx *n = nullptr;
+    uint32_t *d_e = nullptr, *d_d = nullptr;
+    bool has_crt = false;
+    rns_ctx *p = nullptr, *q = nullptr;
+    uint32_t *d_dp = nullptr, *d_dq = nullptr;
+    uint32_t *d_centry_p = nullptr, *d_centry_q = nullptr;  // entry tables for n_limbs-limb inputs
+    uint32_t *d_gentry = nullptr;                           // Garner entry table (p-modulus)
+    uint32_t *d_qlimbs = nullptr;
+    ~rsa_key() {
+        delete n;
+        delete p;
+        delete q;
+        for (uint32_t *x : {d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_gentry, d_qlimbs})
+            if (x) hipFree(x);
+    }
+};
+
+namespace {
+
+int ctx_from_plan(ModPlan &&mp, int window, rns_ctx **out) {
+    std::unique_ptr<rns_ctx> c(new (std::nothrow) rns_ctx);
+    if (!c) return fail(RNS_ENOMEM, "out of host memory");
+    c->plan = std::move(mp);
+    c->window = window;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int rc = device_base(c->plan.base, &c->d_base);
+    if (rc) return rc;
+    if ((rc = upload(c->plan.blob, &c->d_mod))) return rc;
+    std::vector<uint32_t> E = make_entry_table(c->plan, {c->plan.R2}, c->plan.L);
+    if ((rc = upload(E, &c->d_entry))) return rc;
+    *out = c.release();
+    return RNS_OK;
+}
+
+bool valid_window(int w) { return w >= 1 && w <= 6; }
+
+int check_opts(const rns_opts *o) {
+    if (o && o->window && !valid_window(o->window)) return fail(RNS_EINVAL, "window must be in 1..6");
+    if (o && o->primes && o->n_primes == 0) return fail(RNS_EINVAL, "primes given with n_primes = 0");
+    return RNS_OK;
+}
+
+// Launch one or two exponentiation jobs sharing the inputs.
+int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
+               int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
+               uint32_t *out1, int out_stride, size_t batch, hipStream_t s) {
+    const BaseSet &bs = *c0->plan.base;
+    const int njobs = c1 ? 2 : 1;
+    const size_t wgs = (batch + 63) / 64 * njobs;
+    Scratch table;
+    int rc = scratch_alloc(table, modexp_table_words(bs.K, bs.W, c0->window, wgs) * sizeof(uint32_t), s);
+    if (rc) return rc;
+    ModexpLaunch a{};
+    a.bc = c0->d_base;
+    a.mc[0] = c0->d_mod;
+    a.mc[1] = c1 ? c1->d_mod : c0->d_mod;
+    a.E[0] = E0;
+    a.E[1] = E1 ? E1 : E0;
+    a.exp[0] = x0;
+    a.exp[1] = x1 ? x1 : x0;
+    a.in = in;
+    a.out[0] = out0;
+    a.out[1] = out1 ? out1 : out0;
+    a.table = (uint32_t *)table.p;
+    a.P.in_limbs = in_limbs;
+    a.P.in_stride = in_limbs;
+    a.P.L = c0->plan.L;
+    a.P.out_stride = out_stride;
+    a.P.exp_limbs = exp_limbs;
+    a.P.exp_stride = exp_stride;
+    a.P.window = c0->window;
+    a.P.batch = (int)batch;
+    a.njobs = njobs;
+    hipError_t e = launch_modexp(bs.K, bs.W, a, s);
+    if (e != hipSuccess) return hip_fail(e, "modexp launch");
+    return RNS_OK;
+}
+
+Limbs limbs_of(const uint32_t *p, size_t n) { return bn_from_ptr(p, n); }
+
+}  // namespace
+
+extern "C" {
+
+const char *rns_last_error(void) { return g_err.c_str(); }
+
+int rns_abi_version(void) { return 1; }
+
+int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out) {
+    if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");
+    *out = nullptr;
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    try {
+        ModPlan mp;
+        std::string err;
+        rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), mp, err);
+        if (rc) return fail(rc, err);
+        rc = ctx_from_plan(std::move(mp), window_or_default(opts), out);
+        if (rc) return rc;
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(RNS_EINVAL, "internal error during setup");
+    }
+    return ok();
+}
+
+void rns_free(rns_ctx *ctx) { delete ctx; }
+
+int rns_get_info(const rns_ctx *ctx, rns_info *info) {
+    if (!ctx || !info) return fail(RNS_EINVAL, "null argument");
+    info->k = ctx->plan.base->K;
+    info->waves = ctx->plan.base->W;
+    info->window = ctx->window;
+    info->mod_limbs = ctx->plan.L;
+    info->mod_bits = (int)bn_bits(ctx->plan.N);
+    return ok();
+}
+
+int rns_get_primes(const rns_ctx *ctx, uint32_t *primes, size_t n) {
+    if (!ctx || !primes) return fail(RNS_EINVAL, "null argument");
+    const BaseSet &bs = *ctx->plan.base;
+    if (n < (size_t)(2 * bs.K)) return fail(RNS_EINVAL, "buffer shorter than 2k");
+    std::copy(bs.B.begin(), bs.B.end(), primes);
+    std::copy(bs.Bp.begin(), bs.Bp.end(), primes + bs.K);
+    return ok();
+}
+
+int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, size_t exp_limbs, size_t exp_stride,
+                     uint32_t *out, size_t batch, void *hip_stream) {
+    if (!ctx) return fail(RNS_EINVAL, "null context");
+    if (batch == 0) return ok();
+    if (!base || !exp || !out || exp_limbs == 0) return fail(RNS_EINVAL, "null buffer or zero exponent limbs");
+    if (exp_stride != 0 && exp_stride < exp_limbs) return fail(RNS_EINVAL, "exp_stride below exp_limbs");
+    if (batch > (size_t)INT32_MAX - 64 || exp_limbs > 1u << 20 || exp_stride > 1u << 24)
+        return fail(RNS_EINVAL, "batch or exponent too large");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != ctx->device) return fail(RNS_EINVAL, "context belongs to another device");
+    int rc = run_modexp(ctx, nullptr, ctx->d_entry, nullptr, base, ctx->plan.L, exp, nullptr, (int)exp_limbs,
+                        (int)exp_stride, out, nullptr, ctx->plan.L, batch, (hipStream_t)hip_stream);
+    return rc ? rc : ok();
+}
+
+int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch,
+                       void *hip_stream) {
+    if (!ctx) return fail(RNS_EINVAL, "null context");
+    if (batch == 0) return ok();
+    if (!x || !y || !out) return fail(RNS_EINVAL, "null buffer");
+    if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
+    const BaseSet &bs = *ctx->plan.base;
+    MontMulLaunch a{ctx->d_base, ctx->d_mod, x, y, out, (int)batch};
+    hipError_t e = launch_montmul(bs.K, bs.W, a, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "montmul launch");
+    return ok();
+}
+
+int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_limbs, const uint32_t *d,
+                 const uint32_t *p, const uint32_t *q, const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
+                 size_t half_limbs, const rns_opts *opts, rsa_key **out) {
+    if (!n || !e || !out || n_limbs == 0 || e_limbs == 0 || n_limbs > 4096 || e_limbs > 4096)
+        return fail(RNS_EINVAL, "bad key arguments");
+    *out = nullptr;
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    const bool any_crt = p || q || dp || dq || qinv;
+    const bool all_crt = p && q && dp && dq && qinv;
+    if (any_crt && !all_crt) return fail(RNS_EINVAL, "CRT parts must be all present or all NULL");
+    if (all_crt && (half_limbs == 0 || 2 * half_limbs < n_limbs)) return fail(RNS_EINVAL, "bad half_limbs");
+    if (opts && opts->primes && all_crt) return fail(RNS_EINVAL, "explicit primes apply to one modulus only");
+    try {
+        std::unique_ptr<rsa_key> key(new rsa_key);
+        key->n_limbs = n_limbs;
+        key->e_limbs = e_limbs;
+        key->half = half_limbs;
+        const int window = window_or_default(opts);
+        std::string err;
+        {
+            ModPlan mp;
+            rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, plan_options(opts), mp, err);
+            if (rc) return fail(rc, err);
+            if ((rc = ctx_from_plan(std::move(mp), window, &key->n))) return rc;
+        }
+        if ((rc = upload(std::vector<uint32_t>(e, e + e_limbs), &key->d_e))) return rc;
+        if (d && (rc = upload(std::vector<uint32_t>(d, d + n_limbs), &key->d_d))) return rc;
+        if (all_crt) {
+            const int L = (int)half_limbs;
+            Limbs P = limbs_of(p, half_limbs), Q = limbs_of(q, half_limbs);
+            Limbs big = bn_cmp(P, Q) >= 0 ? P : Q;
+            ModPlan pp, qp;
+            rc = make_modplan(big, L, plan_options(opts), pp, err);  // base set fitting both halves
+            if (rc) return fail(rc, err);
+            std::shared_ptr<const BaseSet> bs = pp.base;
+            if ((rc = make_modplan_on(P, L, bs, pp, err))) return fail(rc, err);
+            if ((rc = make_modplan_on(Q, L, bs, qp, err))) return fail(rc, err);
+            // inputs of n_limbs limbs enter as sum_h c_h (2^(32 L h) M^2 mod p)
+            const int chunks = (int)((n_limbs + half_limbs - 1) / half_limbs);
+            std::vector<Limbs> Yp, Yq;
+            for (int h = 0; h < chunks; h++) {
+                Yp.push_back(bn_mod(bn_mul(bn_shl(Limbs{1}, 32u * L * h), pp.R2), P));
+                Yq.push_back(bn_mod(bn_mul(bn_shl(Limbs{1}, 32u * L * h), qp.R2), Q));
+            }
+            std::vector<uint32_t> Ep = make_entry_table(pp, Yp, L), Eq = make_entry_table(qp, Yq, L);
+            Ep.resize((size_t)n_limbs * Layout{bs->K, bs->KP}.ecols());
+            Eq.resize((size_t)n_limbs * Layout{bs->K, bs->KP}.ecols());
+            // Garner: Z = m_p A + m_q (p - A), A = qinv M mod p
+            Limbs A = bn_mod(bn_mul(limbs_of(qinv, half_limbs), pp.Mmod), P);
+            Limbs Bv = bn_is_zero(A) ? Limbs{} : bn_sub(P, A);
+            std::vector<uint32_t> Eg = make_entry_table(pp, {A, Bv}, L);
+            if ((rc = ctx_from_plan(std::move(pp), window, &key->p))) return rc;
+            if ((rc = ctx_from_plan(std::move(qp), window, &key->q))) return rc;
+            if ((rc = upload(Ep, &key->d_centry_p))) return rc;
+            if ((rc = upload(Eq, &key->d_centry_q))) return rc;
+            if ((rc = upload(Eg, &key->d_gentry))) return rc;
+            if ((rc = upload(std::vector<uint32_t>(dp, dp + half_limbs), &key->d_dp))) return rc;
+            if ((rc = upload(std::vector<uint32_t>(dq, dq + half_limbs), &key->d_dq))) return rc;
+            if ((rc = upload(std::vector<uint32_t>(q, q + half_limbs), &key->d_qlimbs))) return rc;
+            key->has_crt = true;
+        }
+        *out = key.release();
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(RNS_EINVAL, "internal error during key load");
+    }
+    return ok();
+}
+
+void rsa_key_free(rsa_key *key) { delete key; }
+
+int rsa_key_info(const rsa_key *key, int which, rns_info *info) {
+    if (!key || !info) return fail(RNS_EINVAL, "null argument");
+    const rns_ctx *c = which == 0 ? key->n : which == 1 ? key->p : which == 2 ? key->q : nullptr;
+    if (!c) return fail(RNS_EINVAL, "no such context in this key");
+    return rns_get_info(c, info);
+}
+
+int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch, void *hip_stream) {
+    if (!key) return fail(RNS_EINVAL, "null key");
+    if (batch == 0) return ok();
+    if (!m || !c) return fail(RNS_EINVAL, "null buffer");
+    if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
+    const rns_ctx *x = key->n;
+    int rc = run_modexp(x, nullptr, x->d_entry, nullptr, m, x->plan.L, key->d_e, nullptr, (int)key->e_limbs, 0, c,
+                        nullptr, x->plan.L, batch, (hipStream_t)hip_stream);
+    return rc ? rc : ok();
+}
+
+int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch, int use_crt, void *hip_stream) {
+    if (!key) return fail(RNS_EINVAL, "null key");
+    if (batch == 0) return ok();
+    if (!c || !m) return fail(RNS_EINVAL, "null buffer");
+    if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!use_crt) {
+        if (!key->d_d) return fail(RNS_EINVAL, "key has no private exponent");
+        const rns_ctx *x = key->n;
+        int rc = run_modexp(x, nullptr, x->d_entry, nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
+                            nullptr, x->plan.L, batch, s);
+        return rc ? rc : ok();
+    }
+    if (!key->has_crt) return fail(RNS_EINVAL, "key has no CRT parts");
+    const int L = (int)key->half;
+    Scratch ws;  // [m_p | m_q] per element
+    int rc = scratch_alloc(ws, batch * 2 * (size_t)L * sizeof(uint32_t), s);
+    if (rc) return rc;
+    uint32_t *w = (uint32_t *)ws.p;
+    rc = run_modexp(key->p, key->q, key->d_centry_p, key->d_centry_q, c, (int)key->n_limbs, key->d_dp, key->d_dq, L,
+                    0, w, w + L, 2 * L, batch, s);
+    if (rc) return rc;
+    const BaseSet &bs = *key->p->plan.base;
+    GarnerLaunch g{};
+    g.bc = key->p->d_base;
+    g.mc = key->p->d_mod;
+    g.E = key->d_gentry;
+    g.qlimbs = key->d_qlimbs;
+    g.in = w;
+    g.out = m;
+    g.L = L;
+    g.out_limbs = (int)key->n_limbs;
+    g.out_stride = (int)key->n_limbs;
+    g.batch = (int)batch;
+    hipError_t e = launch_garner(bs.K, bs.W, g, s);
+    if (e != hipSuccess) return hip_fail(e, "garner launch");
+    return ok();
+}
+
+// ---- host-side planning and model ---------------------------------------
+
+int rns_plan_create(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_plan **out) {
+    if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");
+    *out = nullptr;
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    try {
+        std::unique_ptr<rns_plan> p(new rns_plan);
+        std::string err;
+        rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), p->plan, err);
+        if (rc) return fail(rc, err);
+        p->window = window_or_default(opts);
+        *out = p.release();
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
+    }
+    return ok();
+}
+
+void rns_plan_free(rns_plan *plan) { delete plan; }
+
+int rns_plan_info(const rns_plan *plan, rns_info *info) {
+    if (!plan || !info) return fail(RNS_EINVAL, "null argument");
+    info->k = plan->plan.base->K;
+    info->waves = plan->plan.base->W;
+    info->window = plan->window;
+    info->mod_limbs = plan->plan.L;
+    info->mod_bits = (int)bn_bits(plan->plan.N);
+    return ok();
+}
+
+int rns_plan_primes(const rns_plan *plan, uint32_t *primes, size_t n) {
+    if (!plan || !primes) return fail(RNS_EINVAL, "null argument");
+    const BaseSet &bs = *plan->plan.base;
+    if (n < (size_t)(2 * bs.K)) return fail(RNS_EINVAL, "buffer shorter than 2k");
+    std::copy(bs.B.begin(), bs.B.end(), primes);
+    std::copy(bs.Bp.begin(), bs.Bp.end(), primes + bs.K);
+    return ok();
+}
+
+int rns_emul_modexp(const rns_plan *plan, const uint32_t *base, const uint32_t *exp, size_t exp_limbs,
+                    size_t exp_stride, uint32_t *out, size_t batch) {
+    if (!plan) return fail(RNS_EINVAL, "null plan");
+    if (batch == 0) return ok();
+    if (!base || !exp || !out || exp_limbs == 0) return fail(RNS_EINVAL, "null buffer or zero exponent limbs");
+    if (exp_stride != 0 && exp_stride < exp_limbs) return fail(RNS_EINVAL, "exp_stride below exp_limbs");
+    std::vector<uint32_t> E = make_entry_table(plan->plan, {plan->plan.R2}, plan->plan.L);
+    emul_modexp(plan->plan, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride, plan->window, out, batch);
+    return ok();
+}
+
+int rns_emul_mont_mul(const rns_plan *plan, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch) {
+    if (!plan) return fail(RNS_EINVAL, "null plan");
+    if (batch == 0) return ok();
+    if (!x || !y || !out) return fail(RNS_EINVAL, "null buffer");
+    emul_mont_mul(plan->plan, x, y, out, batch);
+    return ok();
+}
+
+}  // extern "C"

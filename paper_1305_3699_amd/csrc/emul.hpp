@@ -1,0 +1,20 @@
+// Host model of the exponentiation kernels (emul.cpp).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace rnsrsa {
+
+// Same contract as the modexp kernel for one job: inputs of in_limbs limbs
+// mapped through entry table E, outputs of mp.L limbs.
+void emul_modexp(const ModPlan &mp, const std::vector<uint32_t> &E, int in_limbs, const uint32_t *base,
+                 const uint32_t *exp, int exp_limbs, size_t exp_stride, int window, uint32_t *out,
+                 size_t batch);
+
+void emul_mont_mul(const ModPlan &mp, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch);
+
+}  // namespace rnsrsa

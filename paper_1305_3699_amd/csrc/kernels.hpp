@@ -1,0 +1,67 @@
+// Launch interface of the RNS modular-exponentiation kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rnsrsa {
+
+// Parameters shared by the two exponentiation jobs of one launch.
+struct ModexpParams {
+    int in_limbs;    // input limbs per element
+    int in_stride;   // limbs between consecutive inputs
+    int L;           // output limbs (modulus limbs)
+    int out_stride;  // limbs between consecutive outputs
+    int exp_limbs;   // exponent limbs
+    int exp_stride;  // 0: one exponent shared by the batch
+    int window;      // window width w, 1..6
+    int batch;       // elements per job
+};
+
+// One launch runs njobs (1 or 2) exponentiation jobs with the same base set:
+// job j uses modulus table mc[j], entry table E[j], exponent exp[j] and writes
+// out[j]; all jobs read the same inputs (a CRT decryption runs its p- and
+// q-halves as the two jobs of one launch).
+struct ModexpLaunch {
+    const uint32_t *bc;
+    const uint32_t *mc[2];
+    const uint32_t *E[2];
+    const uint32_t *exp[2];
+    const uint32_t *in;
+    uint32_t *out[2];
+    uint32_t *table;  // scratch, modexp_table_words(...) words
+    ModexpParams P;
+    int njobs;
+};
+
+// Garner recombination m = m_q + q * ((m_p - m_q) qinv mod p) over the
+// p-modulus tables: in = [m_p | m_q] (2*L limbs per element).
+struct GarnerLaunch {
+    const uint32_t *bc;
+    const uint32_t *mc;    // p-modulus table
+    const uint32_t *E;     // entry table mapping (m_p, m_q) to (m_p - m_q) qinv M
+    const uint32_t *qlimbs;  // L limbs of q
+    const uint32_t *in;
+    uint32_t *out;
+    int L;          // half limbs
+    int out_limbs;  // limbs written per result (<= 2L)
+    int out_stride;
+    int batch;
+};
+
+struct MontMulLaunch {
+    const uint32_t *bc;
+    const uint32_t *mc;
+    const uint32_t *x, *y;
+    uint32_t *out;
+    int batch;
+};
+
+size_t modexp_table_words(int K, int W, int window, size_t workgroups);
+hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s);
+hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s);
+hipError_t launch_montmul(int K, int W, const MontMulLaunch &a, hipStream_t s);
+
+}  // namespace rnsrsa

@@ -1,0 +1,50 @@
+// Dispatch from a runtime (K, W) shape to the kernel instantiations, which
+// are compiled one shape per translation unit (see the build script).
+#include "kernels.hpp"
+
+namespace rnsrsa {
+
+template <int K, int W>
+hipError_t launch_modexp_t(const ModexpLaunch &a, hipStream_t s);
+template <int K, int W>
+hipError_t launch_garner_t(const GarnerLaunch &a, hipStream_t s);
+template <int K, int W>
+hipError_t launch_montmul_t(const MontMulLaunch &a, hipStream_t s);
+
+#define RNSRSA_SHAPE(k, w)                                                          \
+    extern template hipError_t launch_modexp_t<k, w>(const ModexpLaunch &, hipStream_t); \
+    extern template hipError_t launch_garner_t<k, w>(const GarnerLaunch &, hipStream_t); \
+    extern template hipError_t launch_montmul_t<k, w>(const MontMulLaunch &, hipStream_t);
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+
+size_t modexp_table_words(int K, int W, int window, size_t workgroups) {
+    const int KS = (K + W - 1) / W;
+    return workgroups * ((size_t)1 << window) * (size_t)W * (2 * KS + 1) * 64;
+}
+
+hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s) {
+#define RNSRSA_SHAPE(k, w) \
+    if (K == k && W == w) return launch_modexp_t<k, w>(a, s);
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s) {
+#define RNSRSA_SHAPE(k, w) \
+    if (K == k && W == w) return launch_garner_t<k, w>(a, s);
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_montmul(int K, int W, const MontMulLaunch &a, hipStream_t s) {
+#define RNSRSA_SHAPE(k, w) \
+    if (K == k && W == w) return launch_montmul_t<k, w>(a, s);
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rnsrsa

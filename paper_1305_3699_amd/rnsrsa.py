@@ -1,0 +1,326 @@
+"""Python binding of librnsrsa (ctypes), argument marshalling only.
+
+Every computation runs in the HIP library: the binding converts Python
+integers to limb arrays for set-up calls, checks tensor shapes, and passes
+device pointers and the current HIP stream.  Batch buffers are torch int32
+tensors on the GPU used as raw 32-bit limb storage (little-endian limbs,
+one row per element).  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "librnsrsa.so")
+
+RNS_OK = 0
+STATUS_NAMES = {0: "RNS_OK", -1: "RNS_EINVAL", -2: "RNS_ERANGE", -3: "RNS_EFACTOR", -4: "RNS_ENOMEM",
+                -5: "RNS_EDEVICE", -6: "RNS_EVERIFY", -7: "RNS_EBUSY", -8: "RNS_EUNSUPPORTED"}
+PRIMES_HIGH = 0
+PRIMES_FULL = 1
+
+
+class RnsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, message))
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("window", ctypes.c_int), ("waves", ctypes.c_int),
+                ("prime_range", ctypes.c_int), ("prime_seed", ctypes.c_uint64),
+                ("primes", ctypes.POINTER(ctypes.c_uint32)), ("n_primes", ctypes.c_size_t)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("waves", ctypes.c_int), ("window", ctypes.c_int),
+                ("mod_limbs", ctypes.c_int), ("mod_bits", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_S = ctypes.c_size_t
+_I = ctypes.c_int
+_SIGNATURES = {
+    "rns_last_error": ([], ctypes.c_char_p),
+    "rns_abi_version": ([], _I),
+    "rns_setup": ([_P, _S, _P, _P], _I),
+    "rns_free": ([_P], None),
+    "rns_get_info": ([_P, _P], _I),
+    "rns_get_primes": ([_P, _P, _S], _I),
+    "rns_modexp_batch": ([_P, _P, _P, _S, _S, _P, _S, _P], _I),
+    "rns_mont_mul_batch": ([_P, _P, _P, _P, _S, _P], _I),
+    "rsa_key_load": ([_P, _S, _P, _S, _P, _P, _P, _P, _P, _P, _S, _P, _P], _I),
+    "rsa_key_free": ([_P], None),
+    "rsa_key_info": ([_P, _I, _P], _I),
+    "rsa_encrypt": ([_P, _P, _P, _S, _P], _I),
+    "rsa_decrypt": ([_P, _P, _P, _S, _I, _P], _I),
+    "rns_plan_create": ([_P, _S, _P, _P], _I),
+    "rns_plan_free": ([_P], None),
+    "rns_plan_info": ([_P, _P], _I),
+    "rns_plan_primes": ([_P, _P, _S], _I),
+    "rns_emul_modexp": ([_P, _P, _P, _S, _S, _P, _S], _I),
+    "rns_emul_mont_mul": ([_P, _P, _P, _P, _S], _I),
+}
+
+_lib_handle = None
+
+
+def lib():
+    """The loaded library (raises ImportError if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("librnsrsa.so not found at %s; build it with "
+                          "`python -m paper_1305_3699_amd.build`" % LIB_PATH)
+    h = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGNATURES.items():
+        f = getattr(h, name)
+        f.argtypes = args
+        f.restype = res
+    _lib_handle = h
+    return h
+
+
+def exported_symbols() -> list:
+    return sorted(_SIGNATURES)
+
+
+def _check(rc: int) -> None:
+    if rc != RNS_OK:
+        msg = lib().rns_last_error()
+        raise RnsError(rc, msg.decode() if msg else "")
+
+
+def int_to_limbs(x: int, nlimbs: int) -> np.ndarray:
+    if x < 0 or x.bit_length() > 32 * nlimbs:
+        raise ValueError("integer does not fit in %d limbs" % nlimbs)
+    return np.frombuffer(x.to_bytes(4 * nlimbs, "little"), dtype="<u4").copy()
+
+
+def nlimbs(x: int) -> int:
+    return max(1, (x.bit_length() + 31) // 32)
+
+
+def _host_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _make_opts(k=0, window=0, waves=0, prime_range=PRIMES_HIGH, prime_seed=0, primes=None):
+    o = Opts()
+    o.k, o.window, o.waves, o.prime_range, o.prime_seed = k, window, waves, prime_range, prime_seed
+    keep = None
+    if primes is not None:
+        keep = np.ascontiguousarray(primes, dtype=np.uint32)
+        o.primes = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        o.n_primes = keep.size
+    return o, keep
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_ptr(t, rows: int, cols: int, what: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % what)
+    if t.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        raise TypeError("%s must hold 32-bit limbs (torch.int32)" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() != rows * cols:
+        raise ValueError("%s must have %d x %d limbs, got shape %s" % (what, rows, cols, tuple(t.shape)))
+    return t.data_ptr()
+
+
+def _info(getter, handle, *extra) -> dict:
+    inf = Info()
+    _check(getter(handle, *extra, ctypes.byref(inf)))
+    return {"k": inf.k, "waves": inf.waves, "window": inf.window, "mod_limbs": inf.mod_limbs,
+            "mod_bits": inf.mod_bits}
+
+
+class RnsContext:
+    """A modulus N with its RNS bases and constants resident on the GPU."""
+
+    def __init__(self, modulus: int, mod_limbs: Optional[int] = None, **opts):
+        self.modulus = int(modulus)
+        self.L = mod_limbs or nlimbs(self.modulus)
+        mod = int_to_limbs(self.modulus, self.L)
+        o, keep = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().rns_setup(_host_ptr(mod), self.L, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rns_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> dict:
+        return _info(lib().rns_get_info, self._h)
+
+    @property
+    def primes(self) -> list:
+        k = self.info["k"]
+        out = np.zeros(2 * k, dtype=np.uint32)
+        _check(lib().rns_get_primes(self._h, _host_ptr(out), out.size))
+        return [int(p) for p in out]
+
+    def modexp(self, base, exp, out=None, stream=None):
+        """out[i] = base[i]^e mod N.  base: [B, L] int32 CUDA tensor; exp: [E]
+        (shared) or [B, E] (per element).  Returns out ([B, L])."""
+        import torch
+        B = base.shape[0] if base.dim() == 2 else 0
+        if base.dim() != 2 or base.shape[1] != self.L:
+            raise ValueError("base must be [B, %d]" % self.L)
+        if exp.dim() == 1:
+            E, stride = exp.shape[0], 0
+            xp = _dev_ptr(exp, 1, E, "exp")
+        elif exp.dim() == 2 and exp.shape[0] == B:
+            E, stride = exp.shape[1], exp.shape[1]
+            xp = _dev_ptr(exp, B, E, "exp")
+        else:
+            raise ValueError("exp must be [E] or [B, E]")
+        if out is None:
+            out = torch.empty_like(base)
+        _check(lib().rns_modexp_batch(self._h, _dev_ptr(base, B, self.L, "base"), xp, E, stride,
+                                      _dev_ptr(out, B, self.L, "out"), B, _stream_handle(stream)))
+        return out
+
+    def mont_mul(self, x, y, out=None, stream=None):
+        """One RNS Montgomery product per element on [2k+1, B] residue tensors."""
+        import torch
+        k = self.info["k"]
+        if x.dim() != 2 or x.shape[0] != 2 * k + 1 or y.shape != x.shape:
+            raise ValueError("x, y must be [2k+1, B]")
+        B = x.shape[1]
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().rns_mont_mul_batch(self._h, _dev_ptr(x, 2 * k + 1, B, "x"), _dev_ptr(y, 2 * k + 1, B, "y"),
+                                        _dev_ptr(out, 2 * k + 1, B, "out"), B, _stream_handle(stream)))
+        return out
+
+
+class RsaKey:
+    """An RSA key (Sec. 3.3) with its RNS contexts resident on the GPU."""
+
+    def __init__(self, n: int, e: int, d: Optional[int] = None, p: Optional[int] = None,
+                 q: Optional[int] = None, dp: Optional[int] = None, dq: Optional[int] = None,
+                 qinv: Optional[int] = None, n_limbs: Optional[int] = None, **opts):
+        self.n, self.e = int(n), int(e)
+        self.L = n_limbs or nlimbs(self.n)
+        nl = int_to_limbs(self.n, self.L)
+        el = int_to_limbs(self.e, nlimbs(self.e))
+        dl = int_to_limbs(int(d), self.L) if d is not None else None
+        crt = [p, q, dp, dq, qinv]
+        if any(v is not None for v in crt) and not all(v is not None for v in crt):
+            raise ValueError("p, q, dp, dq, qinv must be given together")
+        half = max(nlimbs(int(p)), nlimbs(int(q))) if p is not None else 0
+        arrs = [int_to_limbs(int(v), half) if v is not None else None for v in crt]
+        ptr = lambda a: _host_ptr(a) if a is not None else None
+        o, keep = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().rsa_key_load(_host_ptr(nl), self.L, _host_ptr(el), el.size, ptr(dl), *[ptr(a) for a in arrs],
+                                  half, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.has_crt = p is not None
+        del keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rsa_key_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, which: int = 0) -> dict:
+        return _info(lib().rsa_key_info, self._h, which)
+
+    def encrypt(self, m, out=None, stream=None):
+        import torch
+        B = m.shape[0]
+        if out is None:
+            out = torch.empty_like(m)
+        _check(lib().rsa_encrypt(self._h, _dev_ptr(m, B, self.L, "m"), _dev_ptr(out, B, self.L, "out"), B,
+                                 _stream_handle(stream)))
+        return out
+
+    def decrypt(self, c, use_crt: bool = True, out=None, stream=None):
+        import torch
+        B = c.shape[0]
+        if out is None:
+            out = torch.empty_like(c)
+        _check(lib().rsa_decrypt(self._h, _dev_ptr(c, B, self.L, "c"), _dev_ptr(out, B, self.L, "out"), B,
+                                 1 if use_crt else 0, _stream_handle(stream)))
+        return out
+
+
+class Plan:
+    """Host-side planning and the host model of the kernels (no GPU needed)."""
+
+    def __init__(self, modulus: int, mod_limbs: Optional[int] = None, **opts):
+        self.modulus = int(modulus)
+        self.L = mod_limbs or nlimbs(self.modulus)
+        mod = int_to_limbs(self.modulus, self.L)
+        o, keep = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().rns_plan_create(_host_ptr(mod), self.L, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().rns_plan_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> dict:
+        return _info(lib().rns_plan_info, self._h)
+
+    @property
+    def primes(self) -> list:
+        k = self.info["k"]
+        out = np.zeros(2 * k, dtype=np.uint32)
+        _check(lib().rns_plan_primes(self._h, _host_ptr(out), out.size))
+        return [int(p) for p in out]
+
+    def emul_modexp(self, base: np.ndarray, exp: np.ndarray) -> np.ndarray:
+        base = np.ascontiguousarray(base, dtype=np.uint32)
+        exp = np.ascontiguousarray(exp, dtype=np.uint32)
+        B = base.shape[0]
+        if base.ndim != 2 or base.shape[1] != self.L:
+            raise ValueError("base must be [B, %d]" % self.L)
+        E, stride = (exp.shape[0], 0) if exp.ndim == 1 else (exp.shape[1], exp.shape[1])
+        out = np.zeros((B, self.L), dtype=np.uint32)
+        _check(lib().rns_emul_modexp(self._h, _host_ptr(base), _host_ptr(exp), E, stride, _host_ptr(out), B))
+        return out
+
+    def emul_mont_mul(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.uint32)
+        y = np.ascontiguousarray(y, dtype=np.uint32)
+        out = np.zeros_like(x)
+        _check(lib().rns_emul_mont_mul(self._h, _host_ptr(x), _host_ptr(y), _host_ptr(out), x.shape[1]))
+        return out

@@ -1,0 +1,222 @@
+"""GPU parity: every output of the HIP path equals the CPU oracle, bit for bit.
+
+All calls go through the C ABI (ctypes binding) on torch-allocated device
+buffers.  Inputs are seeded and synthetic (gen); expected values come from
+the oracle only.
+"""
+import math
+import random
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import rns_ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the GPU tests need an MI355X")
+    from paper_1305_3699_amd import rnsrsa
+    rnsrsa.lib()          # fails loudly if the HIP library is missing
+    yield
+
+
+def _dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def _host(t) -> np.ndarray:
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _ctx(N, L, **kw):
+    from paper_1305_3699_amd import RnsContext
+    return RnsContext(N, L, **kw)
+
+
+def _run_modexp(ctx, bases, exp):
+    b = _dev(bases)
+    e = _dev(exp)
+    out = ctx.modexp(b, e)
+    return _host(out)
+
+
+def test_toy_key_all_messages():
+    """Encrypt and decrypt every m < 3233 with the textbook key (51 groups of
+    64 plus a ragged tail of 33)."""
+    N, e, d = 3233, 17, 2753
+    ctx = _ctx(N, 1)
+    msgs = np.arange(N, dtype=np.uint32)[:, None]
+    c = _run_modexp(ctx, msgs, np.array([e], np.uint32))
+    assert np.array_equal(c, oracle.modexp_batch(msgs, np.array([e], np.uint32), np.array([N], np.uint32)))
+    m = _run_modexp(ctx, c, np.array([d], np.uint32))
+    assert np.array_equal(m, msgs)
+    assert c[65, 0] == 2790
+
+
+@pytest.mark.parametrize("bits", [20, 64, 100, 500, 1024, 1500, 2048, 3072, 4096])
+def test_modexp_sizes(bits):
+    rng = random.Random(bits)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | rng.getrandbits(1)
+    L = (bits + 31) // 32
+    ctx = _ctx(N, L)
+    B = 130                                   # two full groups of 64 and a tail of 2
+    bases = [rng.getrandbits(32 * L) for _ in range(B - 4)] + [0, 1, N - 1, (1 << (32 * L)) - 1]
+    ebits = 96 if bits > 1024 else 257
+    e = rng.getrandbits(ebits) | (1 << (ebits - 1))
+    el = gen.to_limbs(e, (ebits + 31) // 32)[0]
+    got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
+    want = oracle.modexp_batch(gen.to_limbs(bases, L), el, gen.to_limbs(N, L)[0])
+    assert np.array_equal(got, want)
+
+
+def test_edge_exponents():
+    rng = random.Random(5)
+    N = rng.getrandbits(777) | (1 << 776) | 1
+    L = 25
+    ctx = _ctx(N, L, window=3)
+    bases = [0, 1, 2, N - 1, N, N + 1, (1 << (32 * L)) - 1] + [rng.getrandbits(32 * L) for _ in range(9)]
+    for e in (0, 1, 2, 3, 8, 65537, (1 << 64) - 1):
+        el = gen.to_limbs(e, 2)[0]
+        got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
+        assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases], e
+
+
+def test_per_element_exponents():
+    rng = random.Random(8)
+    N = rng.getrandbits(1024) | (1 << 1023) | 1
+    ctx = _ctx(N, 32)
+    B = 100
+    bases = [rng.getrandbits(1024) for _ in range(B)]
+    exps = [rng.getrandbits(rng.choice([0, 1, 7, 64, 130])) for _ in range(B)]
+    got = _run_modexp(ctx, gen.to_limbs(bases, 32), gen.to_limbs(exps, 5))
+    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b, e in zip(bases, exps)]
+
+
+@pytest.mark.parametrize("window", [1, 2, 3, 4, 5, 6])
+def test_window_invariance(window):
+    rng = random.Random(77)
+    N = rng.getrandbits(1024) | (1 << 1023) | 1
+    ctx = _ctx(N, 32, window=window)
+    bases = [rng.getrandbits(1024) for _ in range(70)]
+    e = rng.getrandbits(1024)
+    el = gen.to_limbs(e, 32)[0]
+    got = _run_modexp(ctx, gen.to_limbs(bases, 32), el)
+    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
+
+
+@pytest.mark.parametrize("k,waves", [(17, 1), (17, 2), (33, 1), (33, 2), (33, 3), (33, 4), (49, 7), (65, 5)])
+def test_shape_invariance(k, waves):
+    rng = random.Random(k * 10 + waves)
+    bits = 32 * (k - 1)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = k - 1
+    ctx = _ctx(N, L, k=k, waves=waves)
+    info = ctx.info
+    assert info["k"] == k and info["waves"] == waves
+    bases = [rng.getrandbits(32 * L) for _ in range(66)]
+    e = rng.getrandbits(80)
+    el = gen.to_limbs(e, 3)[0]
+    got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
+    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
+
+
+def test_mont_mul_matches_definition():
+    rng = random.Random(3)
+    N = rng.getrandbits(1024) | (1 << 1023) | 1
+    ctx = _ctx(N, 32)
+    k = ctx.info["k"]
+    pr = ctx.primes
+    B, Bp = pr[:k], pr[k:]
+    n = 200
+    X = [rng.randrange((k + 1) * N) for _ in range(n - 2)] + [0, (k + 1) * N - 1]
+    Y = [rng.randrange((k + 1) * N) for _ in range(n - 2)] + [(k + 1) * N - 1, (k + 1) * N - 1]
+
+    def res(vals):
+        return np.array([[v % m for v in vals] for m in B] + [[v % m for v in vals] for m in Bp]
+                        + [[v % (1 << 32) for v in vals]], dtype=np.uint32)
+
+    out = _host(ctx.mont_mul(_dev(res(X)), _dev(res(Y))))
+    want = res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)])
+    assert np.array_equal(out, want)
+
+
+def test_rsa1024_config_bit_exact():
+    """One seeded RSA-1024 key, 64 messages, 64 encryptions and 64 plain
+    decryptions with bases of 2 x 33 random 32-bit primes."""
+    from paper_1305_3699_amd import PRIMES_FULL, RsaKey
+    key = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
+    rk = RsaKey(key.n, key.e, key.d, prime_range=PRIMES_FULL, prime_seed=gen.config_seed(1, 4))
+    assert rk.info(0)["k"] == 33
+    ms = gen.uniform_below(key.n, 64, seed=gen.config_seed(1, 2))
+    c = _host(rk.encrypt(_dev(gen.to_limbs(ms, 32))))
+    want_c = oracle.modexp_batch(gen.to_limbs(ms, 32), gen.to_limbs(key.e, 1)[0], gen.to_limbs(key.n, 32)[0])
+    assert np.array_equal(c, want_c)
+    m = _host(rk.decrypt(_dev(c), use_crt=False))
+    want_m = oracle.modexp_batch(c, gen.to_limbs(key.d, 32)[0], gen.to_limbs(key.n, 32)[0])
+    assert np.array_equal(m, want_m)
+    assert oracle.rows_to_ints(m) == ms
+
+
+def _rsa2048():
+    from paper_1305_3699_amd import RsaKey
+    key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
+    return key, RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv)
+
+
+def test_rsa2048_crt_decrypt_small():
+    key, rk = _rsa2048()
+    c = gen.uniform_below(key.n, 120, seed=11) + [0, 1, key.n - 1, key.p, 2 * key.q, key.q, key.p * 3, key.n - key.p]
+    cl = gen.to_limbs(c, 64)
+    got = _host(rk.decrypt(_dev(cl), use_crt=True))
+    want = oracle.rsa_crt_batch(cl, key.p, key.q, key.dp, key.dq, key.qinv)
+    assert np.array_equal(got, want)
+    # the definition: c^d mod n
+    assert oracle.rows_to_ints(got[:8]) == [pow(x, key.d, key.n) for x in c[:8]]
+
+
+def test_rsa2048_crt_full_batch_sampled():
+    """The benchmark's launch: 16384 ciphertexts in one CRT decryption.  The
+    oracle checks 48 sampled rows; every row is checked by re-encryption."""
+    key, rk = _rsa2048()
+    B = 16384
+    c = gen.uniform_below(key.n, B, seed=gen.config_seed(2, 2))
+    cl = gen.to_limbs(c, 64)
+    dc = _dev(cl)
+    m = rk.decrypt(dc, use_crt=True)
+    back = _host(rk.encrypt(m))
+    assert np.array_equal(back, cl)
+    mh = _host(m)
+    idx = sorted(random.Random(1).sample(range(B), 46)) + [0, B - 1]
+    want = oracle.rsa_crt_batch(cl[idx], key.p, key.q, key.dp, key.dq, key.qinv)
+    assert np.array_equal(mh[idx], want)
+
+
+def test_determinism_and_aliasing():
+    rng = random.Random(12)
+    N = rng.getrandbits(2048) | (1 << 2047) | 1
+    ctx = _ctx(N, 64)
+    bases = gen.to_limbs([rng.getrandbits(2048) for _ in range(64)], 64)
+    el = gen.to_limbs(rng.getrandbits(300), 10)[0]
+    b = _dev(bases)
+    e = _dev(el)
+    r1 = _host(ctx.modexp(b, e))
+    r2 = _host(ctx.modexp(b, e))
+    assert np.array_equal(r1, r2)
+    ctx.modexp(b, e, out=b)                   # out aliases base
+    assert np.array_equal(_host(b), r1)
+
+
+def test_zero_batch_is_a_no_op():
+    ctx = _ctx(3233, 1)
+    empty = torch.zeros((0, 1), dtype=torch.int32, device="cuda")
+    out = ctx.modexp(empty, torch.tensor([5], dtype=torch.int32, device="cuda"))
+    assert out.shape == (0, 1)

@@ -1,0 +1,147 @@
+"""Host-side tests of librnsrsa (no GPU): the library loads and exports every
+declared symbol, base planning obeys its bounds, error paths return the
+documented status codes, and the host model of the kernels agrees with the
+oracle (which pins the constant tables and the algorithm before any GPU run).
+"""
+import math
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import rns_ref
+from paper_1305_3699_amd import rnsrsa
+from paper_1305_3699_amd.rnsrsa import Plan, RnsError
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in ("rnsrsa.h", "rnsrsa_host.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(?:int|void|const char \*)\s*\*?\s*((?:rns|rsa)_\w+)\s*\(", txt):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rnsrsa.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(rnsrsa.exported_symbols())
+    assert lib.rns_abi_version() == 1
+
+
+def _check_bounds(plan, N, L):
+    info = plan.info
+    k = info["k"]
+    pr = plan.primes
+    B, Bp = pr[:k], pr[k:]
+    assert len(set(pr)) == 2 * k
+    assert all((1 << 31) < p < (1 << 32) and pow(2, p - 1, p) == 1 for p in pr)
+    M, Mp = math.prod(B), math.prod(Bp)
+    assert M >= (k + 1) ** 2 * N and M >= 2 ** (32 * L + 1) and Mp >= (k + 1) * N
+    assert math.gcd(M, N) == 1
+
+
+@pytest.mark.parametrize("bits", [2, 12, 64, 512, 1024, 2048, 3072, 4096])
+def test_plan_bounds(bits):
+    N = (1 << bits) - 1 if bits > 2 else 3
+    L = (bits + 31) // 32
+    p = Plan(N, L)
+    _check_bounds(p, N, L)
+    assert p.info["k"] >= L + 1
+
+
+def test_plan_full_range_primes_rsa1024():
+    key = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
+    p = Plan(key.n, 32, prime_range=rnsrsa.PRIMES_FULL, prime_seed=gen.config_seed(1, 4))
+    assert p.info["k"] == 33
+    _check_bounds(p, key.n, 32)
+
+
+def test_plan_errors():
+    with pytest.raises(RnsError) as e:
+        Plan(1)
+    assert e.value.status == -2                      # RNS_ERANGE
+    with pytest.raises(RnsError) as e:
+        Plan(3233, window=9)
+    assert e.value.status == -1                      # RNS_EINVAL
+    with pytest.raises(RnsError) as e:
+        Plan(3233, k=7)                              # no kernel for k = 7
+    assert e.value.status == -8
+    with pytest.raises(RnsError) as e:
+        Plan(3233, primes=[5, 7, 11, 13])            # not 32-bit primes
+    assert e.value.status == -1
+    pr = gen.rns_primes(4, seed=1)
+    with pytest.raises(RnsError) as e:
+        Plan(pr[0] * 3, primes=pr)                   # a channel prime divides N
+    assert e.value.status == -3
+    with pytest.raises(RnsError) as e:
+        Plan((1 << 200) + 1, 7, primes=pr)           # base too small
+    assert e.value.status == -2
+
+
+def _res(vals, B, Bp):
+    return np.array([[v % m for v in vals] for m in B] + [[v % m for v in vals] for m in Bp]
+                    + [[v % (1 << 32) for v in vals]], dtype=np.uint32)
+
+
+@pytest.mark.parametrize("bits", [12, 300, 1024, 2048])
+def test_emul_mont_mul_matches_definition(bits):
+    rng = random.Random(bits)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = (bits + 31) // 32
+    p = Plan(N, L)
+    k = p.info["k"]
+    B, Bp = p.primes[:k], p.primes[k:]
+    X = [rng.randrange((k + 1) * N) for _ in range(20)] + [0, (k + 1) * N - 1]
+    Y = [rng.randrange((k + 1) * N) for _ in range(20)] + [(k + 1) * N - 1, (k + 1) * N - 1]
+    out = p.emul_mont_mul(_res(X, B, Bp), _res(Y, B, Bp))
+    want = [rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)]
+    assert np.array_equal(out, _res(want, B, Bp))
+
+
+@pytest.mark.parametrize("bits,window", [(12, 5), (64, 1), (250, 3), (1024, 5), (1024, 6), (2048, 4)])
+def test_emul_modexp_matches_oracle(bits, window):
+    rng = random.Random(bits * 7 + window)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | rng.getrandbits(1)
+    L = (bits + 31) // 32
+    p = Plan(N, L, window=window)
+    bases = [rng.getrandbits(32 * L) for _ in range(5)] + [0, 1, N - 1, N, (1 << (32 * L)) - 1]
+    e = rng.getrandbits(min(bits, 200)) | 1
+    out = p.emul_modexp(gen.to_limbs(bases, L), gen.to_limbs(e, (e.bit_length() + 31) // 32)[0])
+    want = oracle.modexp_batch(gen.to_limbs(bases, L), gen.to_limbs(e, (e.bit_length() + 31) // 32)[0],
+                               gen.to_limbs(N, L)[0])
+    assert np.array_equal(out, want)
+
+
+def test_emul_edge_exponents_and_per_element():
+    N = 3233
+    p = Plan(N, 1, window=2)
+    bases = list(range(0, 40)) + [N - 1, N, 2 ** 32 - 1]
+    for e in (0, 1, 2, 3, 17, 2753):
+        out = p.emul_modexp(gen.to_limbs(bases, 1), np.array([e], np.uint32))
+        assert out[:, 0].tolist() == [pow(b, e, N) for b in bases]
+    rng = random.Random(3)
+    exps = [rng.getrandbits(40) for _ in bases]
+    out = p.emul_modexp(gen.to_limbs(bases, 1), gen.to_limbs(exps, 2))
+    assert out[:, 0].tolist() == [pow(b, e, N) for b, e in zip(bases, exps)]
+
+
+def test_emul_rsa1024_config_round_trip():
+    key = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
+    p = Plan(key.n, 32, prime_range=rnsrsa.PRIMES_FULL, prime_seed=gen.config_seed(1, 4))
+    ms = gen.uniform_below(key.n, 4, seed=gen.config_seed(1, 2))
+    c = p.emul_modexp(gen.to_limbs(ms, 32), gen.to_limbs(key.e, 1)[0])
+    assert oracle.rows_to_ints(c) == [pow(m, key.e, key.n) for m in ms]
+    m = p.emul_modexp(c, gen.to_limbs(key.d, 32)[0])
+    assert oracle.rows_to_ints(m) == ms

@@ -1,0 +1,281 @@
+"""Benchmark: RSA-2048 CRT decryptions per second on one MI355X.
+
+One step = one CRT decryption of a batch of 16384 ciphertexts (seeded, uniform
+in [0, n), one seeded RSA-2048 key, full-length d_p and d_q) resident in HBM:
+the two 1024-bit half exponentiations in one launch, then the Garner launch.
+Prints one JSON line (see the design doc for every field).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--window w]
+  python bench.py --sweep-window      # one line per window width 1..6
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RSA-2048 CRT decrypts/sec on 1 MI355X (batched vs plain), p50/p99 latency"
+# MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz; v_mad_u64_u32 (32x32->64
+# multiply-add) issues at the full per-lane rate on gfx950.
+PEAK_MUL_PER_S = 256 * 64 * 2.4e9
+KERNEL_SOURCES = ["paper_1305_3699_amd/csrc/kernels_impl.hpp", "paper_1305_3699_amd/csrc/arith.hpp",
+                  "paper_1305_3699_amd/csrc/kernel_configs.inc"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def mm_count(exp: int, exp_bits: int, w: int) -> int:
+    """RNS Montgomery products of one exponentiation as the kernel schedules
+    them: entry, 2^w - 2 table products, w squarings per digit after the
+    leading non-zero one plus one multiply per non-zero digit, exit."""
+    nd = (exp_bits + w - 1) // w
+    digits = [(exp >> (w * (nd - 1 - i))) & ((1 << w) - 1) for i in range(nd)]
+    n = 1 + (1 << w) - 2 + 1
+    started = False
+    for d in digits:
+        if not started:
+            started = d != 0
+            continue
+        n += w + (1 if d else 0)
+    return n
+
+
+def wide_muls_per_mm(k: int) -> int:
+    """Algorithmic 32x32->64 products of one RNS Montgomery product: the two
+    base extensions (k(k+1) each) and seven per-channel products per channel."""
+    return 2 * k * (k + 1) + 7 * k
+
+
+def cpu_threads() -> int:
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def load_traffic(kernel_name: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or kernel_name not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel_name].get("bytes_per_launch")
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, calib_mb: int) -> dict:
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
+    into HBM bytes per launch of each kernel, scaled so that the calibration
+    kernel (an elementwise copy reading and writing calib_mb MiB) reads exactly
+    calib_mb MiB and writes calib_mb MiB; writes profiles/traffic.json."""
+    import csv
+
+    def per_kernel(path):
+        rows = list(csv.DictReader(open(path)))
+        vals = {}
+        for r in rows:
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    known_kib = calib_mb * 1024.0
+    calib = [v for name, vs in f.items() if "elementwise" in name for v in vs]
+    fetch_scale = known_kib / max(calib)
+    calib_w = [v for name, vs in w.items() if "elementwise" in name for v in vs]
+    write_scale = known_kib / max(calib_w)
+    out = {"kernel_source_hash": kernel_source_hash(), "fetch_scale": round(fetch_scale, 4),
+           "write_scale": round(write_scale, 4), "calibration": "elementwise copy of %d MiB" % calib_mb,
+           "kernels": {}}
+    for name in f:
+        short = name.split("(")[0].replace("void ", "").replace("rnsrsa::", "")
+        base = short.split("<")[0]
+        if base not in ("modexp_kernel", "garner_kernel", "montmul_kernel"):
+            continue
+        fk = statistics.mean(f[name]) * fetch_scale
+        wk = statistics.mean(w.get(name, [0.0])) * write_scale
+        out["kernels"][base] = {"instance": short, "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                                "bytes_per_launch": int(round((fk + wk) * 1024))}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def run(args) -> dict:
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1305_3699_amd import RsaKey
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs the GPU")
+    torch.cuda.set_device(0)
+    key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
+    opts = {"window": args.window}
+    if args.waves:
+        opts.update(k=33, waves=args.waves)
+    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, **opts)
+    info = rk.info(1)
+    B = args.batch
+    c_int = gen.uniform_below(key.n, B, seed=gen.config_seed(2, 2))
+    c_np = gen.to_limbs(c_int, 64)
+    c = torch.from_numpy(c_np.view(np.int32)).cuda()
+    half = rk.half_limbs
+    mpq = torch.empty((B, 2 * half), dtype=torch.int32, device="cuda")
+    m = torch.empty((B, 64), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    if args.calib_copy_mb:
+        # a plain streaming kernel of known traffic (reads and writes N MiB) for
+        # scaling hardware byte counters; runs before and outside the timed region
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.zeros(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(args.warmup):
+        rk.crt_halves(c, out=mpq)
+        rk.crt_combine(mpq, out=m)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b, d in evs:
+        a.record(stream)
+        rk.crt_halves(c, out=mpq)
+        b.record(stream)
+        rk.crt_combine(mpq, out=m)
+        d.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    step_ms = [a.elapsed_time(d) for a, b, d in evs]
+    modexp_ms = [a.elapsed_time(b) for a, b, d in evs]
+    garner_ms = [b.elapsed_time(d) for a, b, d in evs]
+    wall = t1 - t0
+    value = B * args.steps / wall
+
+    k = info["k"]
+    mms = mm_count(key.dp, 32 * half, info["window"]) + mm_count(key.dq, 32 * half, info["window"])
+    muls_per_launch = B * mms * wide_muls_per_mm(k)
+    mean_modexp_s = statistics.mean(modexp_ms) / 1e3
+    achieved = muls_per_launch / mean_modexp_s
+
+    sq = sorted(step_ms)
+    p50 = statistics.median(sq)
+    p99 = sq[min(len(sq) - 1, int(round(0.99 * (len(sq) - 1))))]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "decrypts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded RSA-2048 key, ciphertexts uniform in [0,n))",
+        "config": {
+            "workload": "RSA-2048 CRT decryption of %d ciphertexts per step, full-length d_p/d_q, "
+                        "both 1024-bit halves in one launch, then Garner" % B,
+            "form": "plain",
+            "batch": B,
+            "key_bits": 2048,
+            "k": k,
+            "waves": info["waves"],
+            "window": info["window"],
+        },
+        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "what": "one step (batch of %d)" % B},
+        "modexps_per_s": round(2 * value, 1),
+        "kernels_ms": {"modexp_crt_halves": round(statistics.mean(modexp_ms), 4),
+                       "garner": round(statistics.mean(garner_ms), 4)},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "modexp_kernel<%d,%d>" % (k, info["waves"]),
+            "achieved": round(achieved / 1e12, 4),
+            "peak": round(PEAK_MUL_PER_S / 1e12, 4),
+            "unit": "Tmul/s",
+            "frac": round(achieved / PEAK_MUL_PER_S, 4),
+            "traffic": load_traffic("modexp_kernel"),
+            "work_per_launch": muls_per_launch,
+            "mm_per_decrypt": mms,
+        },
+        "cpu_baseline": None,
+    }
+    if args.cpu_sample > 0:
+        import oracle
+        ns = min(args.cpu_sample, B)
+        threads = cpu_threads()
+        sample = c_np[:ns]
+        t2 = time.perf_counter()
+        ref = oracle.rsa_crt_batch(sample, key.p, key.q, key.dp, key.dq, key.qinv, nthreads=threads)
+        t3 = time.perf_counter()
+        got = m.cpu().numpy().view(np.uint32)[:ns]
+        out["cpu_baseline"] = {
+            "value": round(ns / (t3 - t2), 2),
+            "unit": "decrypts/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d of the %d ciphertexts, the oracle's schoolbook CRT/Garner path, %.1f s wall"
+                      % (ns, B, t3 - t2),
+            "matches_gpu": bool(np.array_equal(ref, got)),
+        }
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--window", type=int, default=6)
+    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (k = 33 shapes)")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="ciphertexts for the oracle baseline (0: skip)")
+    ap.add_argument("--sweep-window", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one elementwise copy of N MiB before the benchmark (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from rocprofv3 counter_collection.csv files")
+    args = ap.parse_args(argv)
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters, calib_mb=args.calib_copy_mb or 256), indent=1))
+        return 0
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(multi-GPU sharding is a design note, not a measured configuration)", file=sys.stderr)
+        return 2
+    if args.sweep_window:
+        for w in range(1, 7):
+            args.window = w
+            r = run(argparse.Namespace(**{**vars(args), "cpu_sample": 0}))
+            print(json.dumps(r), flush=True)
+        return 0
+    print(json.dumps(run(args)), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

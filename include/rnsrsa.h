@@ -160,7 +160,9 @@ int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint3
  *   d          host, n_limbs limbs, or NULL (public-only key)
  *   p, q, dp, dq, qinv   host, half_limbs limbs each, or all NULL (no CRT);
  *              qinv = q^-1 mod p, dp = d mod (p-1), dq = d mod (q-1), n = p*q
- *   opts       host or NULL; applied to every context of the key
+ *   opts       host or NULL; applied to every context of the key, except that
+ *              an explicit k too small for n (one sized for the CRT halves)
+ *              leaves the full-modulus context sized automatically
  * The private parts stay in library-owned memory (the paper keeps private keys
  * on the GPU, Sec. 4.3).  Release with rsa_key_free.
  */
@@ -186,6 +188,20 @@ int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch
  */
 int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch, int use_crt,
                 void *hip_stream);
+
+/*
+ * The two launches of a CRT decryption, exposed separately (rsa_decrypt with
+ * use_crt = 1 is exactly rsa_crt_halves followed by rsa_crt_combine):
+ *   rsa_crt_halves   mpq[i] = (c[i]^dp mod p, c[i]^dq mod q): both half-size
+ *                    exponentiations in one launch.  c: device, batch x
+ *                    n_limbs; mpq: device, batch x (2 * half_limbs), m_p in
+ *                    the first half_limbs limbs of a row, m_q in the rest.
+ *   rsa_crt_combine  m[i] = m_q + q ((m_p - m_q) qinv mod p) (Garner), from
+ *                    an mpq buffer laid out as above; m: batch x n_limbs.
+ * RNS_EINVAL if the key has no CRT parts.
+ */
+int rsa_crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, void *hip_stream);
+int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -225,6 +225,32 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
 
 Limbs limbs_of(const uint32_t *p, size_t n) { return bn_from_ptr(p, n); }
 
+// Both half-size exponentiations of a CRT decryption in one launch.
+int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s) {
+    const int L = (int)key->half;
+    return run_modexp(key->p, key->q, key->d_centry_p, key->d_centry_q, c, (int)key->n_limbs, key->d_dp, key->d_dq,
+                      L, 0, mpq, mpq + L, 2 * L, batch, s);
+}
+
+// Garner recombination over the p-modulus tables.
+int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s) {
+    const BaseSet &bs = *key->p->plan.base;
+    GarnerLaunch g{};
+    g.bc = key->p->d_base;
+    g.mc = key->p->d_mod;
+    g.E = key->d_gentry;
+    g.qlimbs = key->d_qlimbs;
+    g.in = mpq;
+    g.out = m;
+    g.L = (int)key->half;
+    g.out_limbs = (int)key->n_limbs;
+    g.out_stride = (int)key->n_limbs;
+    g.batch = (int)batch;
+    hipError_t e = launch_garner(bs.K, bs.W, g, s);
+    if (e != hipSuccess) return hip_fail(e, "garner launch");
+    return RNS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -326,7 +352,14 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
         std::string err;
         {
             ModPlan mp;
-            rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, plan_options(opts), mp, err);
+            PlanOptions po = plan_options(opts);
+            rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, po, mp, err);
+            if (rc == RNS_ERANGE && all_crt && po.k) {
+                // an explicit k sized for the CRT halves: size the full modulus automatically
+                po.k = 0;
+                po.waves = 0;
+                rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, po, mp, err);
+            }
             if (rc) return fail(rc, err);
             if ((rc = ctx_from_plan(std::move(mp), window, &key->n))) return rc;
         }
@@ -409,29 +442,32 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
         return rc ? rc : ok();
     }
     if (!key->has_crt) return fail(RNS_EINVAL, "key has no CRT parts");
-    const int L = (int)key->half;
     Scratch ws;  // [m_p | m_q] per element
-    int rc = scratch_alloc(ws, batch * 2 * (size_t)L * sizeof(uint32_t), s);
+    int rc = scratch_alloc(ws, batch * 2 * key->half * sizeof(uint32_t), s);
     if (rc) return rc;
-    uint32_t *w = (uint32_t *)ws.p;
-    rc = run_modexp(key->p, key->q, key->d_centry_p, key->d_centry_q, c, (int)key->n_limbs, key->d_dp, key->d_dq, L,
-                    0, w, w + L, 2 * L, batch, s);
-    if (rc) return rc;
-    const BaseSet &bs = *key->p->plan.base;
-    GarnerLaunch g{};
-    g.bc = key->p->d_base;
-    g.mc = key->p->d_mod;
-    g.E = key->d_gentry;
-    g.qlimbs = key->d_qlimbs;
-    g.in = w;
-    g.out = m;
-    g.L = L;
-    g.out_limbs = (int)key->n_limbs;
-    g.out_stride = (int)key->n_limbs;
-    g.batch = (int)batch;
-    hipError_t e = launch_garner(bs.K, bs.W, g, s);
-    if (e != hipSuccess) return hip_fail(e, "garner launch");
+    if ((rc = crt_halves(key, c, (uint32_t *)ws.p, batch, s))) return rc;
+    if ((rc = crt_combine(key, (uint32_t *)ws.p, m, batch, s))) return rc;
     return ok();
+}
+
+int rsa_crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, void *hip_stream) {
+    if (!key) return fail(RNS_EINVAL, "null key");
+    if (batch == 0) return ok();
+    if (!c || !mpq) return fail(RNS_EINVAL, "null buffer");
+    if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
+    if (!key->has_crt) return fail(RNS_EINVAL, "key has no CRT parts");
+    int rc = crt_halves(key, c, mpq, batch, (hipStream_t)hip_stream);
+    return rc ? rc : ok();
+}
+
+int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, void *hip_stream) {
+    if (!key) return fail(RNS_EINVAL, "null key");
+    if (batch == 0) return ok();
+    if (!mpq || !m) return fail(RNS_EINVAL, "null buffer");
+    if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
+    if (!key->has_crt) return fail(RNS_EINVAL, "key has no CRT parts");
+    int rc = crt_combine(key, mpq, m, batch, (hipStream_t)hip_stream);
+    return rc ? rc : ok();
 }
 
 // ---- host-side planning and model ---------------------------------------

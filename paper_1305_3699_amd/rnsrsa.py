@@ -58,6 +58,8 @@ _SIGNATURES = {
     "rsa_key_info": ([_P, _I, _P], _I),
     "rsa_encrypt": ([_P, _P, _P, _S, _P], _I),
     "rsa_decrypt": ([_P, _P, _P, _S, _I, _P], _I),
+    "rsa_crt_halves": ([_P, _P, _P, _S, _P], _I),
+    "rsa_crt_combine": ([_P, _P, _P, _S, _P], _I),
     "rns_plan_create": ([_P, _S, _P, _P], _I),
     "rns_plan_free": ([_P], None),
     "rns_plan_info": ([_P, _P], _I),
@@ -240,6 +242,7 @@ class RsaKey:
                                   half, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self.has_crt = p is not None
+        self._half = half
         del keep
 
     def close(self):
@@ -272,6 +275,31 @@ class RsaKey:
             out = torch.empty_like(c)
         _check(lib().rsa_decrypt(self._h, _dev_ptr(c, B, self.L, "c"), _dev_ptr(out, B, self.L, "out"), B,
                                  1 if use_crt else 0, _stream_handle(stream)))
+        return out
+
+
+    @property
+    def half_limbs(self) -> int:
+        return self._half
+
+    def crt_halves(self, c, out=None, stream=None):
+        """[B, 2*half] tensor of (c^dp mod p | c^dq mod q) per row (one launch)."""
+        import torch
+        B = c.shape[0]
+        if out is None:
+            out = torch.empty((B, 2 * self._half), dtype=torch.int32, device=c.device)
+        _check(lib().rsa_crt_halves(self._h, _dev_ptr(c, B, self.L, "c"), _dev_ptr(out, B, 2 * self._half, "mpq"),
+                                    B, _stream_handle(stream)))
+        return out
+
+    def crt_combine(self, mpq, out=None, stream=None):
+        """Garner recombination of crt_halves output into [B, n_limbs]."""
+        import torch
+        B = mpq.shape[0]
+        if out is None:
+            out = torch.empty((B, self.L), dtype=torch.int32, device=mpq.device)
+        _check(lib().rsa_crt_combine(self._h, _dev_ptr(mpq, B, 2 * self._half, "mpq"), _dev_ptr(out, B, self.L, "m"),
+                                     B, _stream_handle(stream)))
         return out
 
 

@@ -25,8 +25,13 @@ METRIC = "RSA-2048 CRT decrypts/sec on 1 MI355X (batched vs plain), p50/p99 late
 # MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz; v_mad_u64_u32 (32x32->64
 # multiply-add) issues at the full per-lane rate on gfx950.
 PEAK_MUL_PER_S = 256 * 64 * 2.4e9
+# MI355X dense int8 matrix-core peak (v_mfma_i32_16x16x64_i8): 5.0 POP/s.
+PEAK_I8_OPS_PER_S = 5.0e15
+ENGINE_NAMES = {1: "channel", 2: "matrix"}
 KERNEL_SOURCES = ["paper_1305_3699_amd/csrc/kernels_impl.hpp", "paper_1305_3699_amd/csrc/arith.hpp",
-                  "paper_1305_3699_amd/csrc/kernel_configs.inc"]
+                  "paper_1305_3699_amd/csrc/kernel_configs.inc", "paper_1305_3699_amd/csrc/kernels_mfma.hpp",
+                  "paper_1305_3699_amd/csrc/mfma_layout.hpp", "paper_1305_3699_amd/csrc/kernel_configs_mfma.inc"]
+KERNELS = ("modexp_kernel", "modexp_mfma_kernel", "garner_kernel", "montmul_kernel")
 
 
 def kernel_source_hash() -> str:
@@ -57,6 +62,26 @@ def wide_muls_per_mm(k: int) -> int:
     """Algorithmic 32x32->64 products of one RNS Montgomery product: the two
     base extensions (k(k+1) each) and seven per-channel products per channel."""
     return 2 * k * (k + 1) + 7 * k
+
+
+def kernel_shape(info: dict) -> tuple:
+    """Template arguments of the exponentiation kernel that serves info."""
+    if info["engine"] != 2:
+        return (info["k"], info["waves"])
+    import re
+    txt = open(os.path.join(ROOT, "paper_1305_3699_amd/csrc/kernel_configs_mfma.inc")).read()
+    for m in re.finditer(r"RNSRSA_MSHAPE\((\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", txt):
+        if int(m.group(1)) == info["k"]:
+            return tuple(int(v) for v in m.groups())
+    return (info["k"], info["waves"])
+
+
+def i8_macs_per_mm(k: int) -> int:
+    """Algorithmic int8 products of the two base extensions of one RNS
+    Montgomery product on the matrix cores: k(k+1) residue products each
+    (k inputs, k+1 outputs with the redundant channel), 16 byte products per
+    32 x 32-bit residue product."""
+    return 2 * 16 * k * (k + 1)
 
 
 def cpu_threads() -> int:
@@ -106,7 +131,7 @@ def ingest_counters(fetch_csv: str, write_csv: str, calib_mb: int) -> dict:
     for name in f:
         short = name.split("(")[0].replace("void ", "").replace("rnsrsa::", "")
         base = short.split("<")[0]
-        if base not in ("modexp_kernel", "garner_kernel", "montmul_kernel"):
+        if base not in KERNELS:
             continue
         fk = statistics.mean(f[name]) * fetch_scale
         wk = statistics.mean(w.get(name, [0.0])) * write_scale
@@ -128,7 +153,7 @@ def run(args) -> dict:
         raise SystemExit("bench.py needs the GPU")
     torch.cuda.set_device(0)
     key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
-    opts = {"window": args.window}
+    opts = {"window": args.window, "engine": args.engine}
     if args.waves:
         opts.update(k=33, waves=args.waves)
     rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, **opts)
@@ -181,6 +206,27 @@ def run(args) -> dict:
     mean_modexp_s = statistics.mean(modexp_ms) / 1e3
     achieved = muls_per_launch / mean_modexp_s
 
+    kbase = "modexp_mfma_kernel" if info["engine"] == 2 else "modexp_kernel"
+    kname = "%s<%s>" % (kbase, ",".join(map(str, kernel_shape(info))))
+    valu = {
+        "achieved": round(achieved / 1e12, 4),
+        "peak": round(PEAK_MUL_PER_S / 1e12, 4),
+        "unit": "Tmul/s",
+        "frac": round(achieved / PEAK_MUL_PER_S, 4),
+        "work_per_launch": muls_per_launch,
+    }
+    if info["engine"] == 2:
+        ops = 2 * B * mms * i8_macs_per_mm(k)
+        roofline = {"bound": "mfma", "kernel": kname,
+                    "achieved": round(ops / mean_modexp_s / 1e12, 2), "peak": PEAK_I8_OPS_PER_S / 1e12,
+                    "unit": "TOP/s", "frac": round(ops / mean_modexp_s / PEAK_I8_OPS_PER_S, 4),
+                    "traffic": load_traffic(kbase), "work_per_launch": ops, "mm_per_decrypt": mms,
+                    "what": "int8 ops of the two base extensions (2 x 16 k(k+1) MACs per RNS product)",
+                    "wide_mul_equiv": valu}
+    else:
+        roofline = {"bound": "alu", "kernel": kname, **valu, "traffic": load_traffic(kbase),
+                    "mm_per_decrypt": mms,
+                    "what": "32x32->64 products W(k) = 2k(k+1) + 7k per RNS product vs full-rate VALU issue"}
     sq = sorted(step_ms)
     p50 = statistics.median(sq)
     p99 = sq[min(len(sq) - 1, int(round(0.99 * (len(sq) - 1))))]
@@ -206,22 +252,13 @@ def run(args) -> dict:
             "k": k,
             "waves": info["waves"],
             "window": info["window"],
+            "engine": ENGINE_NAMES[info["engine"]],
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "what": "one step (batch of %d)" % B},
         "modexps_per_s": round(2 * value, 1),
         "kernels_ms": {"modexp_crt_halves": round(statistics.mean(modexp_ms), 4),
                        "garner": round(statistics.mean(garner_ms), 4)},
-        "roofline": {
-            "bound": "alu",
-            "kernel": "modexp_kernel<%d,%d>" % (k, info["waves"]),
-            "achieved": round(achieved / 1e12, 4),
-            "peak": round(PEAK_MUL_PER_S / 1e12, 4),
-            "unit": "Tmul/s",
-            "frac": round(achieved / PEAK_MUL_PER_S, 4),
-            "traffic": load_traffic("modexp_kernel"),
-            "work_per_launch": muls_per_launch,
-            "mm_per_decrypt": mms,
-        },
+        "roofline": roofline,
         "cpu_baseline": None,
     }
     if args.cpu_sample > 0:
@@ -253,6 +290,7 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--window", type=int, default=6)
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (k = 33 shapes)")
+    ap.add_argument("--engine", type=int, default=0, help="0 auto, 1 channel (VALU), 2 matrix cores")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="ciphertexts for the oracle baseline (0: skip)")
     ap.add_argument("--sweep-window", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,

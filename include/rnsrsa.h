@@ -54,6 +54,13 @@ enum rns_status {
     RNS_EUNSUPPORTED = -8   /* no kernel is built for the requested shape */
 };
 
+/* Exponentiation engines (the same results; different hardware paths). */
+enum rns_engine {
+    RNS_ENGINE_AUTO = 0,     /* matrix cores when a kernel exists for k, else channel */
+    RNS_ENGINE_CHANNEL = 1,  /* base extensions as 32x32->64 multiply-adds on the vector ALUs */
+    RNS_ENGINE_MATRIX = 2    /* base extensions as int8 matrix products (MFMA), exact int32 sums */
+};
+
 /* Prime ranges for the channel moduli. */
 enum rns_prime_range {
     RNS_PRIMES_HIGH = 0,    /* primes in [2^32 - 2^24, 2^32) */
@@ -73,11 +80,13 @@ enum rns_prime_range {
  *   prime_range rns_prime_range; prime_seed seeds the deterministic draw.
  *   primes      optional explicit bases: n_primes = 2k distinct primes in
  *               (2^31, 2^32), B first then B'.  Overrides k and prime_range.
+ *   engine      rns_engine (0 = auto).  rns_mont_mul_batch and the Garner
+ *               step of CRT decryption always use the channel kernels.
  * Both bases hold k primes; with the redundant channel 2^32 an operand has
  * 2k+1 residues.  A base pair is accepted for modulus N of L limbs when
- *   M >= (k+1)^2 N,  M >= 2^(32L+1),  M' >= (k+1) N,  gcd(N, M) = 1,
- * which keeps every Montgomery product below (k+1) N and makes the second
- * base extension exact.
+ *   M >= (k+2)^2 N,  M >= 2^(32L+1),  M' >= (k+2) N,  gcd(N, M) = 1,
+ * which keeps every Montgomery product below (k+2) N (below (k+1) N on the
+ * channel engine) and makes the second base extension exact.
  */
 typedef struct rns_opts {
     int k;
@@ -87,6 +96,7 @@ typedef struct rns_opts {
     uint64_t prime_seed;
     const uint32_t *primes;
     size_t n_primes;
+    int engine;
 } rns_opts;
 
 typedef struct rns_info {
@@ -95,6 +105,7 @@ typedef struct rns_info {
     int window;         /* exponent window width */
     int mod_limbs;      /* L */
     int mod_bits;       /* bit length of N */
+    int engine;         /* RNS_ENGINE_CHANNEL or RNS_ENGINE_MATRIX */
 } rns_info;
 
 typedef struct rns_ctx rns_ctx;
@@ -104,7 +115,7 @@ typedef struct rsa_key rsa_key;
  * is valid until the next library call on this thread. */
 const char *rns_last_error(void);
 
-/* ABI version of this header (currently 1). */
+/* ABI version of this header (currently 2). */
 int rns_abi_version(void);
 
 /*

@@ -28,12 +28,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           # packed FP32 instructions stay disabled in every HIP compile
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-I", INC, "-I", CSRC]
-HOST_SOURCES = ["capi.cpp", "plan.cpp", "emul.cpp", "kernels_dispatch.cpp"]
+HOST_SOURCES = ["capi.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp", "emul_mfma.cpp", "kernels_dispatch.cpp"]
 
 
 def shapes() -> list:
     txt = open(os.path.join(CSRC, "kernel_configs.inc")).read()
     return [(int(k), int(w)) for k, w in re.findall(r"RNSRSA_SHAPE\((\d+),\s*(\d+)\)", txt)]
+
+
+def mfma_shapes() -> list:
+    txt = open(os.path.join(CSRC, "kernel_configs_mfma.inc")).read()
+    return [tuple(int(v) for v in m) for m in
+            re.findall(r"RNSRSA_MSHAPE\((\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", txt)]
 
 
 def _shape_source(k: int, w: int) -> str:
@@ -68,6 +74,15 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             with open(src, "w") as f:
                 f.write(text)
         units.append((src, os.path.join(BUILD, "shape_%d_%d.o" % (k, w))))
+    for k, w, mt, nt in mfma_shapes():
+        src = os.path.join(BUILD, "mshape_%d_%d_%d_%d.hip" % (k, w, mt, nt))
+        text = ('#include "kernels_mfma.hpp"\nnamespace rnsrsa {\n'
+                "template hipError_t launch_modexp_mfma_t<%d, %d, %d, %d>(const ModexpMfmaLaunch &, hipStream_t);\n"
+                "}\n" % (k, w, mt, nt))
+        if not os.path.exists(src) or open(src).read() != text:
+            with open(src, "w") as f:
+                f.write(text)
+        units.append((src, os.path.join(BUILD, "mshape_%d_%d_%d_%d.o" % (k, w, mt, nt))))
     for name in HOST_SOURCES:
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name.replace(".cpp", ".o"))))
     # longest compiles first

@@ -142,6 +142,20 @@ inline uint32_t powmod32(uint32_t a, uint64_t e, uint32_t m) {
     return (uint32_t)r;
 }
 
+// prod(ms) mod m
+inline uint32_t prod_mod32(const std::vector<uint32_t> &ms, uint32_t m) {
+    uint64_t r = 1 % m;
+    for (uint32_t x : ms) r = r * (x % m) % m;
+    return (uint32_t)r;
+}
+
+inline uint32_t pow2_32_mod(uint32_t m) { return (uint32_t)(((uint64_t)1 << 32) % m); }
+
+inline uint32_t pow2_64_mod(uint32_t m) {
+    uint64_t r = ((uint64_t)1 << 32) % m;
+    return (uint32_t)(r * r % m);
+}
+
 // a^-1 mod m by the extended Euclidean algorithm; 0 when gcd(a, m) != 1.
 inline uint32_t invmod32(uint32_t a, uint32_t m) {
     int64_t t = 0, nt = 1, r = m, nr = a % m;

@@ -12,6 +12,7 @@
 #include "emul.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "plan_mfma.hpp"
 #include "rnsrsa.h"
 #include "rnsrsa_host.h"
 
@@ -46,6 +47,7 @@ PlanOptions plan_options(const rns_opts *o) {
     if (o->prime_seed) p.seed = o->prime_seed;
     p.primes = o->primes;
     p.n_primes = o->n_primes;
+    p.engine = o->engine;
     return p;
 }
 
@@ -65,6 +67,28 @@ int upload(const std::vector<uint32_t> &v, uint32_t **out) {
         *out = nullptr;
         return hip_fail(e, "hipMemcpy");
     }
+    return RNS_OK;
+}
+
+// Device copies of the matrix-core base tables, per (base set, device).
+std::map<std::pair<const BaseSet *, int>, std::pair<std::shared_ptr<const BaseSet>, uint32_t *>> g_dev_mbases;
+
+int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const std::vector<uint32_t> &blob, uint32_t **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto key = std::make_pair(bs.get(), dev);
+    auto it = g_dev_mbases.find(key);
+    if (it != g_dev_mbases.end()) {
+        *out = it->second.second;
+        return RNS_OK;
+    }
+    uint32_t *d = nullptr;
+    int rc = upload(blob, &d);
+    if (rc) return rc;
+    g_dev_mbases[key] = std::make_pair(bs, d);
+    *out = d;
     return RNS_OK;
 }
 
@@ -128,18 +152,26 @@ struct rns_ctx {
     ModPlan plan;
     int window = 5;
     int device = 0;
+    int engine = RNS_ENGINE_CHANNEL;
     uint32_t *d_base = nullptr;  // shared, owned by the process-wide cache
     uint32_t *d_mod = nullptr;
     uint32_t *d_entry = nullptr;  // entry table for L-limb inputs (factor M^2 mod N)
+    // matrix-core engine
+    MfmaShape mshape{};
+    uint32_t *d_mbase = nullptr;  // shared, owned by the process-wide cache
+    uint32_t *d_mkey = nullptr;
+    uint32_t *d_mentry = nullptr;
     ~rns_ctx() {
-        if (d_mod) hipFree(d_mod);
-        if (d_entry) hipFree(d_entry);
+        for (uint32_t *x : {d_mod, d_entry, d_mkey, d_mentry})
+            if (x) hipFree(x);
     }
 };
 
 struct rns_plan {
     ModPlan plan;
     int window = 5;
+    int engine = RNS_ENGINE_CHANNEL;
+    MfmaTables mt;
 };
 
 struct rsa_key {
@@ -150,31 +182,59 @@ struct rsa_key {
     rns_ctx *p = nullptr, *q = nullptr;
     uint32_t *d_dp = nullptr, *d_dq = nullptr;
     uint32_t *d_centry_p = nullptr, *d_centry_q = nullptr;  // entry tables for n_limbs-limb inputs
+    uint32_t *d_mcentry_p = nullptr, *d_mcentry_q = nullptr;  // the same for the matrix-core engine
     uint32_t *d_gentry = nullptr;                           // Garner entry table (p-modulus)
     uint32_t *d_qlimbs = nullptr;
     ~rsa_key() {
         delete n;
         delete p;
         delete q;
-        for (uint32_t *x : {d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_gentry, d_qlimbs})
+        for (uint32_t *x : {d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_mcentry_p, d_mcentry_q, d_gentry, d_qlimbs})
             if (x) hipFree(x);
     }
 };
 
 namespace {
 
-int ctx_from_plan(ModPlan &&mp, int window, rns_ctx **out) {
+// Engine for a plan: the matrix-core kernel when one exists for k (unless the
+// channel engine was asked for).
+int choose_engine(int K, int requested, int *engine) {
+    if (requested < 0 || requested > RNS_ENGINE_MATRIX) return fail(RNS_EINVAL, "bad engine");
+    if (requested == RNS_ENGINE_CHANNEL) {
+        *engine = RNS_ENGINE_CHANNEL;
+        return RNS_OK;
+    }
+    MfmaShape sh;
+    if (mfma_shape_for(K, sh)) {
+        *engine = RNS_ENGINE_MATRIX;
+        return RNS_OK;
+    }
+    if (requested == RNS_ENGINE_MATRIX) return fail(RNS_EUNSUPPORTED, "no matrix-core kernel for this k");
+    *engine = RNS_ENGINE_CHANNEL;
+    return RNS_OK;
+}
+
+int ctx_from_plan(ModPlan &&mp, int window, int engine_req, rns_ctx **out) {
     std::unique_ptr<rns_ctx> c(new (std::nothrow) rns_ctx);
     if (!c) return fail(RNS_ENOMEM, "out of host memory");
     c->plan = std::move(mp);
     c->window = window;
+    int rc = choose_engine(c->plan.base->K, engine_req, &c->engine);
+    if (rc) return rc;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    int rc = device_base(c->plan.base, &c->d_base);
-    if (rc) return rc;
+    if ((rc = device_base(c->plan.base, &c->d_base))) return rc;
     if ((rc = upload(c->plan.blob, &c->d_mod))) return rc;
     std::vector<uint32_t> E = make_entry_table(c->plan, {c->plan.R2}, c->plan.L);
     if ((rc = upload(E, &c->d_entry))) return rc;
+    if (c->engine == RNS_ENGINE_MATRIX) {
+        mfma_shape_for(c->plan.base->K, c->mshape);
+        MfmaTables t = make_mfma_tables(c->plan, c->mshape);
+        if ((rc = device_mfma_base(c->plan.base, t.base, &c->d_mbase))) return rc;
+        if ((rc = upload(t.key, &c->d_mkey))) return rc;
+        std::vector<uint32_t> Em = make_mfma_entry_table(c->plan, c->mshape, {c->plan.R2}, c->plan.L);
+        if ((rc = upload(Em, &c->d_mentry))) return rc;
+    }
     *out = c.release();
     return RNS_OK;
 }
@@ -193,6 +253,37 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
                uint32_t *out1, int out_stride, size_t batch, hipStream_t s) {
     const BaseSet &bs = *c0->plan.base;
     const int njobs = c1 ? 2 : 1;
+    ModexpParams P{};
+    P.in_limbs = in_limbs;
+    P.in_stride = in_limbs;
+    P.L = c0->plan.L;
+    P.out_stride = out_stride;
+    P.exp_limbs = exp_limbs;
+    P.exp_stride = exp_stride;
+    P.window = c0->window;
+    P.batch = (int)batch;
+    if (c0->engine == RNS_ENGINE_MATRIX) {
+        Scratch table;
+        int rc = scratch_alloc(table, modexp_mfma_table_words(bs.K, c0->window, batch, njobs) * sizeof(uint32_t), s);
+        if (rc) return rc;
+        ModexpMfmaLaunch a{};
+        a.mb = c0->d_mbase;
+        a.mk[0] = c0->d_mkey;
+        a.mk[1] = c1 ? c1->d_mkey : c0->d_mkey;
+        a.E[0] = E0;
+        a.E[1] = E1 ? E1 : E0;
+        a.exp[0] = x0;
+        a.exp[1] = x1 ? x1 : x0;
+        a.in = in;
+        a.out[0] = out0;
+        a.out[1] = out1 ? out1 : out0;
+        a.table = (uint32_t *)table.p;
+        a.P = P;
+        a.njobs = njobs;
+        hipError_t e = launch_modexp_mfma(bs.K, a, s);
+        if (e != hipSuccess) return hip_fail(e, "modexp (matrix cores) launch");
+        return RNS_OK;
+    }
     const size_t wgs = (batch + 63) / 64 * njobs;
     Scratch table;
     int rc = scratch_alloc(table, modexp_table_words(bs.K, bs.W, c0->window, wgs) * sizeof(uint32_t), s);
@@ -225,11 +316,14 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
 
 Limbs limbs_of(const uint32_t *p, size_t n) { return bn_from_ptr(p, n); }
 
+const uint32_t *entry_of(const rns_ctx *c) { return c->engine == RNS_ENGINE_MATRIX ? c->d_mentry : c->d_entry; }
+
 // Both half-size exponentiations of a CRT decryption in one launch.
 int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s) {
     const int L = (int)key->half;
-    return run_modexp(key->p, key->q, key->d_centry_p, key->d_centry_q, c, (int)key->n_limbs, key->d_dp, key->d_dq,
-                      L, 0, mpq, mpq + L, 2 * L, batch, s);
+    const bool m = key->p->engine == RNS_ENGINE_MATRIX;
+    return run_modexp(key->p, key->q, m ? key->d_mcentry_p : key->d_centry_p, m ? key->d_mcentry_q : key->d_centry_q,
+                      c, (int)key->n_limbs, key->d_dp, key->d_dq, L, 0, mpq, mpq + L, 2 * L, batch, s);
 }
 
 // Garner recombination over the p-modulus tables.
@@ -257,7 +351,7 @@ extern "C" {
 
 const char *rns_last_error(void) { return g_err.c_str(); }
 
-int rns_abi_version(void) { return 1; }
+int rns_abi_version(void) { return 2; }
 
 int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out) {
     if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");
@@ -269,7 +363,7 @@ int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_c
         std::string err;
         rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), mp, err);
         if (rc) return fail(rc, err);
-        rc = ctx_from_plan(std::move(mp), window_or_default(opts), out);
+        rc = ctx_from_plan(std::move(mp), window_or_default(opts), opts ? opts->engine : 0, out);
         if (rc) return rc;
     } catch (const std::bad_alloc &) {
         return fail(RNS_ENOMEM, "out of host memory");
@@ -288,6 +382,8 @@ int rns_get_info(const rns_ctx *ctx, rns_info *info) {
     info->window = ctx->window;
     info->mod_limbs = ctx->plan.L;
     info->mod_bits = (int)bn_bits(ctx->plan.N);
+    info->engine = ctx->engine;
+    if (ctx->engine == RNS_ENGINE_MATRIX) info->waves = ctx->mshape.W;
     return ok();
 }
 
@@ -312,8 +408,8 @@ int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, si
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != ctx->device) return fail(RNS_EINVAL, "context belongs to another device");
-    int rc = run_modexp(ctx, nullptr, ctx->d_entry, nullptr, base, ctx->plan.L, exp, nullptr, (int)exp_limbs,
-                        (int)exp_stride, out, nullptr, ctx->plan.L, batch, (hipStream_t)hip_stream);
+    int rc = run_modexp(ctx, nullptr, entry_of(ctx), nullptr, base, ctx->plan.L, exp, nullptr, (int)exp_limbs, (int)exp_stride,
+                        out, nullptr, ctx->plan.L, batch, (hipStream_t)hip_stream);
     return rc ? rc : ok();
 }
 
@@ -349,6 +445,7 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
         key->e_limbs = e_limbs;
         key->half = half_limbs;
         const int window = window_or_default(opts);
+        const int engine = opts ? opts->engine : 0;
         std::string err;
         {
             ModPlan mp;
@@ -361,7 +458,7 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
                 rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, po, mp, err);
             }
             if (rc) return fail(rc, err);
-            if ((rc = ctx_from_plan(std::move(mp), window, &key->n))) return rc;
+            if ((rc = ctx_from_plan(std::move(mp), window, engine, &key->n))) return rc;
         }
         if ((rc = upload(std::vector<uint32_t>(e, e + e_limbs), &key->d_e))) return rc;
         if (d && (rc = upload(std::vector<uint32_t>(d, d + n_limbs), &key->d_d))) return rc;
@@ -389,10 +486,23 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
             Limbs A = bn_mod(bn_mul(limbs_of(qinv, half_limbs), pp.Mmod), P);
             Limbs Bv = bn_is_zero(A) ? Limbs{} : bn_sub(P, A);
             std::vector<uint32_t> Eg = make_entry_table(pp, {A, Bv}, L);
-            if ((rc = ctx_from_plan(std::move(pp), window, &key->p))) return rc;
-            if ((rc = ctx_from_plan(std::move(qp), window, &key->q))) return rc;
+            std::vector<uint32_t> Epm, Eqm;
+            MfmaShape msh;
+            const bool mfma = mfma_shape_for(bs->K, msh);
+            if (mfma) {
+                Epm = make_mfma_entry_table(pp, msh, Yp, L);
+                Eqm = make_mfma_entry_table(qp, msh, Yq, L);
+                Epm.resize((size_t)n_limbs * msh.ecols());
+                Eqm.resize((size_t)n_limbs * msh.ecols());
+            }
+            if ((rc = ctx_from_plan(std::move(pp), window, engine, &key->p))) return rc;
+            if ((rc = ctx_from_plan(std::move(qp), window, engine, &key->q))) return rc;
             if ((rc = upload(Ep, &key->d_centry_p))) return rc;
             if ((rc = upload(Eq, &key->d_centry_q))) return rc;
+            if (key->p->engine == RNS_ENGINE_MATRIX) {
+                if ((rc = upload(Epm, &key->d_mcentry_p))) return rc;
+                if ((rc = upload(Eqm, &key->d_mcentry_q))) return rc;
+            }
             if ((rc = upload(Eg, &key->d_gentry))) return rc;
             if ((rc = upload(std::vector<uint32_t>(dp, dp + half_limbs), &key->d_dp))) return rc;
             if ((rc = upload(std::vector<uint32_t>(dq, dq + half_limbs), &key->d_dq))) return rc;
@@ -423,7 +533,7 @@ int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch
     if (!m || !c) return fail(RNS_EINVAL, "null buffer");
     if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
     const rns_ctx *x = key->n;
-    int rc = run_modexp(x, nullptr, x->d_entry, nullptr, m, x->plan.L, key->d_e, nullptr, (int)key->e_limbs, 0, c,
+    int rc = run_modexp(x, nullptr, entry_of(x), nullptr, m, x->plan.L, key->d_e, nullptr, (int)key->e_limbs, 0, c,
                         nullptr, x->plan.L, batch, (hipStream_t)hip_stream);
     return rc ? rc : ok();
 }
@@ -437,7 +547,7 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
     if (!use_crt) {
         if (!key->d_d) return fail(RNS_EINVAL, "key has no private exponent");
         const rns_ctx *x = key->n;
-        int rc = run_modexp(x, nullptr, x->d_entry, nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
+        int rc = run_modexp(x, nullptr, entry_of(x), nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
                             nullptr, x->plan.L, batch, s);
         return rc ? rc : ok();
     }
@@ -483,6 +593,12 @@ int rns_plan_create(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts,
         rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), p->plan, err);
         if (rc) return fail(rc, err);
         p->window = window_or_default(opts);
+        if ((rc = choose_engine(p->plan.base->K, opts ? opts->engine : 0, &p->engine))) return rc;
+        if (p->engine == RNS_ENGINE_MATRIX) {
+            MfmaShape sh;
+            mfma_shape_for(p->plan.base->K, sh);
+            p->mt = make_mfma_tables(p->plan, sh);
+        }
         *out = p.release();
     } catch (const std::bad_alloc &) {
         return fail(RNS_ENOMEM, "out of host memory");
@@ -499,6 +615,8 @@ int rns_plan_info(const rns_plan *plan, rns_info *info) {
     info->window = plan->window;
     info->mod_limbs = plan->plan.L;
     info->mod_bits = (int)bn_bits(plan->plan.N);
+    info->engine = plan->engine;
+    if (plan->engine == RNS_ENGINE_MATRIX) info->waves = plan->mt.shape.W;
     return ok();
 }
 
@@ -517,6 +635,12 @@ int rns_emul_modexp(const rns_plan *plan, const uint32_t *base, const uint32_t *
     if (batch == 0) return ok();
     if (!base || !exp || !out || exp_limbs == 0) return fail(RNS_EINVAL, "null buffer or zero exponent limbs");
     if (exp_stride != 0 && exp_stride < exp_limbs) return fail(RNS_EINVAL, "exp_stride below exp_limbs");
+    if (plan->engine == RNS_ENGINE_MATRIX) {
+        std::vector<uint32_t> E = make_mfma_entry_table(plan->plan, plan->mt.shape, {plan->plan.R2}, plan->plan.L);
+        emul_modexp_mfma(plan->plan, plan->mt, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride, plan->window,
+                         out, batch);
+        return ok();
+    }
     std::vector<uint32_t> E = make_entry_table(plan->plan, {plan->plan.R2}, plan->plan.L);
     emul_modexp(plan->plan, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride, plan->window, out, batch);
     return ok();

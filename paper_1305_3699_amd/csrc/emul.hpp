@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "plan_mfma.hpp"
 
 namespace rnsrsa {
 
@@ -14,6 +15,11 @@ namespace rnsrsa {
 void emul_modexp(const ModPlan &mp, const std::vector<uint32_t> &E, int in_limbs, const uint32_t *base,
                  const uint32_t *exp, int exp_limbs, size_t exp_stride, int window, uint32_t *out,
                  size_t batch);
+
+// Host model of the matrix-core kernel (emul_mfma.cpp), same contract.
+void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
+                      const uint32_t *base, const uint32_t *exp, int exp_limbs, size_t exp_stride, int window,
+                      uint32_t *out, size_t batch);
 
 void emul_mont_mul(const ModPlan &mp, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch);
 

@@ -1,0 +1,301 @@
+// Host model of the matrix-core exponentiation kernel (kernels_mfma.hpp).
+//
+// It runs the kernel's steps on the same tables, element by element.  Each
+// base-extension constant is rebuilt from the A-tile bytes through the
+// hardware operand layout of v_mfma_i32_16x16x64_i8 (lane l holds row l%16
+// and K indices 16*(l/16) + byte), independently of how the tables were
+// packed, so a packing mistake shows up here before any GPU run.
+#include <algorithm>
+
+#include "emul.hpp"
+#include "plan_mfma.hpp"
+
+namespace rnsrsa {
+
+namespace {
+
+struct MCtx {
+    const MfmaTables &T;
+    const MLayout ly;
+    int K;
+    std::vector<int64_t> V1, V2;  // [W][4MT][64*KSTEPS] extension constants
+
+    MCtx(const MfmaTables &t) : T(t), ly(t.shape), K(t.shape.K) {
+        const int SW = 4 * ly.MT, KK = 64 * ly.KSTEPS();
+        V1.assign((size_t)ly.W * SW * KK, 0);
+        V2.assign((size_t)ly.W * SW * KK, 0);
+        for (int w = 0; w < ly.W; w++)
+            for (int s = 0; s < SW; s++)
+                for (int kap = 0; kap < KK; kap++) {
+                    V1[((size_t)w * SW + s) * KK + kap] = tile_value(T.key.data() + ly.a1(), w, s, kap);
+                    V2[((size_t)w * SW + s) * KK + kap] = tile_value(T.base.data() + ly.a2(), w, s, kap);
+                }
+    }
+    int64_t tile_value(const uint32_t *tiles, int w, int s, int kap) const {
+        const int mt = s / 4, g = s % 4, ks = kap / 64, k = kap % 64, lg = k / 16, j = k % 16;
+        int64_t v = 0;
+        for (int b = 0; b < 4; b++) {
+            const int lane = 16 * lg + 4 * g + b;  // A row 4g+b lives in lane (row + 16*lg)
+            const uint32_t word = tiles[((((size_t)w * ly.MT + mt) * ly.KSTEPS() + ks) * 64 + lane) * 4 + j / 4];
+            v += (int64_t)(int8_t)(word >> (8 * (j % 4))) * ((int64_t)1 << (8 * b));
+        }
+        return v;
+    }
+    // per-lane constant of slot s in wave w: any lane of group s%4
+    uint32_t slot(size_t off, size_t fields, int field, int w, int s) const {
+        return T.base[off + (((size_t)w * ly.MT + s / 4) * fields + field) * 64 + 16 * (s % 4)];
+    }
+    uint32_t kslot(size_t off, size_t fields, int field, int w, int s) const {
+        return T.key[off + (((size_t)w * ly.MT + s / 4) * fields + field) * 64 + 16 * (s % 4)];
+    }
+    int channel(int w, int s) const { return mfma_slot_channel(ly, w, s / 4, s % 4); }
+    bool real(int w, int s) const {
+        const int c = channel(w, s);
+        return c >= 0 && c < K;
+    }
+};
+
+struct MSt {
+    std::vector<uint32_t> b, p;  // [W][4MT][NM]
+    std::vector<uint32_t> r;     // [NM]
+};
+
+uint32_t pack_digits(uint32_t v, uint32_t m) {
+    const uint32_t c = v >= kDigitSplit ? v - m : v;
+    return (c + 0x80808080u) ^ 0x80808080u;
+}
+
+uint32_t reduce_signed(int64_t S, uint32_t m, uint32_t u) {
+    const uint64_t x = (uint64_t)(S + ((int64_t)m << 16));
+    return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
+}
+
+// sum over K indices of V * digit, digits from the packed rows of element e
+int64_t extension(const std::vector<int64_t> &V, size_t vrow, const std::vector<uint32_t> &dig, int e, int KK, int BROW) {
+    int64_t s = 0;
+    for (int kap = 0; kap < KK; kap++) {
+        const uint32_t word = dig[(size_t)e * BROW + kap / 4];
+        s += V[vrow + kap] * (int64_t)(int8_t)(word >> (8 * (kap % 4)));
+    }
+    return s;
+}
+
+// One product x <- x*y*M^-1 for the NM elements of one workgroup; fills dig2
+// (xi' digits) and returns nothing; with full == false skips the second extension.
+void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::vector<uint32_t> &dig2, bool full) {
+    const MLayout &ly = c.ly;
+    const int SW = 4 * ly.MT, NM = ly.NM(), KK = 64 * ly.KSTEPS(), BROW = ly.BROW(), K = c.K;
+    const uint32_t Mpinv_r = c.T.base[ly.bscal()], Minv_r = c.T.base[ly.bscal() + 1], N_r = c.T.key[ly.kscal()];
+    auto idx = [&](int w, int s, int e) { return ((size_t)w * SW + s) * NM + e; };
+    std::vector<uint32_t> a1(x.p.size());
+    for (int w = 0; w < ly.W; w++)
+        for (int s = 0; s < SW; s++) {
+            const uint32_t m = c.slot(ly.slotB(), 3, 0, w, s), u = c.slot(ly.slotB(), 3, 1, w, s);
+            const uint32_t ci = c.kslot(ly.slotC(), 1, 0, w, s);
+            const uint32_t mp = c.slot(ly.slotP(), 4, 0, w, s), up = c.slot(ly.slotP(), 4, 1, w, s);
+            for (int e = 0; e < NM; e++) {
+                const uint32_t t = mulredc(x.b[idx(w, s, e)], y.b[idx(w, s, e)], m, u);
+                const uint32_t xi = mulredc(t, ci, m, u);
+                if (c.real(w, s)) dig1[(size_t)e * BROW + c.channel(w, s)] = pack_digits(xi, m);
+                a1[idx(w, s, e)] = mulredc(x.p[idx(w, s, e)], y.p[idx(w, s, e)], mp, up);
+            }
+        }
+    std::vector<uint32_t> rr(NM);
+    for (int e = 0; e < NM; e++) {
+        // every wave carries the same redundant row; take wave 0's
+        const int64_t S = extension(c.V1, ((size_t)0 * SW + SW - 1) * KK, dig1, e, KK, BROW);
+        rr[e] = (x.r[e] * y.r[e] + (uint32_t)S * N_r) * Minv_r;
+    }
+    for (int w = 0; w < ly.W; w++)
+        for (int s = 0; s < SW; s++) {
+            const uint32_t m = c.slot(ly.slotP(), 4, 0, w, s), u = c.slot(ly.slotP(), 4, 1, w, s);
+            const uint32_t H = c.slot(ly.slotP(), 4, 2, w, s);
+            for (int e = 0; e < NM; e++) {
+                const int64_t S = extension(c.V1, ((size_t)w * SW + s) * KK, dig1, e, KK, BROW);
+                const uint32_t q = reduce_signed(S, m, u);
+                const uint64_t sum = (uint64_t)a1[idx(w, s, e)] + q;
+                const uint32_t r = (uint32_t)(sum >= m ? sum - m : sum);
+                x.p[idx(w, s, e)] = r;
+                if (c.real(w, s)) dig2[(size_t)e * BROW + c.channel(w, s)] = pack_digits(mulredc(r, H, m, u), m);
+            }
+        }
+    for (int e = 0; e < NM; e++) x.r[e] = rr[e];
+    (void)K;
+    if (!full) return;
+    for (int w = 0; w < ly.W; w++) {
+        std::vector<uint32_t> alpha(NM);
+        for (int e = 0; e < NM; e++) {
+            const int64_t S = extension(c.V2, ((size_t)w * SW + SW - 1) * KK, dig2, e, KK, BROW);
+            alpha[e] = ((uint32_t)S - rr[e]) * Mpinv_r;
+        }
+        for (int s = 0; s < SW; s++) {
+            const uint32_t m = c.slot(ly.slotB(), 3, 0, w, s), u = c.slot(ly.slotB(), 3, 1, w, s);
+            const uint32_t nu = c.slot(ly.slotB(), 3, 2, w, s);
+            for (int e = 0; e < NM; e++) {
+                const int64_t S = extension(c.V2, ((size_t)w * SW + s) * KK, dig2, e, KK, BROW);
+                x.b[idx(w, s, e)] = reduce_signed(S + (int64_t)((uint64_t)alpha[e] * nu), m, u);
+            }
+        }
+    }
+}
+
+uint32_t digit_of(const uint32_t *e, int nlimbs, int nd, int w, int di) {
+    const int lo = (nd - 1 - di) * w;
+    const int limb = lo >> 5, sh = lo & 31;
+    uint64_t v = e[limb];
+    if (limb + 1 < nlimbs) v |= (uint64_t)e[limb + 1] << 32;
+    return (uint32_t)(v >> sh) & ((1u << w) - 1u);
+}
+
+}  // namespace
+
+void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
+                      const uint32_t *base, const uint32_t *exp, int exp_limbs, size_t exp_stride, int window,
+                      uint32_t *out, size_t batch) {
+    const MCtx c(T);
+    const MLayout &ly = c.ly;
+    const int K = c.K, SW = 4 * ly.MT, NM = ly.NM(), BROW = ly.BROW(), L = mp.L;
+    const int w = window, TT = 1 << w;
+    const int nd = (32 * exp_limbs + w - 1) / w;
+    const size_t ecols = ly.ecols();
+    auto idx = [&](int wv, int s, int e) { return ((size_t)wv * SW + s) * NM + e; };
+    for (size_t g0 = 0; g0 < batch; g0 += NM) {
+        std::vector<uint32_t> dig1((size_t)NM * BROW, 0), dig2((size_t)NM * BROW, 0);
+        for (int e = 0; e < NM; e++) {
+            dig1[(size_t)e * BROW + K] = 1;
+            dig2[(size_t)e * BROW + K] = 1;
+        }
+        MSt a, unit, one;
+        for (MSt *st : {&a, &unit, &one}) {
+            st->b.assign((size_t)ly.W * SW * NM, 0);
+            st->p.assign((size_t)ly.W * SW * NM, 0);
+            st->r.assign(NM, 0);
+        }
+        for (int wv = 0; wv < ly.W; wv++)
+            for (int s = 0; s < SW; s++) {
+                const uint32_t m = c.slot(ly.slotB(), 3, 0, wv, s), u = c.slot(ly.slotB(), 3, 1, wv, s);
+                const uint32_t mpp = c.slot(ly.slotP(), 4, 0, wv, s), up = c.slot(ly.slotP(), 4, 1, wv, s);
+                const uint32_t kap = c.slot(ly.slotP(), 4, 3, wv, s);
+                const size_t colB = (size_t)wv * SW + s, colP = (size_t)ly.W * SW + wv * SW + s;
+                for (int e = 0; e < NM; e++) {
+                    const size_t el = g0 + e;
+                    Acc sb, sp;
+                    for (int l = 0; l < in_limbs; l++) {
+                        const uint32_t v = el < batch ? base[el * in_limbs + l] : 0u;
+                        acc_mac(sb, v, E[(size_t)l * ecols + colB]);
+                        acc_mac(sp, v, E[(size_t)l * ecols + colP]);
+                    }
+                    a.b[idx(wv, s, e)] = acc_redc(sb, m, u);
+                    a.p[idx(wv, s, e)] = acc_redc(sp, mpp, up);
+                    unit.b[idx(wv, s, e)] = 0u - m;
+                    unit.p[idx(wv, s, e)] = kap;
+                    one.b[idx(wv, s, e)] = c.kslot(ly.one(), 2, 0, wv, s);
+                    one.p[idx(wv, s, e)] = c.kslot(ly.one(), 2, 1, wv, s);
+                }
+            }
+        for (int e = 0; e < NM; e++) {
+            const size_t el = g0 + e;
+            uint32_t z = 0;
+            for (int l = 0; l < in_limbs; l++) z += (el < batch ? base[el * in_limbs + l] : 0u) * E[(size_t)l * ecols + ecols - 1];
+            a.r[e] = z;
+            unit.r[e] = 1;
+            one.r[e] = T.key[ly.one() + (size_t)ly.W * ly.MT * 2 * 64];
+        }
+        mm(c, a, unit, dig1, dig2, true);
+        std::vector<MSt> tbl(TT);
+        tbl[0] = one;
+        tbl[1] = a;
+        for (int j = 2; j < TT; j++) {
+            mm(c, a, tbl[1], dig1, dig2, true);
+            tbl[j] = a;
+        }
+        int di = 0;
+        if (exp_stride == 0) {
+            while (di < nd && digit_of(exp, exp_limbs, nd, w, di) == 0) di++;
+            if (di < nd) {
+                a = tbl[digit_of(exp, exp_limbs, nd, w, di)];
+                di++;
+            } else {
+                a = one;
+            }
+        } else {
+            a = one;
+        }
+        for (; di < nd; di++) {
+            for (int s = 0; s < w; s++) {
+                MSt sq = a;
+                mm(c, a, sq, dig1, dig2, true);
+            }
+            if (exp_stride == 0) {
+                const uint32_t d = digit_of(exp, exp_limbs, nd, w, di);
+                if (d) mm(c, a, tbl[d], dig1, dig2, true);
+            } else {
+                MSt y = one;
+                for (int e = 0; e < NM; e++) {
+                    const size_t el = std::min(g0 + e, batch - 1);
+                    const uint32_t d = digit_of(exp + el * exp_stride, exp_limbs, nd, w, di);
+                    for (size_t q = 0; q < y.b.size(); q++)
+                        if ((int)(q % NM) == e) {
+                            y.b[q] = tbl[d].b[q];
+                            y.p[q] = tbl[d].p[q];
+                        }
+                    y.r[e] = tbl[d].r[e];
+                }
+                mm(c, a, y, dig1, dig2, true);
+            }
+        }
+        mm(c, a, unit, dig1, dig2, false);
+        // leave the RNS, element by element
+        for (int e = 0; e < NM && g0 + e < batch; e++) {
+            std::vector<uint32_t> X(K), acc(L + 1), tmp(L + 1);
+            uint32_t s2 = 0;
+            for (int j = 0; j < K; j++) {
+                uint32_t v = (dig2[(size_t)e * BROW + j] ^ 0x80808080u) - 0x80808080u;
+                const uint32_t mj = T.base[ly.mpj() + j];
+                v = v >= kDigitSplit ? v + mj : v;     // centred range reaches below -2^31
+                X[j] = v;
+                s2 += v * T.base[ly.mplo() + j];
+            }
+            const uint32_t alpha = (s2 - a.r[e]) * T.base[ly.bscal()];
+            uint64_t cy = 0;
+            for (int l = 0; l <= L; l++) {
+                Acc sum;
+                sum.lo = cy;
+                for (int j = 0; j < K; j++) acc_mac(sum, X[j], T.base[ly.MpL() + (size_t)j * (K + 1) + l]);
+                uint64_t lo;
+                uint32_t top;
+                acc_value(sum, lo, top);
+                acc[l] = (uint32_t)lo;
+                cy = (lo >> 32) | ((uint64_t)top << 32);
+            }
+            uint64_t carry = 0;
+            uint32_t borrow = 0;
+            for (int l = 0; l <= L; l++) {
+                const uint64_t p = (uint64_t)alpha * T.base[ly.MpF() + l] + carry;
+                carry = p >> 32;
+                const uint32_t v = acc[l], pl = (uint32_t)p;
+                const uint32_t d = v - pl, d2 = d - borrow;
+                borrow = (v < pl) | (d < borrow);
+                acc[l] = d2;
+            }
+            int qb = 0;
+            while ((1 << qb) <= K + 1) qb++;
+            for (int b = qb - 1; b >= 0; b--) {
+                uint32_t br = 0;
+                for (int l = 0; l <= L; l++) {
+                    const uint32_t nlo = l < L ? T.key[ly.Nl() + l] : 0u;
+                    const uint32_t nhi = (b && l > 0) ? (T.key[ly.Nl() + l - 1] >> (32 - b)) : 0u;
+                    const uint32_t nl = (nlo << b) | nhi;
+                    const uint32_t v = acc[l];
+                    const uint32_t d = v - nl, d2 = d - br;
+                    br = (v < nl) | (d < br);
+                    tmp[l] = d2;
+                }
+                if (!br) acc = tmp;
+            }
+            std::copy(acc.begin(), acc.begin() + L, out + (g0 + e) * (size_t)L);
+        }
+    }
+}
+
+}  // namespace rnsrsa

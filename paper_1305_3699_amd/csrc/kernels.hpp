@@ -59,7 +59,24 @@ struct MontMulLaunch {
     int batch;
 };
 
+// Matrix-core variant of ModexpLaunch: mb is the key-independent table, mk[j]
+// the per-modulus table of job j (plan_mfma.hpp), E[j] its entry table.
+struct ModexpMfmaLaunch {
+    const uint32_t *mb;
+    const uint32_t *mk[2];
+    const uint32_t *E[2];
+    const uint32_t *exp[2];
+    const uint32_t *in;
+    uint32_t *out[2];
+    uint32_t *table;  // scratch, modexp_mfma_table_words(...) words
+    ModexpParams P;
+    int njobs;
+};
+
 size_t modexp_table_words(int K, int W, int window, size_t workgroups);
+size_t modexp_mfma_table_words(int K, int window, size_t elements, int njobs);
+bool mfma_supported(int K);
+hipError_t launch_modexp_mfma(int K, const ModexpMfmaLaunch &a, hipStream_t s);
 hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s);
 hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s);
 hipError_t launch_montmul(int K, int W, const MontMulLaunch &a, hipStream_t s);

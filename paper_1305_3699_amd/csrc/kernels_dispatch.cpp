@@ -1,6 +1,7 @@
 // Dispatch from a runtime (K, W) shape to the kernel instantiations, which
 // are compiled one shape per translation unit (see the build script).
 #include "kernels.hpp"
+#include "mfma_layout.hpp"
 
 namespace rnsrsa {
 
@@ -17,6 +18,41 @@ hipError_t launch_montmul_t(const MontMulLaunch &a, hipStream_t s);
     extern template hipError_t launch_montmul_t<k, w>(const MontMulLaunch &, hipStream_t);
 #include "kernel_configs.inc"
 #undef RNSRSA_SHAPE
+
+template <int K, int W, int MT, int NT>
+hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s);
+#define RNSRSA_MSHAPE(k, w, mt, nt) \
+    extern template hipError_t launch_modexp_mfma_t<k, w, mt, nt>(const ModexpMfmaLaunch &, hipStream_t);
+#include "kernel_configs_mfma.inc"
+#undef RNSRSA_MSHAPE
+
+bool mfma_supported(int K) {
+#define RNSRSA_MSHAPE(k, w, mt, nt) \
+    if (K == k) return true;
+#include "kernel_configs_mfma.inc"
+#undef RNSRSA_MSHAPE
+    return false;
+}
+
+size_t modexp_mfma_table_words(int K, int window, size_t elements, int njobs) {
+#define RNSRSA_MSHAPE(k, w, mt, nt)                                                                 \
+    if (K == k) {                                                                                   \
+        constexpr MLayout ly{k, w, mt, nt};                                                          \
+        const size_t wgs = (elements + ly.NM() - 1) / ly.NM() * (size_t)njobs;                       \
+        return wgs * ((size_t)1 << window) * (size_t)w * ly.SLOTS() * 64;                            \
+    }
+#include "kernel_configs_mfma.inc"
+#undef RNSRSA_MSHAPE
+    return 0;
+}
+
+hipError_t launch_modexp_mfma(int K, const ModexpMfmaLaunch &a, hipStream_t s) {
+#define RNSRSA_MSHAPE(k, w, mt, nt) \
+    if (K == k) return launch_modexp_mfma_t<k, w, mt, nt>(a, s);
+#include "kernel_configs_mfma.inc"
+#undef RNSRSA_MSHAPE
+    return hipErrorInvalidValue;
+}
 
 size_t modexp_table_words(int K, int W, int window, size_t workgroups) {
     const int KS = (K + W - 1) / W;

@@ -1,0 +1,510 @@
+// Matrix-core (MFMA) variant of the exponentiation kernel.
+//
+// Same algorithm as kernels_impl.hpp (RNS Montgomery products with two base
+// extensions, fixed-window exponent loop, CRT exit), but both base extensions
+// run on the int8 matrix cores: each quotient digit xi (a residue below 2^32)
+// is centred and split into four signed bytes, and each extension is the
+// product of a constant A matrix (rows = 4 bytes of each output channel,
+// columns = 4 digits of each input channel, constants pre-multiplied by
+// 2^(8 digit)) with the digit matrix B (columns = elements), accumulated
+// exactly in int32 by v_mfma_i32_16x16x64_i8.  One extra column adds the
+// centring offset c*M; one extra row per wave computes the redundant 2^32
+// channel.  The four byte partials of an output are recombined to a signed
+// 64-bit integer and reduced by one REDC.
+//
+// Layout (plan_mfma.hpp): W waves serve 16*NT elements; lane l of a wave
+// owns slot 4*mt + l/16 of tile mt for elements 16*nt + l%16, which is
+// exactly where the matrix core leaves the outputs of that slot, so the
+// per-channel steps run in place with no transposition.  Channel residues
+// are kept scaled: x*2^32 mod m in B, x*2^32*M^-1 mod m' in B'.
+#pragma once
+
+#include "arith.hpp"
+#include "kernels.hpp"
+#include "mfma_layout.hpp"
+
+namespace rnsrsa {
+
+typedef int mfma_v4i __attribute__((ext_vector_type(4)));
+
+template <int K, int W, int MT, int NT>
+struct MShp {
+    static constexpr MLayout LY{K, W, MT, NT};
+    static constexpr int CH = LY.CH();
+    static constexpr int KSTEPS = LY.KSTEPS();
+    static constexpr int BROW = LY.BROW();
+    static constexpr int NM = LY.NM();
+    static constexpr int SLOTS = LY.SLOTS();
+    static constexpr int ECOLS = (int)LY.ecols();
+    // smallest b with 2^b > K+1: an exit value below (K+2)N has quotient < 2^b
+    static constexpr int qbits() {
+        int b = 0;
+        while ((1 << b) <= K + 1) b++;
+        return b;
+    }
+    static constexpr int EXIT_WORDS = (K + 2 * (K + 1)) * NM;
+    static constexpr int BUF_WORDS = 2 * NM * BROW;
+    static constexpr int LDS_WORDS = EXIT_WORDS > BUF_WORDS ? EXIT_WORDS : BUF_WORDS;
+};
+
+template <int MT, int NT>
+struct MState {
+    uint32_t b[MT][NT];  // slots of B (x * 2^32 mod m)
+    uint32_t p[MT][NT];  // slots of B' (x * 2^32 * M^-1 mod m')
+    uint32_t r[NT];      // redundant channel, replicated over the lane groups
+};
+
+// Per-lane constants held in registers for the whole kernel.
+template <int MT, int KSTEPS>
+struct MConst {
+    mfma_v4i A1[MT][KSTEPS], A2[MT][KSTEPS];
+    uint32_t mB[MT], uB[MT], nuB[MT], cB[MT];
+    uint32_t mP[MT], uP[MT], HP[MT];
+    uint32_t Mpinv_r, Minv_r, N_r;
+};
+
+// balanced four-byte digits of a residue of m, packed as signed bytes
+__device__ __forceinline__ uint32_t mfma_pack(uint32_t v, uint32_t m) {
+    const uint32_t c = v >= kDigitSplit ? v - m : v;     // centred, as a 32-bit two's complement value
+    return (c + 0x80808080u) ^ 0x80808080u;
+}
+
+// signed 64-bit value of the four byte partials of one output
+__device__ __forceinline__ int64_t mfma_combine(const mfma_v4i &d) {
+    const int32_t t1 = d[0] + (d[1] << 8);
+    const int32_t t2 = d[2] + (d[3] << 8);
+    return (int64_t)t1 + ((int64_t)t2 << 16);
+}
+
+// (S + off) * 2^-32 mod m for |S| < 2^47, off = m * 2^16 keeps it positive.
+__device__ __forceinline__ uint32_t mfma_reduce(int64_t S, uint32_t m, uint32_t u) {
+    const uint64_t x = (uint64_t)(S + ((int64_t)m << 16));
+    return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
+}
+
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C, bool second,
+                                               const uint32_t *buf, int lane, mfma_v4i (&D)[MT][NT]) {
+    using S = MShp<K, W, MT, NT>;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) D[mt][nt] = mfma_v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < S::KSTEPS; ks++) {
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const mfma_v4i bop =
+                *(const mfma_v4i *)(buf + (16 * nt + (lane & 15)) * S::BROW + 16 * ks + 4 * (lane >> 4));
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++)
+                D[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(second ? C.A2[mt][ks] : C.A1[mt][ks], bop,
+                                                                   D[mt][nt], 0, 0, 0);
+        }
+    }
+}
+
+// One RNS Montgomery product x <- x*y*M^-1 in the matrix-core layout.  With
+// full == false the second extension is skipped (the caller leaves the RNS
+// from the xi' digits in buf2).  Returns nothing; x.r holds the new redundant
+// residue.
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C, MState<MT, NT> &x,
+                                        const MState<MT, NT> &y, uint32_t *buf1, uint32_t *buf2, int wave, int lane,
+                                        bool full) {
+    using S = MShp<K, W, MT, NT>;
+    const int g = lane >> 4;
+    // (i) quotient digits of B, published as the B operand of the first extension
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const int ch = wave * S::CH + 4 * mt + g;
+        const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], C.mB[mt], C.uB[mt]);   // x y 2^32
+            const uint32_t xi = mulredc(t, C.cB[mt], C.mB[mt], C.uB[mt]);              // x y c_i
+            if (real) buf1[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xi, C.mB[mt]);
+        }
+    }
+    uint32_t a1[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) a1[mt][nt] = mulredc(x.p[mt][nt], y.p[mt][nt], C.mP[mt], C.uP[mt]);
+    uint32_t sr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) sr[nt] = x.r[nt] * y.r[nt];
+    __syncthreads();
+
+    // (ii) first extension on the matrix cores: q^'' N M^-1 (scaled) in each B' slot
+    mfma_v4i D[MT][NT];
+    mfma_extension<K, W, MT, NT>(C, false, buf1, lane, D);
+    const int rsrc = ((lane & 15) + 48) * 4;
+    uint32_t rr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        const uint32_t lo = (uint32_t)mfma_combine(D[MT - 1][nt]);
+        const uint32_t qr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)lo);   // q^'' mod 2^32
+        rr[nt] = (sr[nt] + qr * C.N_r) * C.Minv_r;
+    }
+    // (iii) r = (XY + q^'' N)/M in B'; publish xi' for the second extension
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const int ch = wave * S::CH + 4 * mt + g;
+        const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const uint32_t m = C.mP[mt];
+            const uint32_t q = mfma_reduce(mfma_combine(D[mt][nt]), m, C.uP[mt]);
+            uint32_t r;
+            const bool ov = __builtin_add_overflow(a1[mt][nt], q, &r);
+            r = (ov || r >= m) ? r - m : r;
+            x.p[mt][nt] = r;
+            const uint32_t xip = mulredc(r, C.HP[mt], m, C.uP[mt]);                     // r (M'_t)^-1
+            if (real) buf2[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xip, m);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) x.r[nt] = rr[nt];
+    __syncthreads();
+    if (!full) return;
+
+    // (iv) second extension, made exact by alpha from the redundant channel
+    mfma_extension<K, W, MT, NT>(C, true, buf2, lane, D);
+    uint32_t alpha[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        const uint32_t lo = (uint32_t)mfma_combine(D[MT - 1][nt]);
+        const uint32_t s2 = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)lo);
+        alpha[nt] = (s2 - rr[nt]) * C.Mpinv_r;
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int64_t s = mfma_combine(D[mt][nt]) + (int64_t)((uint64_t)alpha[nt] * C.nuB[mt]);
+            x.b[mt][nt] = mfma_reduce(s, C.mB[mt], C.uB[mt]);
+        }
+}
+
+template <int MT, int NT>
+__device__ __forceinline__ void mstate_store(uint32_t *__restrict__ p, const MState<MT, NT> &a) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            p[(mt * NT + nt) * 64] = a.b[mt][nt];
+            p[(MT * NT + mt * NT + nt) * 64] = a.p[mt][nt];
+        }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) p[(2 * MT * NT + nt) * 64] = a.r[nt];
+}
+
+template <int MT, int NT>
+__device__ __forceinline__ void mstate_load(const uint32_t *__restrict__ p, MState<MT, NT> &a) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            a.b[mt][nt] = p[(mt * NT + nt) * 64];
+            a.p[mt][nt] = p[(MT * NT + mt * NT + nt) * 64];
+        }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) a.r[nt] = p[(2 * MT * NT + nt) * 64];
+}
+
+__device__ __forceinline__ uint32_t mexp_digit(const uint32_t *__restrict__ e, int nlimbs, int nd, int w, int di) {
+    const int lo = (nd - 1 - di) * w;
+    const int limb = lo >> 5, sh = lo & 31;
+    uint64_t v = e[limb];
+    if (limb + 1 < nlimbs) v |= (uint64_t)e[limb + 1] << 32;
+    return (uint32_t)(v >> sh) & ((1u << w) - 1u);
+}
+
+// Exponentiation kernel, matrix-core variant.  Same contract as
+// modexp_kernel (kernels_impl.hpp); bc / mc are the channel tables of that
+// kernel (used to leave the RNS), mb / mk the matrix-core tables.
+template <int K, int W, int MT, int NT>
+__global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
+    const uint32_t *__restrict__ mb, const uint32_t *__restrict__ mk0, const uint32_t *__restrict__ mk1,
+    const uint32_t *__restrict__ E0, const uint32_t *__restrict__ E1, const uint32_t *__restrict__ ex0,
+    const uint32_t *__restrict__ ex1, const uint32_t *__restrict__ in, uint32_t *__restrict__ out0,
+    uint32_t *__restrict__ out1, uint32_t *__restrict__ table, ModexpParams P) {
+    using S = MShp<K, W, MT, NT>;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
+    uint32_t *buf1 = lds;
+    uint32_t *buf2 = lds + S::NM * S::BROW;
+
+    const int job = blockIdx.y;
+    const uint32_t *__restrict__ mk = job ? mk1 : mk0;
+    const uint32_t *__restrict__ E = job ? E1 : E0;
+    const uint32_t *__restrict__ ex = job ? ex1 : ex0;
+    uint32_t *__restrict__ out = job ? out1 : out0;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+
+    // constant digit rows: channel K holds the offset digit 1, the rest zero
+    for (int i = threadIdx.x; i < S::NM * (S::BROW - K); i += 64 * W) {
+        const int n = i / (S::BROW - K), c = K + i % (S::BROW - K);
+        const uint32_t v = c == K ? 1u : 0u;
+        buf1[n * S::BROW + c] = v;
+        buf2[n * S::BROW + c] = v;
+    }
+
+    // per-lane constants
+    MConst<MT, S::KSTEPS> C;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const size_t sl = (size_t)wave * MT + mt;
+#pragma unroll
+        for (int ks = 0; ks < S::KSTEPS; ks++) {
+            const size_t ti = ((sl * S::KSTEPS + ks) * 64 + lane) * 4;
+            C.A1[mt][ks] = *(const mfma_v4i *)(mk + S::LY.a1() + ti);
+            C.A2[mt][ks] = *(const mfma_v4i *)(mb + S::LY.a2() + ti);
+        }
+        C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
+        C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
+        C.nuB[mt] = mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
+        C.mP[mt] = mb[S::LY.slotP() + (sl * 4 + 0) * 64 + lane];
+        C.uP[mt] = mb[S::LY.slotP() + (sl * 4 + 1) * 64 + lane];
+        C.HP[mt] = mb[S::LY.slotP() + (sl * 4 + 2) * 64 + lane];
+        C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
+    }
+    C.Mpinv_r = mb[S::LY.bscal() + 0];
+    C.Minv_r = mb[S::LY.bscal() + 1];
+    C.N_r = mk[S::LY.kscal() + 0];
+
+    // entry: residues of Z = sum_h X_h Y_h in the kept representation
+    MState<MT, NT> a, y;
+    {
+        Acc ab[MT][NT], ap[MT][NT];
+        uint32_t zr[NT];
+        int msg[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            msg[nt] = blockIdx.x * S::NM + 16 * nt + (lane & 15);
+            zr[nt] = 0;
+        }
+        const int colB = wave * 4 * MT + g, colP = W * 4 * MT + wave * 4 * MT + g;
+        for (int l = 0; l < P.in_limbs; l++) {
+            const uint32_t *__restrict__ row = E + (size_t)l * S::ECOLS;
+            uint32_t v[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++)
+                v[nt] = msg[nt] < P.batch ? in[(size_t)msg[nt] * P.in_stride + l] : 0u;
+            const uint32_t er = row[S::ECOLS - 1];
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++) {
+                const uint32_t eb = row[colB + 4 * mt], ep = row[colP + 4 * mt];
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) {
+                    acc_mac(ab[mt][nt], v[nt], eb);
+                    acc_mac(ap[mt][nt], v[nt], ep);
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) zr[nt] += v[nt] * er;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) {
+                a.b[mt][nt] = acc_redc(ab[mt][nt], C.mB[mt], C.uB[mt]);
+                a.p[mt][nt] = acc_redc(ap[mt][nt], C.mP[mt], C.uP[mt]);
+            }
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) a.r[nt] = zr[nt];
+    }
+    // y = 1 in the kept representation: 2^32 mod m in B, 2^32 M^-1 mod m' in B'
+    MState<MT, NT> unit;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const uint32_t kap = mb[S::LY.slotP() + (((size_t)wave * MT + mt) * 4 + 3) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            unit.b[mt][nt] = 0u - C.mB[mt];
+            unit.p[mt][nt] = kap;
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) unit.r[nt] = 1u;
+
+    const int w = P.window;
+    const int T = 1 << w;
+    const size_t wg = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const size_t estride = (size_t)W * S::SLOTS * 64;
+    uint32_t *__restrict__ tw = table + (wg * T * W + wave) * (size_t)(S::SLOTS * 64) + lane;
+    {
+        MState<MT, NT> one;
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++) {
+            const size_t sl = (size_t)wave * MT + mt;
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) {
+                one.b[mt][nt] = mk[S::LY.one() + (sl * 2 + 0) * 64 + lane];
+                one.p[mt][nt] = mk[S::LY.one() + (sl * 2 + 1) * 64 + lane];
+            }
+        }
+        const uint32_t onr = mk[S::LY.one() + (size_t)W * MT * 2 * 64];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) one.r[nt] = onr;
+        mstate_store<MT, NT>(tw, one);   // T[0] = M mod N
+    }
+
+    const int nd = (32 * P.exp_limbs + w - 1) / w;
+    const bool shared_exp = P.exp_stride == 0;
+    enum { ENTRY, BUILD, MAIN, EXIT };
+    int phase = ENTRY, j = 2, di = 0, s = 0;
+    y = unit;
+    for (;;) {
+        mfma_mm<K, W, MT, NT>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
+        if (phase == EXIT) break;
+        if (phase == ENTRY) {
+            mstate_store<MT, NT>(tw + estride, a);
+            phase = BUILD;
+        } else if (phase == BUILD) {
+            mstate_store<MT, NT>(tw + (size_t)j * estride, a);
+            j++;
+        }
+        if (phase == BUILD) {
+            if (j < T) {
+                mstate_load<MT, NT>(tw + estride, y);
+                continue;
+            }
+            phase = MAIN;
+            s = 0;
+            if (shared_exp) {
+                uint32_t d = 0;
+                while (di < nd) {
+                    d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, P.exp_limbs, nd, w, di));
+                    if (d) break;
+                    di++;
+                }
+                if (di < nd) {
+                    mstate_load<MT, NT>(tw + (size_t)d * estride, a);
+                    di++;
+                } else {
+                    mstate_load<MT, NT>(tw, a);
+                }
+            } else {
+                mstate_load<MT, NT>(tw, a);
+            }
+        }
+        for (;;) {
+            if (di >= nd) {
+                phase = EXIT;
+                y = unit;
+                break;
+            }
+            if (s < w) {
+                y = a;
+                s++;
+                break;
+            }
+            di++;
+            s = 0;
+            if (shared_exp) {
+                const uint32_t d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, P.exp_limbs, nd, w, di - 1));
+                if (d != 0) {
+                    mstate_load<MT, NT>(tw + (size_t)d * estride, y);
+                    break;
+                }
+            } else {
+                // per-element exponents: each lane slot loads the entry of its own element
+                MState<MT, NT> t;
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) {
+                    const int m = blockIdx.x * S::NM + 16 * nt + (lane & 15);
+                    const uint32_t *__restrict__ ep = ex + (size_t)(m < P.batch ? m : 0) * P.exp_stride;
+                    const uint32_t d = mexp_digit(ep, P.exp_limbs, nd, w, di - 1);
+                    const uint32_t *__restrict__ pe = tw + (size_t)d * estride;
+#pragma unroll
+                    for (int mt = 0; mt < MT; mt++) {
+                        t.b[mt][nt] = pe[(mt * NT + nt) * 64];
+                        t.p[mt][nt] = pe[(MT * NT + mt * NT + nt) * 64];
+                    }
+                    t.r[nt] = pe[(2 * MT * NT + nt) * 64];
+                }
+                y = t;
+                break;
+            }
+        }
+    }
+
+    // leave the RNS: wave 0, lane n < NM handles element n of the workgroup
+    __syncthreads();
+    if (wave != 0 || lane >= S::NM) return;
+    const int n = lane;
+    const int msg = blockIdx.x * S::NM + n;
+    uint32_t rr = a.r[0];
+#pragma unroll
+    for (int nt = 1; nt < NT; nt++) rr = (n >> 4) == nt ? a.r[nt] : rr;   // lane n holds element n's r in slot n/16
+    const int L = P.L;
+    constexpr int NM = S::NM;
+    uint32_t *X = lds;                               // [K][NM] xi'_j of the exit product
+    uint32_t *acc = lds + K * NM;                    // [L+1][NM]
+    uint32_t *tmp = acc + (L + 1) * NM;              // [L+1][NM]
+    uint32_t s2 = 0;
+    for (int jj = 0; jj < K; jj++) {
+        const uint32_t packed = buf2[n * S::BROW + jj];
+        uint32_t v = (packed ^ 0x80808080u) - 0x80808080u;           // centred digit mod 2^32
+        const uint32_t mj = mb[S::LY.mpj() + jj];
+        v = v >= kDigitSplit ? v + mj : v;                            // back to [0, m'_j)
+        X[jj * NM + n] = v;
+        s2 += v * mb[S::LY.mplo() + jj];
+    }
+    const uint32_t alpha = (s2 - rr) * C.Mpinv_r;                    // in [0, K)
+    {
+        uint64_t carry = 0;
+        for (int l = 0; l <= L; l++) {
+            Acc sum;
+            sum.lo = carry;
+            for (int jj = 0; jj < K; jj++) acc_mac(sum, X[jj * NM + n], mb[S::LY.MpL() + (size_t)jj * (K + 1) + l]);
+            uint64_t lo;
+            uint32_t top;
+            acc_value(sum, lo, top);
+            acc[l * NM + n] = (uint32_t)lo;
+            carry = (lo >> 32) | ((uint64_t)top << 32);
+        }
+    }
+    {
+        uint64_t carry = 0;
+        uint32_t borrow = 0;
+        for (int l = 0; l <= L; l++) {
+            const uint64_t p = (uint64_t)alpha * mb[S::LY.MpF() + l] + carry;
+            carry = p >> 32;
+            const uint32_t v = acc[l * NM + n], pl = (uint32_t)p;
+            const uint32_t d = v - pl, d2 = d - borrow;
+            borrow = (v < pl) | (d < borrow);
+            acc[l * NM + n] = d2;
+        }
+    }
+    for (int b = S::qbits() - 1; b >= 0; b--) {
+        uint32_t borrow = 0;
+        for (int l = 0; l <= L; l++) {
+            const uint32_t nlo = l < L ? mk[S::LY.Nl() + l] : 0u;
+            const uint32_t nhi = (b && l > 0) ? (mk[S::LY.Nl() + l - 1] >> (32 - b)) : 0u;
+            const uint32_t nl = (nlo << b) | nhi;
+            const uint32_t v = acc[l * NM + n];
+            const uint32_t d = v - nl, d2 = d - borrow;
+            borrow = (v < nl) | (d < borrow);
+            tmp[l * NM + n] = d2;
+        }
+        if (!borrow)
+            for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
+    }
+    if (msg < P.batch)
+        for (int l = 0; l < L; l++) out[(size_t)msg * P.out_stride + l] = acc[l * NM + n];
+}
+
+template <int K, int W, int MT, int NT>
+hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s) {
+    const unsigned gx = (unsigned)((a.P.batch + 16 * NT - 1) / (16 * NT));
+    hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT>), dim3(gx, (unsigned)a.njobs), dim3(64 * W), 0, s, a.mb,
+                       a.mk[0], a.mk[1], a.E[0], a.E[1], a.exp[0], a.exp[1], a.in, a.out[0], a.out[1], a.table,
+                       a.P);
+    return hipGetLastError();
+}
+
+}  // namespace rnsrsa

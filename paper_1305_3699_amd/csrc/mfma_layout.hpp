@@ -1,0 +1,50 @@
+// Word layout of the matrix-core kernel's tables, shared by the host code that
+// builds them (plan_mfma.cpp) and the kernel that reads them (kernels_mfma.hpp).
+// All per-lane tables have rows of 64 words (one per lane) so each lane reads
+// its own value with one coalesced load.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rnsrsa {
+
+// Balanced-digit threshold: a residue v >= kDigitSplit of m is stored as the
+// negative value v - m, so that every stored value lies in
+// [kDigitSplit - m, kDigitSplit), inside the range of four signed bytes
+// [-0x80808080, 0x7F7F7F7F].  For m > 2^31 + kDigitSplit that range reaches
+// below -2^31: a stored value is negative exactly when its 32-bit pattern is
+// >= kDigitSplit, never by its int32 sign.
+constexpr uint32_t kDigitSplit = 0x7F7F7F80u;
+
+struct MLayout {
+    int K, W, MT, NT;
+    constexpr int CH() const { return 4 * MT - 1; }                 // prime channels per wave
+    constexpr int KSTEPS() const { return (4 * K + 1 + 63) / 64; }  // 64-deep steps: 4 digits/channel + offset
+    constexpr int KCH() const { return KSTEPS() * 16; }             // channels covered by the steps
+    constexpr int BROW() const { return KCH() + 4; }                // LDS words per element row of digits
+    constexpr int NM() const { return 16 * NT; }                    // elements per workgroup
+    constexpr int SLOTS() const { return 2 * MT * NT + NT; }        // table words per lane per entry
+    constexpr size_t tiles() const { return (size_t)W * MT * KSTEPS() * 64 * 4; }
+    // key-independent table
+    constexpr size_t a2() const { return 0; }                                  // [W][MT][KSTEPS][64][4] second extension
+    constexpr size_t slotB() const { return tiles(); }                         // [W][MT][3][64] m, m^-1 mod 2^32, nu
+    constexpr size_t slotP() const { return slotB() + (size_t)W * MT * 3 * 64; }  // [W][MT][4][64] m', m'^-1, H, kappa
+    constexpr size_t mpj() const { return slotP() + (size_t)W * MT * 4 * 64; }  // [K] m'_j
+    constexpr size_t mplo() const { return mpj() + K; }                        // [K] M'_j mod 2^32
+    constexpr size_t MpL() const { return mplo() + K; }                        // [K][K+1] limbs of M'_j
+    constexpr size_t MpF() const { return MpL() + (size_t)K * (K + 1); }        // [K+1] limbs of M'
+    constexpr size_t bscal() const { return MpF() + K + 1; }                   // [4] M'^-1, M^-1 mod 2^32
+    constexpr size_t base_size() const { return bscal() + 4; }
+    // per-modulus table
+    constexpr size_t a1() const { return 0; }                                  // [W][MT][KSTEPS][64][4] first extension
+    constexpr size_t slotC() const { return tiles(); }                         // [W][MT][64] c_i
+    constexpr size_t one() const { return slotC() + (size_t)W * MT * 64; }     // [W][MT][2][64] + [1]: M mod N
+    constexpr size_t Nl() const { return one() + (size_t)W * MT * 2 * 64 + 1; }  // [K] limbs of N
+    constexpr size_t kscal() const { return Nl() + K; }                        // [4] N mod 2^32
+    constexpr size_t key_size() const { return kscal() + 4; }
+    // entry table: per input limb [W*4*MT B slots | W*4*MT B' slots | redundant]
+    constexpr size_t ecols() const { return (size_t)2 * W * 4 * MT + 1; }
+};
+
+}  // namespace rnsrsa

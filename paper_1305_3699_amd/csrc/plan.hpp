@@ -51,6 +51,7 @@ struct PlanOptions {
     uint64_t seed = 0x5eed;
     const uint32_t *primes = nullptr;  // explicit 2K primes (B then B')
     size_t n_primes = 0;
+    int engine = 0;              // 0 auto, 1 channel (VALU) kernel, 2 matrix-core kernel
 };
 
 // Returns 0 or a negative status (rnsrsa.h codes); err receives a message.
@@ -65,7 +66,7 @@ int make_modplan_on(const Limbs &N, int L, std::shared_ptr<const BaseSet> bs, Mo
 // value (2^(32 (j mod L)) * Y_(j div L)) mod m, scaled by R^2 for B and B'.
 std::vector<uint32_t> make_entry_table(const ModPlan &mp, const std::vector<Limbs> &Y, int L);
 
-// True when M >= (K+1)^2 N, M >= 2^(32 L + 1), M' >= (K+1) N and no channel
+// True when M >= (K+2)^2 N, M >= 2^(32 L + 1), M' >= (K+2) N and no channel
 // prime of B divides N.
 bool bounds_hold(const BaseSet &bs, const Limbs &N, int L);
 

@@ -1,0 +1,235 @@
+// Host-side tables of the matrix-core exponentiation kernel (plan_mfma.hpp).
+#include "plan_mfma.hpp"
+
+#include <cmath>
+
+namespace rnsrsa {
+
+bool mfma_shape_for(int K, MfmaShape &out) {
+#define RNSRSA_MSHAPE(k, w, mt, nt) \
+    if (K == k) {                   \
+        out = MfmaShape{k, w, mt, nt}; \
+        return true;                \
+    }
+#include "kernel_configs_mfma.inc"
+#undef RNSRSA_MSHAPE
+    return false;
+}
+
+namespace {
+
+// Representative of v mod m in [kDigitSplit - m, kDigitSplit): four balanced bytes.
+int64_t balanced(uint32_t v, uint32_t m) { return v >= kDigitSplit ? (int64_t)v - m : (int64_t)v; }
+
+// Representative of v mod 2^32 in [-0x80808080, 0x7F7F7F7F].
+int64_t balanced32(uint32_t v) { return v > 0x7F7F7F7Fu ? (int64_t)v - ((int64_t)1 << 32) : (int64_t)v; }
+
+// Signed byte b of a balanced value V = sum_b d_b 256^b, d_b in [-128, 127].
+int8_t digit(int64_t V, int b) {
+    uint32_t u = (uint32_t)(V + 0x80808080ll);
+    return (int8_t)((int)((u >> (8 * b)) & 0xFFu) - 128);
+}
+
+// c = ceil(sum_i max(0, 1 - T/m_i)): offset (in multiples of the base product)
+// that makes the extension of centred digits non-negative.
+uint32_t centring_offset(const std::vector<uint32_t> &ms) {
+    double s = 0;
+    for (uint32_t m : ms)
+        if (m > kDigitSplit) s += 1.0 - (double)kDigitSplit / (double)m;
+    return (uint32_t)std::ceil(s);
+}
+
+uint32_t pow2_mod(uint32_t e, uint32_t m) { return powmod32(2, e, m); }
+
+// One matrix of A tiles [W][MT][KSTEPS][64 lanes][16 bytes] from a value
+// function V(slot channel t (-1: redundant), input channel i (K: offset slot), digit a).
+template <class F>
+void fill_tiles(const MfmaShape &sh, uint32_t *dst, F value) {
+    const int KS = sh.KSTEPS();
+    for (int w = 0; w < sh.W; w++)
+        for (int mt = 0; mt < sh.MT; mt++)
+            for (int ks = 0; ks < KS; ks++)
+                for (int l = 0; l < 64; l++) {
+                    uint32_t words[4] = {0, 0, 0, 0};
+                    const int row = l % 16, g = row / 4, b = row % 4;
+                    const int t = mfma_slot_channel(sh, w, mt, g);
+                    for (int j = 0; j < 16; j++) {
+                        const int kappa = 64 * ks + 16 * (l / 16) + j;
+                        const int ch = kappa / 4, a = kappa % 4;
+                        int64_t V = 0;
+                        if (t < sh.K && ch <= sh.K && (ch < sh.K || a == 0)) V = value(t, ch, a);
+                        words[j / 4] |= (uint32_t)(uint8_t)digit(V, b) << (8 * (j % 4));
+                    }
+                    uint32_t *p = dst + ((((size_t)w * sh.MT + mt) * KS + ks) * 64 + l) * 4;
+                    for (int q = 0; q < 4; q++) p[q] = words[q];
+                }
+}
+
+// Per-lane slot table [W][MT][64] of f(channel) (channel -1 or >= K: junk).
+template <class F>
+void fill_slots(const MfmaShape &sh, uint32_t *dst, size_t field_stride, F f) {
+    for (int w = 0; w < sh.W; w++)
+        for (int mt = 0; mt < sh.MT; mt++)
+            for (int l = 0; l < 64; l++) dst[((size_t)w * sh.MT + mt) * field_stride + l] = f(mfma_slot_channel(sh, w, mt, l / 16));
+}
+
+}  // namespace
+
+MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
+    const BaseSet &bs = *mp.base;
+    const int K = bs.K;
+    const MLayout &ly = sh;
+    MfmaTables out;
+    out.shape = sh;
+    out.base.assign(ly.base_size(), 0);
+    out.key.assign(ly.key_size(), 0);
+    const Limbs &N = mp.N;
+    const uint32_t c1 = centring_offset(bs.B), c2 = centring_offset(bs.Bp);
+    const uint32_t Mlo = bn_low(bs.M), Mplo = bn_low(bs.Mp);
+
+    // residues of M_i = M / m_i and M'_j = M' / m'_j modulo other moduli
+    auto Mi_mod = [&](int i, uint32_t m) { return mulmod32(prod_mod32(bs.B, m), invmod32(bs.B[i] % m, m), m); };
+    auto Mpj_mod = [&](int j, uint32_t m) { return mulmod32(prod_mod32(bs.Bp, m), invmod32(bs.Bp[j] % m, m), m); };
+    auto Mi_lo = [&](int i) {
+        uint32_t w = 1;
+        for (int j = 0; j < K; j++)
+            if (j != i) w *= bs.B[j];
+        return w;
+    };
+    auto Mpj_lo = [&](int j) {
+        uint32_t w = 1;
+        for (int t = 0; t < K; t++)
+            if (t != j) w *= bs.Bp[t];
+        return w;
+    };
+
+    // BE1 (key table): slot t of B' gets q^'' * G_t with G_t = N R^2 M^-2 mod m'_t,
+    // so that one REDC of the extension yields q^'' N M^-1 * (R M^-1).
+    std::vector<uint32_t> G(K);
+    for (int t = 0; t < K; t++) {
+        uint32_t m = bs.Bp[t];
+        uint32_t minv = invmod32(prod_mod32(bs.B, m), m);
+        G[t] = mulmod32(mulmod32(bn_mod_word(N, m), pow2_64_mod(m), m), mulmod32(minv, minv, m), m);
+    }
+    fill_tiles(sh, out.key.data() + ly.a1(), [&](int t, int i, int a) -> int64_t {
+        if (t < 0) {
+            uint32_t v = i < K ? Mi_lo(i) << (8 * a) : c1 * Mlo;
+            return balanced32(v);
+        }
+        uint32_t m = bs.Bp[t];
+        uint32_t v = i < K ? mulmod32(mulmod32(Mi_mod(i, m), G[t], m), pow2_mod(8 * a, m), m)
+                           : mulmod32(mulmod32(bn_mod_word(bs.M, m), G[t], m), c1 % m, m);
+        return balanced(v, m);
+    });
+    // BE2 (base table): slot i of B gets (sum xi'_j M'_j + c2 M') R^2 mod m_i.
+    fill_tiles(sh, out.base.data() + ly.a2(), [&](int t, int j, int a) -> int64_t {
+        if (t < 0) {
+            uint32_t v = j < K ? Mpj_lo(j) << (8 * a) : c2 * Mplo;
+            return balanced32(v);
+        }
+        uint32_t m = bs.B[t];
+        uint32_t v = j < K ? mulmod32(mulmod32(Mpj_mod(j, m), pow2_64_mod(m), m), pow2_mod(8 * a, m), m)
+                           : mulmod32(mulmod32(bn_mod_word(bs.Mp, m), pow2_64_mod(m), m), c2 % m, m);
+        return balanced(v, m);
+    });
+
+    // per-slot constants; junk slots use a valid modulus and zero constants
+    const uint32_t mB0 = bs.B[K - 1], mP0 = bs.Bp[K - 1];
+    const size_t fs = (size_t)3 * 64;      // [W][MT][3][64]
+    auto okc = [&](int t) { return t >= 0 && t < K; };
+    fill_slots(sh, out.base.data() + ly.slotB() + 0 * 64, fs, [&](int t) { return okc(t) ? bs.B[t] : mB0; });
+    fill_slots(sh, out.base.data() + ly.slotB() + 1 * 64, fs, [&](int t) { return inv2_32(okc(t) ? bs.B[t] : mB0); });
+    fill_slots(sh, out.base.data() + ly.slotB() + 2 * 64, fs, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        uint32_t m = bs.B[t], mpm = prod_mod32(bs.Bp, m);
+        return mulmod32(mpm ? m - mpm : 0, pow2_64_mod(m), m);   // nu = -M' R^2 mod m_i
+    });
+    const size_t fp = (size_t)4 * 64;      // [W][MT][4][64]
+    fill_slots(sh, out.base.data() + ly.slotP() + 0 * 64, fp, [&](int t) { return okc(t) ? bs.Bp[t] : mP0; });
+    fill_slots(sh, out.base.data() + ly.slotP() + 1 * 64, fp, [&](int t) { return inv2_32(okc(t) ? bs.Bp[t] : mP0); });
+    fill_slots(sh, out.base.data() + ly.slotP() + 3 * 64, fp, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        uint32_t m = bs.Bp[t];
+        return mulmod32(pow2_32_mod(m), invmod32(prod_mod32(bs.B, m), m), m);     // kappa = R M^-1
+    });
+    fill_slots(sh, out.base.data() + ly.slotP() + 2 * 64, fp, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        uint32_t m = bs.Bp[t];
+        std::vector<uint32_t> others;
+        for (int j = 0; j < K; j++)
+            if (j != t) others.push_back(bs.Bp[j]);
+        return mulmod32(prod_mod32(bs.B, m), invmod32(prod_mod32(others, m), m), m);   // H = M (M'_t)^-1
+    });
+    // leaving the RNS: m'_j, M'_j mod 2^32, limbs of M'_j and of M'
+    for (int j = 0; j < K; j++) {
+        out.base[ly.mpj() + j] = bs.Bp[j];
+        out.base[ly.mplo() + j] = Mpj_lo(j);
+        std::vector<uint32_t> others;
+        for (int t = 0; t < K; t++)
+            if (t != j) others.push_back(bs.Bp[t]);
+        Limbs Mj{1};
+        for (uint32_t x : others) Mj = bn_mul_word(Mj, x);
+        for (int l = 0; l <= K && l < (int)Mj.size(); l++) out.base[ly.MpL() + (size_t)j * (K + 1) + l] = Mj[l];
+    }
+    for (int l = 0; l <= K && l < (int)bs.Mp.size(); l++) out.base[ly.MpF() + l] = bs.Mp[l];
+    out.base[ly.bscal() + 0] = inv2_32(Mplo);
+    out.base[ly.bscal() + 1] = inv2_32(Mlo);
+
+    // key: c_i = -N^-1 M_i^-1 mod m_i; "one" = M mod N in the kept representation
+    fill_slots(sh, out.key.data() + ly.slotC(), 64, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        uint32_t m = bs.B[t];
+        uint32_t ninv = invmod32(bn_mod_word(N, m), m);
+        std::vector<uint32_t> others;                                  // M_t mod m_t: product of the other primes
+        for (int j = 0; j < K; j++)
+            if (j != t) others.push_back(bs.B[j]);
+        return mulmod32(m - ninv, invmod32(prod_mod32(others, m), m), m);
+    });
+    const size_t os = (size_t)2 * 64;      // [W][MT][2][64]
+    fill_slots(sh, out.key.data() + ly.one(), os, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        uint32_t m = bs.B[t];
+        return mulmod32(bn_mod_word(mp.Mmod, m), pow2_32_mod(m), m);
+    });
+    fill_slots(sh, out.key.data() + ly.one() + 64, os, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        uint32_t m = bs.Bp[t];
+        uint32_t kappa = mulmod32(pow2_32_mod(m), invmod32(prod_mod32(bs.B, m), m), m);   // R M^-1
+        return mulmod32(bn_mod_word(mp.Mmod, m), kappa, m);
+    });
+    out.key[ly.one() + (size_t)sh.W * sh.MT * 2 * 64] = bn_low(mp.Mmod);
+    for (int l = 0; l < K && l < (int)N.size(); l++) out.key[ly.Nl() + l] = N[l];
+    out.key[ly.kscal() + 0] = bn_low(N);
+    return out;
+}
+
+std::vector<uint32_t> make_mfma_entry_table(const ModPlan &mp, const MfmaShape &sh, const std::vector<Limbs> &Y,
+                                            int L) {
+    const BaseSet &bs = *mp.base;
+    const int K = bs.K;
+    const MLayout &ly = sh;
+    const size_t cols = ly.ecols();
+    const int rows = (int)Y.size() * L;
+    const int SW = 4 * sh.MT;    // slots per wave
+    std::vector<uint32_t> e((size_t)rows * cols, 0);
+    for (int j = 0; j < rows; j++) {
+        Limbs v = bn_shl(Y[j / L], 32u * (j % L));
+        for (int w = 0; w < sh.W; w++)
+            for (int s = 0; s < SW; s++) {
+                const int t = mfma_slot_channel(sh, w, s / 4, s % 4);
+                if (t < 0 || t >= K) continue;
+                uint32_t m = bs.B[t];
+                uint32_t r3 = mulmod32(pow2_64_mod(m), pow2_32_mod(m), m);
+                e[(size_t)j * cols + (size_t)w * SW + s] = mulmod32(bn_mod_word(v, m), r3, m);
+                uint32_t mp2 = bs.Bp[t];
+                uint32_t r3p = mulmod32(pow2_64_mod(mp2), pow2_32_mod(mp2), mp2);
+                uint32_t minv = invmod32(prod_mod32(bs.B, mp2), mp2);
+                e[(size_t)j * cols + (size_t)sh.W * SW + (size_t)w * SW + s] =
+                    mulmod32(mulmod32(bn_mod_word(v, mp2), r3p, mp2), minv, mp2);
+            }
+        e[(size_t)j * cols + cols - 1] = bn_low(v);
+    }
+    return e;
+}
+
+}  // namespace rnsrsa

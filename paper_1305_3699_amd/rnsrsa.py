@@ -22,6 +22,9 @@ STATUS_NAMES = {0: "RNS_OK", -1: "RNS_EINVAL", -2: "RNS_ERANGE", -3: "RNS_EFACTO
                 -5: "RNS_EDEVICE", -6: "RNS_EVERIFY", -7: "RNS_EBUSY", -8: "RNS_EUNSUPPORTED"}
 PRIMES_HIGH = 0
 PRIMES_FULL = 1
+ENGINE_AUTO = 0
+ENGINE_CHANNEL = 1
+ENGINE_MATRIX = 2
 
 
 class RnsError(RuntimeError):
@@ -33,12 +36,13 @@ class RnsError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("window", ctypes.c_int), ("waves", ctypes.c_int),
                 ("prime_range", ctypes.c_int), ("prime_seed", ctypes.c_uint64),
-                ("primes", ctypes.POINTER(ctypes.c_uint32)), ("n_primes", ctypes.c_size_t)]
+                ("primes", ctypes.POINTER(ctypes.c_uint32)), ("n_primes", ctypes.c_size_t),
+                ("engine", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("waves", ctypes.c_int), ("window", ctypes.c_int),
-                ("mod_limbs", ctypes.c_int), ("mod_bits", ctypes.c_int)]
+                ("mod_limbs", ctypes.c_int), ("mod_bits", ctypes.c_int), ("engine", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -112,9 +116,10 @@ def _host_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _make_opts(k=0, window=0, waves=0, prime_range=PRIMES_HIGH, prime_seed=0, primes=None):
+def _make_opts(k=0, window=0, waves=0, prime_range=PRIMES_HIGH, prime_seed=0, primes=None, engine=ENGINE_AUTO):
     o = Opts()
     o.k, o.window, o.waves, o.prime_range, o.prime_seed = k, window, waves, prime_range, prime_seed
+    o.engine = engine
     keep = None
     if primes is not None:
         keep = np.ascontiguousarray(primes, dtype=np.uint32)
@@ -146,7 +151,7 @@ def _info(getter, handle, *extra) -> dict:
     inf = Info()
     _check(getter(handle, *extra, ctypes.byref(inf)))
     return {"k": inf.k, "waves": inf.waves, "window": inf.window, "mod_limbs": inf.mod_limbs,
-            "mod_bits": inf.mod_bits}
+            "mod_bits": inf.mod_bits, "engine": inf.engine}
 
 
 class RnsContext:

@@ -115,11 +115,13 @@ def test_window_invariance(window):
 
 @pytest.mark.parametrize("k,waves", [(17, 1), (17, 2), (33, 1), (33, 2), (33, 3), (33, 4), (49, 7), (65, 5)])
 def test_shape_invariance(k, waves):
+    """Every wave shape of the channel engine gives the oracle's results."""
+    from paper_1305_3699_amd import ENGINE_CHANNEL
     rng = random.Random(k * 10 + waves)
     bits = 32 * (k - 1)
     N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
     L = k - 1
-    ctx = _ctx(N, L, k=k, waves=waves)
+    ctx = _ctx(N, L, k=k, waves=waves, engine=ENGINE_CHANNEL)
     info = ctx.info
     assert info["k"] == k and info["waves"] == waves
     bases = [rng.getrandbits(32 * L) for _ in range(66)]
@@ -127,6 +129,38 @@ def test_shape_invariance(k, waves):
     el = gen.to_limbs(e, 3)[0]
     got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
     assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
+
+
+@pytest.mark.parametrize("bits", [20, 64, 130, 500, 1024, 1500, 2048, 3072, 4096])
+def test_engines_agree(bits):
+    """Channel and matrix-core engines give identical bytes, equal to the oracle."""
+    from paper_1305_3699_amd import ENGINE_CHANNEL, ENGINE_MATRIX
+    rng = random.Random(bits + 5)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | rng.getrandbits(1)
+    L = (bits + 31) // 32
+    bases = gen.to_limbs([rng.getrandbits(32 * L) for _ in range(97)] + [0, 1, N - 1], L)
+    e = gen.to_limbs(rng.getrandbits(70) | (1 << 69), 3)[0]
+    outs = []
+    for eng in (ENGINE_CHANNEL, ENGINE_MATRIX):
+        ctx = _ctx(N, L, engine=eng, window=4)
+        assert ctx.info["engine"] == eng
+        outs.append(_run_modexp(ctx, bases, e))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[1], oracle.modexp_batch(bases, e, gen.to_limbs(N, L)[0]))
+
+
+@pytest.mark.parametrize("engine", [1, 2])
+def test_rsa2048_crt_both_engines(engine):
+    from paper_1305_3699_amd import RsaKey
+    key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
+    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, engine=engine)
+    assert rk.info(1)["engine"] == engine
+    c = gen.uniform_below(key.n, 70, seed=12) + [0, 1, key.n - 1, key.p, key.q]
+    cl = gen.to_limbs(c, 64)
+    got = _host(rk.decrypt(_dev(cl), use_crt=True))
+    assert np.array_equal(got, oracle.rsa_crt_batch(cl, key.p, key.q, key.dp, key.dq, key.qinv))
+    got2 = _host(rk.decrypt(_dev(cl), use_crt=False))
+    assert np.array_equal(got2, got)
 
 
 def test_mont_mul_matches_definition():

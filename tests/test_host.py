@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(rnsrsa.exported_symbols())
-    assert lib.rns_abi_version() == 1
+    assert lib.rns_abi_version() == 2
 
 
 def _check_bounds(plan, N, L):
@@ -48,7 +48,7 @@ def _check_bounds(plan, N, L):
     assert len(set(pr)) == 2 * k
     assert all((1 << 31) < p < (1 << 32) and pow(2, p - 1, p) == 1 for p in pr)
     M, Mp = math.prod(B), math.prod(Bp)
-    assert M >= (k + 1) ** 2 * N and M >= 2 ** (32 * L + 1) and Mp >= (k + 1) * N
+    assert M >= (k + 2) ** 2 * N and M >= 2 ** (32 * L + 1) and Mp >= (k + 2) * N
     assert math.gcd(M, N) == 1
 
 
@@ -110,12 +110,17 @@ def test_emul_mont_mul_matches_definition(bits):
     assert np.array_equal(out, _res(want, B, Bp))
 
 
+ENGINES = [rnsrsa.ENGINE_CHANNEL, rnsrsa.ENGINE_MATRIX]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("bits,window", [(12, 5), (64, 1), (250, 3), (1024, 5), (1024, 6), (2048, 4)])
-def test_emul_modexp_matches_oracle(bits, window):
+def test_emul_modexp_matches_oracle(bits, window, engine):
     rng = random.Random(bits * 7 + window)
     N = rng.getrandbits(bits) | (1 << (bits - 1)) | rng.getrandbits(1)
     L = (bits + 31) // 32
-    p = Plan(N, L, window=window)
+    p = Plan(N, L, window=window, engine=engine)
+    assert p.info["engine"] == engine
     bases = [rng.getrandbits(32 * L) for _ in range(5)] + [0, 1, N - 1, N, (1 << (32 * L)) - 1]
     e = rng.getrandbits(min(bits, 200)) | 1
     out = p.emul_modexp(gen.to_limbs(bases, L), gen.to_limbs(e, (e.bit_length() + 31) // 32)[0])
@@ -124,9 +129,10 @@ def test_emul_modexp_matches_oracle(bits, window):
     assert np.array_equal(out, want)
 
 
-def test_emul_edge_exponents_and_per_element():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_emul_edge_exponents_and_per_element(engine):
     N = 3233
-    p = Plan(N, 1, window=2)
+    p = Plan(N, 1, window=2, engine=engine)
     bases = list(range(0, 40)) + [N - 1, N, 2 ** 32 - 1]
     for e in (0, 1, 2, 3, 17, 2753):
         out = p.emul_modexp(gen.to_limbs(bases, 1), np.array([e], np.uint32))
@@ -137,11 +143,54 @@ def test_emul_edge_exponents_and_per_element():
     assert out[:, 0].tolist() == [pow(b, e, N) for b, e in zip(bases, exps)]
 
 
-def test_emul_rsa1024_config_round_trip():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_emul_rsa1024_config_round_trip(engine):
     key = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
-    p = Plan(key.n, 32, prime_range=rnsrsa.PRIMES_FULL, prime_seed=gen.config_seed(1, 4))
+    p = Plan(key.n, 32, prime_range=rnsrsa.PRIMES_FULL, prime_seed=gen.config_seed(1, 4), engine=engine)
     ms = gen.uniform_below(key.n, 4, seed=gen.config_seed(1, 2))
     c = p.emul_modexp(gen.to_limbs(ms, 32), gen.to_limbs(key.e, 1)[0])
     assert oracle.rows_to_ints(c) == [pow(m, key.e, key.n) for m in ms]
     m = p.emul_modexp(c, gen.to_limbs(key.d, 32)[0])
     assert oracle.rows_to_ints(m) == ms
+
+
+def test_engine_selection():
+    assert Plan(3233).info["engine"] == rnsrsa.ENGINE_MATRIX          # auto: matrix cores when built
+    assert Plan(3233, engine=rnsrsa.ENGINE_CHANNEL).info["engine"] == rnsrsa.ENGINE_CHANNEL
+    with pytest.raises(RnsError) as e:
+        Plan(3233, engine=7)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("bits", [96, 1536, 3000])
+def test_emul_engines_agree_per_element_exponents(bits):
+    rng = random.Random(bits)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = (bits + 31) // 32
+    bases = gen.to_limbs([rng.getrandbits(32 * L) for _ in range(33)], L)
+    exps = gen.to_limbs([rng.getrandbits(rng.choice([1, 9, 40])) for _ in range(33)], 2)
+    outs = [Plan(N, L, window=3, engine=e).emul_modexp(bases, exps) for e in ENGINES]
+    assert np.array_equal(outs[0], outs[1])
+    assert oracle.rows_to_ints(outs[1]) == [pow(b, e, N) for b, e in zip(oracle.rows_to_ints(bases),
+                                                                         oracle.rows_to_ints(exps))]
+
+
+def test_emul_exit_digit_below_int32_min():
+    """Regression: at the exit, a centred digit of a prime above 2^31 + T
+    (T = 0x7F7F7F80) can lie below -2^31 and must still be recognised as
+    negative.  For this 100-bit modulus the state of a zero base is c N with
+    c = ceil(sum(1 - T/m_i)), and its first B' digit falls in that range."""
+    rng = random.Random(100)
+    N = rng.getrandbits(100) | (1 << 99) | rng.getrandbits(1)
+    T = 0x7F7F7F80
+    p = Plan(N, 4, window=2, engine=rnsrsa.ENGINE_MATRIX)
+    k = p.info["k"]
+    B, Bp = p.primes[:k], p.primes[k:]
+    c = math.ceil(sum(max(0.0, 1 - T / m) for m in B))
+    Mp = math.prod(Bp)
+    digits = [c * N * pow(Mp // m, -1, m) % m for m in Bp]
+    assert any(T <= d < m - (1 << 31) for d, m in zip(digits, Bp))    # the case is exercised
+    bases = [0, N, 2 * N, 1, N - 1]
+    for e in (1, 2, 65537):
+        out = p.emul_modexp(gen.to_limbs(bases, 4), gen.to_limbs(e, 1)[0])
+        assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]

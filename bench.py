@@ -71,8 +71,9 @@ def kernel_shape(info: dict) -> tuple:
     import re
     txt = open(os.path.join(ROOT, "paper_1305_3699_amd/csrc/kernel_configs_mfma.inc")).read()
     for m in re.finditer(r"RNSRSA_MSHAPE\((\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", txt):
-        if int(m.group(1)) == info["k"]:
-            return tuple(int(v) for v in m.groups())
+        k, w, mt, nt = (int(v) for v in m.groups())
+        if k == info["k"] and w == info["waves"] and 16 * nt == info["group"]:
+            return (k, w, mt, nt)
     return (info["k"], info["waves"])
 
 
@@ -153,7 +154,7 @@ def run(args) -> dict:
         raise SystemExit("bench.py needs the GPU")
     torch.cuda.set_device(0)
     key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
-    opts = {"window": args.window, "engine": args.engine}
+    opts = {"window": args.window, "engine": args.engine, "group": args.group}
     if args.waves:
         opts.update(k=33, waves=args.waves)
     rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, **opts)
@@ -253,6 +254,7 @@ def run(args) -> dict:
             "waves": info["waves"],
             "window": info["window"],
             "engine": ENGINE_NAMES[info["engine"]],
+            "group": info["group"],
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "what": "one step (batch of %d)" % B},
         "modexps_per_s": round(2 * value, 1),
@@ -282,6 +284,76 @@ def run(args) -> dict:
     return out
 
 
+def run_mixed(args) -> dict:
+    """Batched vs plain on the mixed-size workload: 64 seeded keys over
+    1024/2048/3072/4096 bits, lognormal per-key counts (median 128), half
+    encryptions and half CRT decryptions.  plain = one rsa_encrypt /
+    rsa_decrypt call per (key, op) in sequence on one stream; batched = one
+    RsaBatch run (one grouped launch per kernel shape, hipGraph)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RsaBatch, RsaKey
+
+    specs, ops = gen.mixed_batch_spec()
+    keys = gen.rsa_keys(specs, processes=cpu_threads())
+    rks = [RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv) for k in keys]
+    items = []
+    for o in ops:
+        k = keys[o.key_index]
+        vals = gen.uniform_below(k.n, o.count, seed=o.msg_seed)
+        inp = torch.from_numpy(gen.to_limbs(vals, o.bits // 32).view(np.int32)).cuda()
+        items.append((o, rks[o.key_index], inp, torch.empty_like(inp), torch.empty_like(inp)))
+    n_ops = sum(o.count for o in ops)
+
+    def plain_run():
+        for o, rk, inp, out_p, _ in items:
+            if o.kind == "encrypt":
+                rk.encrypt(inp, out=out_p)
+            else:
+                rk.decrypt(inp, use_crt=True, out=out_p)
+
+    t0 = time.perf_counter()
+    batch = RsaBatch([(rk, OP_ENCRYPT if o.kind == "encrypt" else OP_DECRYPT, inp, out_b)
+                      for o, rk, inp, _, out_b in items], autotune=True, use_graph=True)
+    create_s = time.perf_counter() - t0
+    res = {}
+    for name, fn in (("plain", plain_run), ("batched", batch.run)):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.mixed_steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        ms.sort()
+        res[name] = {"ops_per_s": round(n_ops / (statistics.mean(ms) / 1e3), 1),
+                     "ms_p50": round(statistics.median(ms), 3), "ms_p99": round(ms[-1], 3)}
+    same = all(torch.equal(out_p, out_b) for _, _, _, out_p, out_b in items)
+    info = batch.info
+    batch.close()
+    return {
+        "workload": "64 keys (16 each of 1024/2048/3072/4096 bits), per-key counts lognormal(median 128, "
+                    "sigma 1, cap 8192), each message encrypt or CRT-decrypt with p = 0.5",
+        "ops": n_ops,
+        "decrypts": sum(o.count for o in ops if o.kind == "decrypt"),
+        "plain": res["plain"],
+        "batched": res["batched"],
+        "speedup": round(res["batched"]["ops_per_s"] / res["plain"]["ops_per_s"], 2),
+        "batched_matches_plain": bool(same),
+        "launches_per_run": {"batched": info["launches"] + info["garner_launches"],
+                             "plain": len(items) + sum(1 for o in ops if o.kind == "decrypt")},
+        "graph": True,
+        "create_s": round(create_s, 2),
+        "workspace_mb": round(info["workspace_bytes"] / 2 ** 20, 1),
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,8 +363,10 @@ def main(argv=None) -> int:
     ap.add_argument("--window", type=int, default=6)
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (k = 33 shapes)")
     ap.add_argument("--engine", type=int, default=0, help="0 auto, 1 channel (VALU), 2 matrix cores")
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="ciphertexts for the oracle baseline (0: skip)")
+    ap.add_argument("--group", type=int, default=0, help="matrix cores: elements per workgroup (16, 32; 0 default)")
+    ap.add_argument("--cpu-sample", type=int, default=16384, help="ciphertexts for the oracle baseline (0: skip)")
     ap.add_argument("--sweep-window", action="store_true")
+    ap.add_argument("--mixed-steps", type=int, default=5, help="timed runs of the batched-vs-plain mix (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one elementwise copy of N MiB before the benchmark (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -308,10 +382,13 @@ def main(argv=None) -> int:
     if args.sweep_window:
         for w in range(1, 7):
             args.window = w
-            r = run(argparse.Namespace(**{**vars(args), "cpu_sample": 0}))
+            r = run(argparse.Namespace(**{**vars(args), "cpu_sample": 0, "mixed_steps": 0}))
             print(json.dumps(r), flush=True)
         return 0
-    print(json.dumps(run(args)), flush=True)
+    out = run(args)
+    if args.mixed_steps > 0:
+        out["batched_vs_plain"] = run_mixed(args)
+    print(json.dumps(out), flush=True)
     return 0
 
 

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "first_primes", "is_probable_prime", "random_prime", "RsaKey", "rsa_key",
     "uniform_below", "random_exponent", "to_limbs", "limbs_needed",
-    "rns_primes", "config_seed",
+    "rns_primes", "config_seed", "MixedOp", "mixed_batch_spec", "rsa_keys",
 ]
 
 # Seed streams: config i uses 1000*i + s, s in {1: keys, 2: messages,
@@ -195,3 +195,55 @@ def rns_primes(count: int, seed: int, lo: int = 1 << 31, hi: int = 1 << 32,
             seen.add(c)
             out.append(c)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Mixed-size batch: keys of several sizes, per-key lognormal batch sizes,
+# encryptions and CRT decryptions mixed.
+
+
+@dataclass(frozen=True)
+class MixedOp:
+    key_index: int     # index into the key list
+    bits: int          # modulus size
+    kind: str          # "encrypt" or "decrypt"
+    count: int
+    msg_seed: int      # seed of the count messages, uniform in [0, n)
+
+
+def mixed_batch_spec(n_keys: int = 64, sizes=(1024, 2048, 3072, 4096), median: float = 128.0,
+                     sigma: float = 1.0, cap: int = 8192, p_decrypt: float = 0.5, config: int = 4):
+    """Keys split evenly over ``sizes`` (key j has size sizes[j * len(sizes) //
+    n_keys]); key j's batch is round(exp(ln(median) + sigma z_j)), z_j ~ N(0, 1),
+    clipped to [1, cap]; each of its messages is a CRT decryption with
+    probability p_decrypt, else an encryption.  Returns (key_specs, ops) with
+    key_specs = [(bits, key_seed)] and ops a list of MixedOp (an encrypt and a
+    decrypt op per key, either possibly with count 0 omitted)."""
+    rng = np.random.default_rng(config_seed(config, 5))
+    z = rng.standard_normal(n_keys)
+    keys, ops = [], []
+    for j in range(n_keys):
+        bits = sizes[j * len(sizes) // n_keys]
+        keys.append((bits, config_seed(config, 1) * 1000 + j))
+        b = int(min(cap, max(1, round(math.exp(math.log(median) + sigma * z[j])))))
+        n_dec = int(rng.binomial(b, p_decrypt))
+        for kind, cnt in (("encrypt", b - n_dec), ("decrypt", n_dec)):
+            if cnt:
+                ops.append(MixedOp(j, bits, kind, cnt, config_seed(config, 2) * 100000 + 2 * j + (kind == "decrypt")))
+    return keys, ops
+
+
+def _key_job(args):
+    bits, seed = args
+    return rsa_key(bits, seed)
+
+
+def rsa_keys(specs, processes: int = 1) -> list:
+    """rsa_key for each (bits, seed) in specs, optionally in a process pool
+    (key generation is pure Python: seconds per 4096-bit key)."""
+    specs = list(specs)
+    if processes <= 1 or len(specs) < 2:
+        return [rsa_key(b, s) for b, s in specs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(processes, len(specs))) as pool:
+        return pool.map(_key_job, specs)

@@ -82,11 +82,14 @@ enum rns_prime_range {
  *               (2^31, 2^32), B first then B'.  Overrides k and prime_range.
  *   engine      rns_engine (0 = auto).  rns_mont_mul_batch and the Garner
  *               step of CRT decryption always use the channel kernels.
+ *   group       matrix-core engine: preferred elements per workgroup, 16 or
+ *               32 (0 = default for k); a k without a kernel of that size
+ *               uses its default.  rns_info.group reports the size in use.
  * Both bases hold k primes; with the redundant channel 2^32 an operand has
  * 2k+1 residues.  A base pair is accepted for modulus N of L limbs when
- *   M >= (k+2)^2 N,  M >= 2^(32L+1),  M' >= (k+2) N,  gcd(N, M) = 1,
- * which keeps every Montgomery product below (k+2) N (below (k+1) N on the
- * channel engine) and makes the second base extension exact.
+ *   M >= (k+1)^2 N,  M >= 2^(32L+1),  M' >= (k+1) N,  gcd(N, M) = 1,
+ * which keeps every Montgomery product below (k+1) N and makes the second
+ * base extension exact (the redundant residue fixes its multiple of M').
  */
 typedef struct rns_opts {
     int k;
@@ -97,6 +100,7 @@ typedef struct rns_opts {
     const uint32_t *primes;
     size_t n_primes;
     int engine;
+    int group;
 } rns_opts;
 
 typedef struct rns_info {
@@ -106,6 +110,7 @@ typedef struct rns_info {
     int mod_limbs;      /* L */
     int mod_bits;       /* bit length of N */
     int engine;         /* RNS_ENGINE_CHANNEL or RNS_ENGINE_MATRIX */
+    int group;          /* elements served by one workgroup */
 } rns_info;
 
 typedef struct rns_ctx rns_ctx;
@@ -115,7 +120,7 @@ typedef struct rsa_key rsa_key;
  * is valid until the next library call on this thread. */
 const char *rns_last_error(void);
 
-/* ABI version of this header (currently 2). */
+/* ABI version of this header (currently 3). */
 int rns_abi_version(void);
 
 /*
@@ -213,6 +218,70 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
  */
 int rsa_crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, void *hip_stream);
 int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, void *hip_stream);
+
+/*
+ * Batched form: many RSA operations over keys of different sizes in a fixed
+ * set of launches (Sec. 3.3 operations, batched as in Sec. 4.3's throughput
+ * use of many messages).  rsa_batch_create plans a list of operations once;
+ * rsa_batch_run enqueues all of them.  Exponentiations of every key whose
+ * half- or full-size k share a matrix-core kernel shape run in ONE launch per
+ * shape (one workgroup per tile of 16 or 32 elements, longest jobs first),
+ * the launches of different shapes run concurrently on internal streams, and
+ * the Garner steps of CRT decryptions follow.  With use_graph the whole set
+ * is captured once into a hipGraph and each run is one graph launch.
+ *
+ *   rsa_op.kind  RSA_OP_ENCRYPT: out = in^e mod n;
+ *                RSA_OP_DECRYPT: out = in^d mod n, by CRT when the key has
+ *                its CRT parts.
+ *   in, out      device, count x n_limbs(key); they may not overlap other
+ *                operations' buffers; out may equal in.
+ * The buffers, keys and counts are bound at creation: a batch is re-run on
+ * new data by writing into the same buffers.  Keys must outlive the batch.
+ *
+ * Tuning (rsa_batch_opts, NULL = defaults):
+ *   autotune     1: for each kernel shape class, time the candidate tiles
+ *                (elements per workgroup) on the device at creation and keep
+ *                the faster (cached per process); 0: default tiles.
+ *   use_graph    1: capture into a hipGraph at creation (default 1; not
+ *                used when some key runs on the channel engine).
+ *   window       0: per job, the window width minimising the number of
+ *                Montgomery products for its exponent; 1..6: fixed.
+ * Errors: RNS_EINVAL (bad op, null buffer), RNS_ENOMEM, RNS_EDEVICE.
+ * rsa_batch_create may run work on `hip_stream` (autotuning) and returns
+ * after it completed.
+ */
+enum rsa_op_kind { RSA_OP_ENCRYPT = 0, RSA_OP_DECRYPT = 1 };
+
+typedef struct rsa_op {
+    const rsa_key *key;
+    int kind;
+    const uint32_t *in;
+    uint32_t *out;
+    size_t count;
+} rsa_op;
+
+typedef struct rsa_batch_opts {
+    int autotune;
+    int use_graph;
+    int window;
+} rsa_batch_opts;
+
+typedef struct rsa_batch_info {
+    int launches;            /* exponentiation launches per run */
+    int jobs;                /* exponentiation jobs (a CRT decryption is 2) */
+    int garner_launches;
+    size_t workspace_bytes;  /* device memory held by the batch */
+    size_t modmuls;          /* RNS Montgomery products per element, summed over elements */
+} rsa_batch_info;
+
+typedef struct rsa_batch rsa_batch;
+
+int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts, void *hip_stream,
+                     rsa_batch **out);
+int rsa_batch_run(rsa_batch *b, void *hip_stream);
+int rsa_batch_info_get(const rsa_batch *b, rsa_batch_info *info);
+/* Waits for the batch's device work, then releases it. */
+void rsa_batch_free(rsa_batch *b);
 
 #ifdef __cplusplus
 }

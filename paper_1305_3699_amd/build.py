@@ -27,8 +27,10 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           # packed FP32 instructions stay disabled in every HIP compile
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # matrix-core results land in VGPRs (no accumulator-register copies)
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-command-line-argument", "-I", INC, "-I", CSRC]
-HOST_SOURCES = ["capi.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp", "emul_mfma.cpp", "kernels_dispatch.cpp"]
+HOST_SOURCES = ["capi.cpp", "batch.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp", "emul_mfma.cpp", "kernels_dispatch.cpp"]
 
 
 def shapes() -> list:
@@ -78,7 +80,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         src = os.path.join(BUILD, "mshape_%d_%d_%d_%d.hip" % (k, w, mt, nt))
         text = ('#include "kernels_mfma.hpp"\nnamespace rnsrsa {\n'
                 "template hipError_t launch_modexp_mfma_t<%d, %d, %d, %d>(const ModexpMfmaLaunch &, hipStream_t);\n"
-                "}\n" % (k, w, mt, nt))
+                "template int mfma_blocks_per_cu_t<%d, %d, %d, %d>();\n"
+                "}\n" % (k, w, mt, nt, k, w, mt, nt))
         if not os.path.exists(src) or open(src).read() != text:
             with open(src, "w") as f:
                 f.write(text)

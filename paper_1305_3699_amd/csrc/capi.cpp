@@ -9,16 +9,15 @@
 #include <string>
 #include <vector>
 
+#include "capi_internal.hpp"
 #include "emul.hpp"
-#include "kernels.hpp"
-#include "plan.hpp"
-#include "plan_mfma.hpp"
-#include "rnsrsa.h"
 #include "rnsrsa_host.h"
 
 using namespace rnsrsa;
+using namespace rnsrsa::api;
 
-namespace {
+namespace rnsrsa {
+namespace api {
 
 thread_local std::string g_err;
 
@@ -125,14 +124,6 @@ void configure_pool_once() {
     });
 }
 
-struct Scratch {
-    void *p = nullptr;
-    hipStream_t s = nullptr;
-    ~Scratch() {
-        if (p) hipFreeAsync(p, s);
-    }
-};
-
 int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s) {
     sc.s = s;
     if (bytes == 0) return RNS_OK;
@@ -145,67 +136,22 @@ int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s) {
     return RNS_OK;
 }
 
-}  // namespace
-
-// A modulus with its device tables.
-struct rns_ctx {
-    ModPlan plan;
-    int window = 5;
-    int device = 0;
-    int engine = RNS_ENGINE_CHANNEL;
-    uint32_t *d_base = nullptr;  // shared, owned by the process-wide cache
-    uint32_t *d_mod = nullptr;
-    uint32_t *d_entry = nullptr;  // entry table for L-limb inputs (factor M^2 mod N)
-    // matrix-core engine
-    MfmaShape mshape{};
-    uint32_t *d_mbase = nullptr;  // shared, owned by the process-wide cache
-    uint32_t *d_mkey = nullptr;
-    uint32_t *d_mentry = nullptr;
-    ~rns_ctx() {
-        for (uint32_t *x : {d_mod, d_entry, d_mkey, d_mentry})
-            if (x) hipFree(x);
-    }
-};
-
-struct rns_plan {
-    ModPlan plan;
-    int window = 5;
-    int engine = RNS_ENGINE_CHANNEL;
-    MfmaTables mt;
-};
-
-struct rsa_key {
-    size_t n_limbs = 0, e_limbs = 0, half = 0;
-    rns_ctx *n = nullptr;
-    uint32_t *d_e = nullptr, *d_d = nullptr;
-    bool has_crt = false;
-    rns_ctx *p = nullptr, *q = nullptr;
-    uint32_t *d_dp = nullptr, *d_dq = nullptr;
-    uint32_t *d_centry_p = nullptr, *d_centry_q = nullptr;  // entry tables for n_limbs-limb inputs
-    uint32_t *d_mcentry_p = nullptr, *d_mcentry_q = nullptr;  // the same for the matrix-core engine
-    uint32_t *d_gentry = nullptr;                           // Garner entry table (p-modulus)
-    uint32_t *d_qlimbs = nullptr;
-    ~rsa_key() {
-        delete n;
-        delete p;
-        delete q;
-        for (uint32_t *x : {d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_mcentry_p, d_mcentry_q, d_gentry, d_qlimbs})
-            if (x) hipFree(x);
-    }
-};
+}  // namespace api
+}  // namespace rnsrsa
 
 namespace {
 
 // Engine for a plan: the matrix-core kernel when one exists for k (unless the
 // channel engine was asked for).
-int choose_engine(int K, int requested, int *engine) {
+int choose_engine(int K, int requested, int group, int *engine) {
     if (requested < 0 || requested > RNS_ENGINE_MATRIX) return fail(RNS_EINVAL, "bad engine");
+    if (group != 0 && group != 16 && group != 32) return fail(RNS_EINVAL, "group must be 0, 16 or 32");
     if (requested == RNS_ENGINE_CHANNEL) {
         *engine = RNS_ENGINE_CHANNEL;
         return RNS_OK;
     }
     MfmaShape sh;
-    if (mfma_shape_for(K, sh)) {
+    if (mfma_shape_for(K, sh, group)) {
         *engine = RNS_ENGINE_MATRIX;
         return RNS_OK;
     }
@@ -214,12 +160,12 @@ int choose_engine(int K, int requested, int *engine) {
     return RNS_OK;
 }
 
-int ctx_from_plan(ModPlan &&mp, int window, int engine_req, rns_ctx **out) {
+int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx **out) {
     std::unique_ptr<rns_ctx> c(new (std::nothrow) rns_ctx);
     if (!c) return fail(RNS_ENOMEM, "out of host memory");
     c->plan = std::move(mp);
     c->window = window;
-    int rc = choose_engine(c->plan.base->K, engine_req, &c->engine);
+    int rc = choose_engine(c->plan.base->K, engine_req, group, &c->engine);
     if (rc) return rc;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -228,7 +174,7 @@ int ctx_from_plan(ModPlan &&mp, int window, int engine_req, rns_ctx **out) {
     std::vector<uint32_t> E = make_entry_table(c->plan, {c->plan.R2}, c->plan.L);
     if ((rc = upload(E, &c->d_entry))) return rc;
     if (c->engine == RNS_ENGINE_MATRIX) {
-        mfma_shape_for(c->plan.base->K, c->mshape);
+        mfma_shape_for(c->plan.base->K, c->mshape, group);
         MfmaTables t = make_mfma_tables(c->plan, c->mshape);
         if ((rc = device_mfma_base(c->plan.base, t.base, &c->d_mbase))) return rc;
         if ((rc = upload(t.key, &c->d_mkey))) return rc;
@@ -247,6 +193,11 @@ int check_opts(const rns_opts *o) {
     return RNS_OK;
 }
 
+}  // namespace
+
+namespace rnsrsa {
+namespace api {
+
 // Launch one or two exponentiation jobs sharing the inputs.
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
@@ -263,24 +214,36 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
     P.window = c0->window;
     P.batch = (int)batch;
     if (c0->engine == RNS_ENGINE_MATRIX) {
-        Scratch table;
-        int rc = scratch_alloc(table, modexp_mfma_table_words(bs.K, c0->window, batch, njobs) * sizeof(uint32_t), s);
-        if (rc) return rc;
+        const MLayout &sh = c0->mshape;
         ModexpMfmaLaunch a{};
-        a.mb = c0->d_mbase;
-        a.mk[0] = c0->d_mkey;
-        a.mk[1] = c1 ? c1->d_mkey : c0->d_mkey;
-        a.E[0] = E0;
-        a.E[1] = E1 ? E1 : E0;
-        a.exp[0] = x0;
-        a.exp[1] = x1 ? x1 : x0;
-        a.in = in;
-        a.out[0] = out0;
-        a.out[1] = out1 ? out1 : out0;
-        a.table = (uint32_t *)table.p;
-        a.P = P;
+        const int per_job = mfma_tiles(sh, batch);
+        for (int j = 0; j < njobs; j++) {
+            const rns_ctx *c = j ? c1 : c0;
+            MJob &J = a.inl[j];
+            J.mb = c->d_mbase;
+            J.mk = c->d_mkey;
+            J.E = j ? E1 : E0;
+            J.exp = j ? x1 : x0;
+            J.in = in;
+            J.out = j ? out1 : out0;
+            J.batch = (int)batch;
+            J.in_limbs = in_limbs;
+            J.in_stride = in_limbs;
+            J.L = c->plan.L;
+            J.out_stride = out_stride;
+            J.exp_limbs = exp_limbs;
+            J.exp_stride = exp_stride;
+            J.window = c0->window;
+            J.tile0 = j * per_job;
+        }
         a.njobs = njobs;
-        hipError_t e = launch_modexp_mfma(bs.K, a, s);
+        a.tiles = per_job * njobs;
+        a.max_window = c0->window;
+        Scratch table;
+        int rc = scratch_alloc(table, modexp_mfma_table_words(sh, a.max_window, (size_t)a.tiles) * sizeof(uint32_t), s);
+        if (rc) return rc;
+        a.table = (uint32_t *)table.p;
+        hipError_t e = launch_modexp_mfma(sh, a, s);
         if (e != hipSuccess) return hip_fail(e, "modexp (matrix cores) launch");
         return RNS_OK;
     }
@@ -345,13 +308,17 @@ int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t bat
     return RNS_OK;
 }
 
+}  // namespace api
+}  // namespace rnsrsa
+
+namespace {
 }  // namespace
 
 extern "C" {
 
 const char *rns_last_error(void) { return g_err.c_str(); }
 
-int rns_abi_version(void) { return 2; }
+int rns_abi_version(void) { return 3; }
 
 int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out) {
     if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");
@@ -363,7 +330,8 @@ int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_c
         std::string err;
         rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), mp, err);
         if (rc) return fail(rc, err);
-        rc = ctx_from_plan(std::move(mp), window_or_default(opts), opts ? opts->engine : 0, out);
+        rc = ctx_from_plan(std::move(mp), window_or_default(opts), opts ? opts->engine : 0, opts ? opts->group : 0,
+                           out);
         if (rc) return rc;
     } catch (const std::bad_alloc &) {
         return fail(RNS_ENOMEM, "out of host memory");
@@ -383,7 +351,11 @@ int rns_get_info(const rns_ctx *ctx, rns_info *info) {
     info->mod_limbs = ctx->plan.L;
     info->mod_bits = (int)bn_bits(ctx->plan.N);
     info->engine = ctx->engine;
-    if (ctx->engine == RNS_ENGINE_MATRIX) info->waves = ctx->mshape.W;
+    info->group = 64;
+    if (ctx->engine == RNS_ENGINE_MATRIX) {
+        info->waves = ctx->mshape.W;
+        info->group = ctx->mshape.NM();
+    }
     return ok();
 }
 
@@ -446,6 +418,7 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
         key->half = half_limbs;
         const int window = window_or_default(opts);
         const int engine = opts ? opts->engine : 0;
+        const int group = opts ? opts->group : 0;
         std::string err;
         {
             ModPlan mp;
@@ -458,10 +431,12 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
                 rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, po, mp, err);
             }
             if (rc) return fail(rc, err);
-            if ((rc = ctx_from_plan(std::move(mp), window, engine, &key->n))) return rc;
+            if ((rc = ctx_from_plan(std::move(mp), window, engine, group, &key->n))) return rc;
         }
-        if ((rc = upload(std::vector<uint32_t>(e, e + e_limbs), &key->d_e))) return rc;
-        if (d && (rc = upload(std::vector<uint32_t>(d, d + n_limbs), &key->d_d))) return rc;
+        key->h_e.assign(e, e + e_limbs);
+        if (d) key->h_d.assign(d, d + n_limbs);
+        if ((rc = upload(key->h_e, &key->d_e))) return rc;
+        if (d && (rc = upload(key->h_d, &key->d_d))) return rc;
         if (all_crt) {
             const int L = (int)half_limbs;
             Limbs P = limbs_of(p, half_limbs), Q = limbs_of(q, half_limbs);
@@ -488,15 +463,15 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
             std::vector<uint32_t> Eg = make_entry_table(pp, {A, Bv}, L);
             std::vector<uint32_t> Epm, Eqm;
             MfmaShape msh;
-            const bool mfma = mfma_shape_for(bs->K, msh);
+            const bool mfma = mfma_shape_for(bs->K, msh, group);
             if (mfma) {
                 Epm = make_mfma_entry_table(pp, msh, Yp, L);
                 Eqm = make_mfma_entry_table(qp, msh, Yq, L);
                 Epm.resize((size_t)n_limbs * msh.ecols());
                 Eqm.resize((size_t)n_limbs * msh.ecols());
             }
-            if ((rc = ctx_from_plan(std::move(pp), window, engine, &key->p))) return rc;
-            if ((rc = ctx_from_plan(std::move(qp), window, engine, &key->q))) return rc;
+            if ((rc = ctx_from_plan(std::move(pp), window, engine, group, &key->p))) return rc;
+            if ((rc = ctx_from_plan(std::move(qp), window, engine, group, &key->q))) return rc;
             if ((rc = upload(Ep, &key->d_centry_p))) return rc;
             if ((rc = upload(Eq, &key->d_centry_q))) return rc;
             if (key->p->engine == RNS_ENGINE_MATRIX) {
@@ -504,8 +479,10 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
                 if ((rc = upload(Eqm, &key->d_mcentry_q))) return rc;
             }
             if ((rc = upload(Eg, &key->d_gentry))) return rc;
-            if ((rc = upload(std::vector<uint32_t>(dp, dp + half_limbs), &key->d_dp))) return rc;
-            if ((rc = upload(std::vector<uint32_t>(dq, dq + half_limbs), &key->d_dq))) return rc;
+            key->h_dp.assign(dp, dp + half_limbs);
+            key->h_dq.assign(dq, dq + half_limbs);
+            if ((rc = upload(key->h_dp, &key->d_dp))) return rc;
+            if ((rc = upload(key->h_dq, &key->d_dq))) return rc;
             if ((rc = upload(std::vector<uint32_t>(q, q + half_limbs), &key->d_qlimbs))) return rc;
             key->has_crt = true;
         }
@@ -593,10 +570,11 @@ int rns_plan_create(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts,
         rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), p->plan, err);
         if (rc) return fail(rc, err);
         p->window = window_or_default(opts);
-        if ((rc = choose_engine(p->plan.base->K, opts ? opts->engine : 0, &p->engine))) return rc;
+        const int group = opts ? opts->group : 0;
+        if ((rc = choose_engine(p->plan.base->K, opts ? opts->engine : 0, group, &p->engine))) return rc;
         if (p->engine == RNS_ENGINE_MATRIX) {
             MfmaShape sh;
-            mfma_shape_for(p->plan.base->K, sh);
+            mfma_shape_for(p->plan.base->K, sh, group);
             p->mt = make_mfma_tables(p->plan, sh);
         }
         *out = p.release();
@@ -616,7 +594,11 @@ int rns_plan_info(const rns_plan *plan, rns_info *info) {
     info->mod_limbs = plan->plan.L;
     info->mod_bits = (int)bn_bits(plan->plan.N);
     info->engine = plan->engine;
-    if (plan->engine == RNS_ENGINE_MATRIX) info->waves = plan->mt.shape.W;
+    info->group = 64;
+    if (plan->engine == RNS_ENGINE_MATRIX) {
+        info->waves = plan->mt.shape.W;
+        info->group = plan->mt.shape.NM();
+    }
     return ok();
 }
 

@@ -1,0 +1,100 @@
+// Internal interface shared by the C ABI translation units (capi.cpp,
+// batch.cpp): error reporting, device uploads, stream-ordered scratch, and
+// the objects behind the opaque handles of include/rnsrsa.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "plan_mfma.hpp"
+#include "rnsrsa.h"
+
+namespace rnsrsa {
+namespace api {
+
+int fail(int code, const std::string &msg);   // records msg for rns_last_error, returns code
+int ok();
+int hip_fail(hipError_t e, const char *what);
+int upload(const std::vector<uint32_t> &v, uint32_t **out);
+
+// A stream-ordered device allocation released (stream-ordered) on destruction.
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~Scratch() {
+        if (p) hipFreeAsync(p, s);
+    }
+};
+int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s);
+
+}  // namespace api
+}  // namespace rnsrsa
+
+// A modulus with its device tables.
+struct rns_ctx {
+    rnsrsa::ModPlan plan;
+    int window = 5;
+    int device = 0;
+    int engine = RNS_ENGINE_CHANNEL;
+    uint32_t *d_base = nullptr;  // shared, owned by the process-wide cache
+    uint32_t *d_mod = nullptr;
+    uint32_t *d_entry = nullptr;  // entry table for L-limb inputs (factor M^2 mod N)
+    // matrix-core engine
+    rnsrsa::MfmaShape mshape{};
+    uint32_t *d_mbase = nullptr;  // shared, owned by the process-wide cache
+    uint32_t *d_mkey = nullptr;
+    uint32_t *d_mentry = nullptr;
+    ~rns_ctx() {
+        for (uint32_t *x : {d_mod, d_entry, d_mkey, d_mentry})
+            if (x) hipFree(x);
+    }
+};
+
+struct rns_plan {
+    rnsrsa::ModPlan plan;
+    int window = 5;
+    int engine = RNS_ENGINE_CHANNEL;
+    rnsrsa::MfmaTables mt;
+};
+
+struct rsa_key {
+    size_t n_limbs = 0, e_limbs = 0, half = 0;
+    std::vector<uint32_t> h_e, h_dp, h_dq, h_d;   // host copies of the exponents
+    rns_ctx *n = nullptr;
+    uint32_t *d_e = nullptr, *d_d = nullptr;
+    bool has_crt = false;
+    rns_ctx *p = nullptr, *q = nullptr;
+    uint32_t *d_dp = nullptr, *d_dq = nullptr;
+    uint32_t *d_centry_p = nullptr, *d_centry_q = nullptr;  // entry tables for n_limbs-limb inputs
+    uint32_t *d_mcentry_p = nullptr, *d_mcentry_q = nullptr;  // the same for the matrix-core engine
+    uint32_t *d_gentry = nullptr;                           // Garner entry table (p-modulus)
+    uint32_t *d_qlimbs = nullptr;
+    ~rsa_key() {
+        delete n;
+        delete p;
+        delete q;
+        for (uint32_t *x : {d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_mcentry_p, d_mcentry_q, d_gentry, d_qlimbs})
+            if (x) hipFree(x);
+    }
+};
+
+
+namespace rnsrsa {
+namespace api {
+
+// Entry table of a context for its own L-limb inputs.
+const uint32_t *entry_of(const rns_ctx *c);
+// Garner recombination of [m_p | m_q] rows into m (n_limbs limbs).
+int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s);
+// One or two exponentiation jobs sharing their inputs (the plain launch).
+int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
+               int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
+               uint32_t *out1, int out_stride, size_t batch, hipStream_t s);
+
+}  // namespace api
+}  // namespace rnsrsa

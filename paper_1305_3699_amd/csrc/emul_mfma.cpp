@@ -60,13 +60,10 @@ struct MSt {
     std::vector<uint32_t> r;     // [NM]
 };
 
-uint32_t pack_digits(uint32_t v, uint32_t m) {
-    const uint32_t c = v >= kDigitSplit ? v - m : v;
-    return (c + 0x80808080u) ^ 0x80808080u;
-}
+uint32_t pack_digits(uint32_t v) { return v ^ kDigitBias; }
 
 uint32_t reduce_signed(int64_t S, uint32_t m, uint32_t u) {
-    const uint64_t x = (uint64_t)(S + ((int64_t)m << 16));
+    const uint64_t x = (uint64_t)(S + ((int64_t)m << 17));
     return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
 }
 
@@ -96,7 +93,7 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
             for (int e = 0; e < NM; e++) {
                 const uint32_t t = mulredc(x.b[idx(w, s, e)], y.b[idx(w, s, e)], m, u);
                 const uint32_t xi = mulredc(t, ci, m, u);
-                if (c.real(w, s)) dig1[(size_t)e * BROW + c.channel(w, s)] = pack_digits(xi, m);
+                if (c.real(w, s)) dig1[(size_t)e * BROW + c.channel(w, s)] = pack_digits(xi);
                 a1[idx(w, s, e)] = mulredc(x.p[idx(w, s, e)], y.p[idx(w, s, e)], mp, up);
             }
         }
@@ -116,7 +113,7 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
                 const uint64_t sum = (uint64_t)a1[idx(w, s, e)] + q;
                 const uint32_t r = (uint32_t)(sum >= m ? sum - m : sum);
                 x.p[idx(w, s, e)] = r;
-                if (c.real(w, s)) dig2[(size_t)e * BROW + c.channel(w, s)] = pack_digits(mulredc(r, H, m, u), m);
+                if (c.real(w, s)) dig2[(size_t)e * BROW + c.channel(w, s)] = pack_digits(mulredc(r, H, m, u));
             }
         }
     for (int e = 0; e < NM; e++) x.r[e] = rr[e];
@@ -250,9 +247,7 @@ void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
             std::vector<uint32_t> X(K), acc(L + 1), tmp(L + 1);
             uint32_t s2 = 0;
             for (int j = 0; j < K; j++) {
-                uint32_t v = (dig2[(size_t)e * BROW + j] ^ 0x80808080u) - 0x80808080u;
-                const uint32_t mj = T.base[ly.mpj() + j];
-                v = v >= kDigitSplit ? v + mj : v;     // centred range reaches below -2^31
+                const uint32_t v = dig2[(size_t)e * BROW + j] ^ kDigitBias;
                 X[j] = v;
                 s2 += v * T.base[ly.mplo() + j];
             }

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "mfma_layout.hpp"
+
 namespace rnsrsa {
 
 // Parameters shared by the two exponentiation jobs of one launch.
@@ -59,24 +61,36 @@ struct MontMulLaunch {
     int batch;
 };
 
-// Matrix-core variant of ModexpLaunch: mb is the key-independent table, mk[j]
-// the per-modulus table of job j (plan_mfma.hpp), E[j] its entry table.
+// One exponentiation job of the matrix-core kernel: `batch` elements
+// out[i] = in[i]^exp mod N with the tables of one modulus: mb the
+// key-independent table and mk the per-modulus table (plan_mfma.hpp), E the
+// entry table of in_limbs rows.  tile0 is the job's first tile (group of
+// 16*NT elements) in its launch.
+struct MJob {
+    const uint32_t *mb, *mk, *E, *exp, *in;
+    uint32_t *out;
+    int batch, in_limbs, in_stride, L, out_stride, exp_limbs, exp_stride, window;
+    int tile0;
+    int unused;
+};
+
+// A launch of the matrix-core kernel: njobs jobs of one shape, from the
+// device array `jobs` or, when it is null, from inl (at most 2 jobs).
 struct ModexpMfmaLaunch {
-    const uint32_t *mb;
-    const uint32_t *mk[2];
-    const uint32_t *E[2];
-    const uint32_t *exp[2];
-    const uint32_t *in;
-    uint32_t *out[2];
-    uint32_t *table;  // scratch, modexp_mfma_table_words(...) words
-    ModexpParams P;
+    MJob inl[2];
+    const MJob *jobs;
     int njobs;
+    int tiles;           // total tiles of all jobs = workgroups launched
+    int max_window;      // window table slots hold 2^max_window entries
+    uint32_t *table;     // scratch: modexp_mfma_table_words(shape, max_window, tiles) words
 };
 
 size_t modexp_table_words(int K, int W, int window, size_t workgroups);
-size_t modexp_mfma_table_words(int K, int window, size_t elements, int njobs);
+size_t modexp_mfma_table_words(const MLayout &shape, int max_window, size_t workgroups);
+int mfma_tiles(const MLayout &shape, size_t elements);
 bool mfma_supported(int K);
-hipError_t launch_modexp_mfma(int K, const ModexpMfmaLaunch &a, hipStream_t s);
+int mfma_blocks_per_cu(const MLayout &shape);
+hipError_t launch_modexp_mfma(const MLayout &shape, const ModexpMfmaLaunch &a, hipStream_t s);
 hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s);
 hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s);
 hipError_t launch_montmul(int K, int W, const MontMulLaunch &a, hipStream_t s);

@@ -21,8 +21,11 @@ hipError_t launch_montmul_t(const MontMulLaunch &a, hipStream_t s);
 
 template <int K, int W, int MT, int NT>
 hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s);
+template <int K, int W, int MT, int NT>
+int mfma_blocks_per_cu_t();
 #define RNSRSA_MSHAPE(k, w, mt, nt) \
-    extern template hipError_t launch_modexp_mfma_t<k, w, mt, nt>(const ModexpMfmaLaunch &, hipStream_t);
+    extern template hipError_t launch_modexp_mfma_t<k, w, mt, nt>(const ModexpMfmaLaunch &, hipStream_t); \
+    extern template int mfma_blocks_per_cu_t<k, w, mt, nt>();
 #include "kernel_configs_mfma.inc"
 #undef RNSRSA_MSHAPE
 
@@ -34,21 +37,23 @@ bool mfma_supported(int K) {
     return false;
 }
 
-size_t modexp_mfma_table_words(int K, int window, size_t elements, int njobs) {
-#define RNSRSA_MSHAPE(k, w, mt, nt)                                                                 \
-    if (K == k) {                                                                                   \
-        constexpr MLayout ly{k, w, mt, nt};                                                          \
-        const size_t wgs = (elements + ly.NM() - 1) / ly.NM() * (size_t)njobs;                       \
-        return wgs * ((size_t)1 << window) * (size_t)w * ly.SLOTS() * 64;                            \
-    }
+size_t modexp_mfma_table_words(const MLayout &s, int max_window, size_t workgroups) {
+    return workgroups * ((size_t)1 << max_window) * (size_t)s.W * s.SLOTS() * 64;
+}
+
+int mfma_tiles(const MLayout &s, size_t elements) { return (int)((elements + s.NM() - 1) / s.NM()); }
+
+int mfma_blocks_per_cu(const MLayout &sh) {
+#define RNSRSA_MSHAPE(k, w, mt, nt) \
+    if (sh.K == k && sh.W == w && sh.MT == mt && sh.NT == nt) return mfma_blocks_per_cu_t<k, w, mt, nt>();
 #include "kernel_configs_mfma.inc"
 #undef RNSRSA_MSHAPE
     return 0;
 }
 
-hipError_t launch_modexp_mfma(int K, const ModexpMfmaLaunch &a, hipStream_t s) {
+hipError_t launch_modexp_mfma(const MLayout &sh, const ModexpMfmaLaunch &a, hipStream_t s) {
 #define RNSRSA_MSHAPE(k, w, mt, nt) \
-    if (K == k) return launch_modexp_mfma_t<k, w, mt, nt>(a, s);
+    if (sh.K == k && sh.W == w && sh.MT == mt && sh.NT == nt) return launch_modexp_mfma_t<k, w, mt, nt>(a, s);
 #include "kernel_configs_mfma.inc"
 #undef RNSRSA_MSHAPE
     return hipErrorInvalidValue;

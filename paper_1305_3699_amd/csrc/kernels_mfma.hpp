@@ -3,14 +3,14 @@
 // Same algorithm as kernels_impl.hpp (RNS Montgomery products with two base
 // extensions, fixed-window exponent loop, CRT exit), but both base extensions
 // run on the int8 matrix cores: each quotient digit xi (a residue below 2^32)
-// is centred and split into four signed bytes, and each extension is the
-// product of a constant A matrix (rows = 4 bytes of each output channel,
-// columns = 4 digits of each input channel, constants pre-multiplied by
-// 2^(8 digit)) with the digit matrix B (columns = elements), accumulated
-// exactly in int32 by v_mfma_i32_16x16x64_i8.  One extra column adds the
-// centring offset c*M; one extra row per wave computes the redundant 2^32
-// channel.  The four byte partials of an output are recombined to a signed
-// 64-bit integer and reduced by one REDC.
+// is handed over as xi ^ 0x80808080, i.e. as the four signed bytes of
+// xi - 0x80808080, and each extension is the product of a constant A matrix
+// (rows = 4 bytes of each output channel, columns = 4 digits of each input
+// channel, constants pre-multiplied by 2^(8 digit)) with the digit matrix B
+// (columns = elements), accumulated exactly in int32 by
+// v_mfma_i32_16x16x64_i8.  One extra column cancels the digit bias; one extra
+// row per wave computes the redundant 2^32 channel.  The four byte partials of
+// an output are recombined to a signed 64-bit integer and reduced by one REDC.
 //
 // Layout (plan_mfma.hpp): W waves serve 16*NT elements; lane l of a wave
 // owns slot 4*mt + l/16 of tile mt for elements 16*nt + l%16, which is
@@ -63,11 +63,8 @@ struct MConst {
     uint32_t Mpinv_r, Minv_r, N_r;
 };
 
-// balanced four-byte digits of a residue of m, packed as signed bytes
-__device__ __forceinline__ uint32_t mfma_pack(uint32_t v, uint32_t m) {
-    const uint32_t c = v >= kDigitSplit ? v - m : v;     // centred, as a 32-bit two's complement value
-    return (c + 0x80808080u) ^ 0x80808080u;
-}
+// digit word of a residue: its bytes, read as signed int8, are those of v - kDigitBias
+__device__ __forceinline__ uint32_t mfma_pack(uint32_t v) { return v ^ kDigitBias; }
 
 // signed 64-bit value of the four byte partials of one output
 __device__ __forceinline__ int64_t mfma_combine(const mfma_v4i &d) {
@@ -76,9 +73,11 @@ __device__ __forceinline__ int64_t mfma_combine(const mfma_v4i &d) {
     return (int64_t)t1 + ((int64_t)t2 << 16);
 }
 
-// (S + off) * 2^-32 mod m for |S| < 2^47, off = m * 2^16 keeps it positive.
+// S * 2^-32 mod m for |S| < 2^48 (at most 4*129+1 terms of |A| <= 0x80808080
+// times |digit byte| <= 128, plus alpha * nu < 2^40): adding m * 2^17 makes
+// the REDC input positive and keeps it below m * 2^32.
 __device__ __forceinline__ uint32_t mfma_reduce(int64_t S, uint32_t m, uint32_t u) {
-    const uint64_t x = (uint64_t)(S + ((int64_t)m << 16));
+    const uint64_t x = (uint64_t)(S + ((int64_t)m << 17));
     return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
 }
 
@@ -104,17 +103,14 @@ __device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, N
     }
 }
 
-// One RNS Montgomery product x <- x*y*M^-1 in the matrix-core layout.  With
-// full == false the second extension is skipped (the caller leaves the RNS
-// from the xi' digits in buf2).  Returns nothing; x.r holds the new redundant
-// residue.
+// Step (i) of a product: quotient digits xi = x y c_i of the B slots,
+// published as the B operand of the first extension.
 template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C, MState<MT, NT> &x,
-                                        const MState<MT, NT> &y, uint32_t *buf1, uint32_t *buf2, int wave, int lane,
-                                        bool full) {
+__device__ __forceinline__ void mfma_publish_xi(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C,
+                                                const MState<MT, NT> &x, const MState<MT, NT> &y, uint32_t *buf1,
+                                                int wave, int lane) {
     using S = MShp<K, W, MT, NT>;
     const int g = lane >> 4;
-    // (i) quotient digits of B, published as the B operand of the first extension
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
         const int ch = wave * S::CH + 4 * mt + g;
@@ -123,9 +119,28 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
         for (int nt = 0; nt < NT; nt++) {
             const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], C.mB[mt], C.uB[mt]);   // x y 2^32
             const uint32_t xi = mulredc(t, C.cB[mt], C.mB[mt], C.uB[mt]);              // x y c_i
-            if (real) buf1[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xi, C.mB[mt]);
+            if (real) buf1[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xi);
         }
     }
+}
+
+// One RNS Montgomery product x <- x*y*M^-1 in the matrix-core layout.  With
+// full == false the second extension is skipped (the caller leaves the RNS
+// from the xi' digits in buf2).  x.r receives the new redundant residue.
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C, MState<MT, NT> &x,
+                                        const MState<MT, NT> &y, uint32_t *buf1, uint32_t *buf2, int wave, int lane,
+                                        bool full) {
+    using S = MShp<K, W, MT, NT>;
+    const int g = lane >> 4;
+    mfma_publish_xi<K, W, MT, NT>(C, x, y, buf1, wave, lane);
+    __syncthreads();
+
+    // (ii) first extension on the matrix cores: q^'' N M^-1 (scaled) in each B'
+    // slot; the B' and redundant products below do not depend on it and can
+    // issue while the matrix cores run
+    mfma_v4i D[MT][NT];
+    mfma_extension<K, W, MT, NT>(C, false, buf1, lane, D);
     uint32_t a1[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
@@ -134,11 +149,6 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
     uint32_t sr[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) sr[nt] = x.r[nt] * y.r[nt];
-    __syncthreads();
-
-    // (ii) first extension on the matrix cores: q^'' N M^-1 (scaled) in each B' slot
-    mfma_v4i D[MT][NT];
-    mfma_extension<K, W, MT, NT>(C, false, buf1, lane, D);
     const int rsrc = ((lane & 15) + 48) * 4;
     uint32_t rr[NT];
 #pragma unroll
@@ -161,7 +171,7 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
             r = (ov || r >= m) ? r - m : r;
             x.p[mt][nt] = r;
             const uint32_t xip = mulredc(r, C.HP[mt], m, C.uP[mt]);                     // r (M'_t)^-1
-            if (real) buf2[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xip, m);
+            if (real) buf2[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xip);
         }
     }
 #pragma unroll
@@ -213,6 +223,25 @@ __device__ __forceinline__ void mstate_load(const uint32_t *__restrict__ p, MSta
     for (int nt = 0; nt < NT; nt++) a.r[nt] = p[(2 * MT * NT + nt) * 64];
 }
 
+// y = 1 in the kept representation: 2^32 mod m in B, 2^32 M^-1 mod m' in B'
+// (read from the table when needed rather than held in registers).
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ void mstate_unit(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C,
+                                            const uint32_t *__restrict__ mb, int wave, int lane, MState<MT, NT> &y) {
+    using S = MShp<K, W, MT, NT>;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const uint32_t kap = mb[S::LY.slotP() + (((size_t)wave * MT + mt) * 4 + 3) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            y.b[mt][nt] = 0u - C.mB[mt];
+            y.p[mt][nt] = kap;
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) y.r[nt] = 1u;
+}
+
 __device__ __forceinline__ uint32_t mexp_digit(const uint32_t *__restrict__ e, int nlimbs, int nd, int w, int di) {
     const int lo = (nd - 1 - di) * w;
     const int limb = lo >> 5, sh = lo & 31;
@@ -221,25 +250,20 @@ __device__ __forceinline__ uint32_t mexp_digit(const uint32_t *__restrict__ e, i
     return (uint32_t)(v >> sh) & ((1u << w) - 1u);
 }
 
-// Exponentiation kernel, matrix-core variant.  Same contract as
-// modexp_kernel (kernels_impl.hpp); bc / mc are the channel tables of that
-// kernel (used to leave the RNS), mb / mk the matrix-core tables.
+// One tile (16*NT elements) of exponentiation job J, elements
+// [e0, e0 + 16*NT) of the job, with window table slot `slot` of the launch.
 template <int K, int W, int MT, int NT>
-__global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
-    const uint32_t *__restrict__ mb, const uint32_t *__restrict__ mk0, const uint32_t *__restrict__ mk1,
-    const uint32_t *__restrict__ E0, const uint32_t *__restrict__ E1, const uint32_t *__restrict__ ex0,
-    const uint32_t *__restrict__ ex1, const uint32_t *__restrict__ in, uint32_t *__restrict__ out0,
-    uint32_t *__restrict__ out1, uint32_t *__restrict__ table, ModexpParams P) {
+__device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t *__restrict__ lds,
+                                                 uint32_t *__restrict__ table, size_t slot, int max_window) {
     using S = MShp<K, W, MT, NT>;
-    __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
     uint32_t *buf1 = lds;
     uint32_t *buf2 = lds + S::NM * S::BROW;
-
-    const int job = blockIdx.y;
-    const uint32_t *__restrict__ mk = job ? mk1 : mk0;
-    const uint32_t *__restrict__ E = job ? E1 : E0;
-    const uint32_t *__restrict__ ex = job ? ex1 : ex0;
-    uint32_t *__restrict__ out = job ? out1 : out0;
+    const uint32_t *__restrict__ mb = J.mb;
+    const uint32_t *__restrict__ mk = J.mk;
+    const uint32_t *__restrict__ E = J.E;
+    const uint32_t *__restrict__ ex = J.exp;
+    const uint32_t *__restrict__ in = J.in;
+    uint32_t *__restrict__ out = J.out;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
@@ -265,11 +289,12 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
         }
         C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
         C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
-        C.nuB[mt] = mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
         C.mP[mt] = mb[S::LY.slotP() + (sl * 4 + 0) * 64 + lane];
         C.uP[mt] = mb[S::LY.slotP() + (sl * 4 + 1) * 64 + lane];
+        C.nuB[mt] = mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
         C.HP[mt] = mb[S::LY.slotP() + (sl * 4 + 2) * 64 + lane];
         C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
+
     }
     C.Mpinv_r = mb[S::LY.bscal() + 0];
     C.Minv_r = mb[S::LY.bscal() + 1];
@@ -283,16 +308,16 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
         int msg[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            msg[nt] = blockIdx.x * S::NM + 16 * nt + (lane & 15);
+            msg[nt] = e0 + 16 * nt + (lane & 15);
             zr[nt] = 0;
         }
         const int colB = wave * 4 * MT + g, colP = W * 4 * MT + wave * 4 * MT + g;
-        for (int l = 0; l < P.in_limbs; l++) {
+        for (int l = 0; l < J.in_limbs; l++) {
             const uint32_t *__restrict__ row = E + (size_t)l * S::ECOLS;
             uint32_t v[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; nt++)
-                v[nt] = msg[nt] < P.batch ? in[(size_t)msg[nt] * P.in_stride + l] : 0u;
+                v[nt] = msg[nt] < J.batch ? in[(size_t)msg[nt] * J.in_stride + l] : 0u;
             const uint32_t er = row[S::ECOLS - 1];
 #pragma unroll
             for (int mt = 0; mt < MT; mt++) {
@@ -316,25 +341,10 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) a.r[nt] = zr[nt];
     }
-    // y = 1 in the kept representation: 2^32 mod m in B, 2^32 M^-1 mod m' in B'
-    MState<MT, NT> unit;
-#pragma unroll
-    for (int mt = 0; mt < MT; mt++) {
-        const uint32_t kap = mb[S::LY.slotP() + (((size_t)wave * MT + mt) * 4 + 3) * 64 + lane];
-#pragma unroll
-        for (int nt = 0; nt < NT; nt++) {
-            unit.b[mt][nt] = 0u - C.mB[mt];
-            unit.p[mt][nt] = kap;
-        }
-    }
-#pragma unroll
-    for (int nt = 0; nt < NT; nt++) unit.r[nt] = 1u;
-
-    const int w = P.window;
+    const int w = J.window;
     const int T = 1 << w;
-    const size_t wg = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     const size_t estride = (size_t)W * S::SLOTS * 64;
-    uint32_t *__restrict__ tw = table + (wg * T * W + wave) * (size_t)(S::SLOTS * 64) + lane;
+    uint32_t *__restrict__ tw = table + ((slot << max_window) * W + wave) * (size_t)(S::SLOTS * 64) + lane;
     {
         MState<MT, NT> one;
 #pragma unroll
@@ -352,11 +362,11 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
         mstate_store<MT, NT>(tw, one);   // T[0] = M mod N
     }
 
-    const int nd = (32 * P.exp_limbs + w - 1) / w;
-    const bool shared_exp = P.exp_stride == 0;
+    const int nd = (32 * J.exp_limbs + w - 1) / w;
+    const bool shared_exp = J.exp_stride == 0;
     enum { ENTRY, BUILD, MAIN, EXIT };
     int phase = ENTRY, j = 2, di = 0, s = 0;
-    y = unit;
+    mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
     for (;;) {
         mfma_mm<K, W, MT, NT>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
         if (phase == EXIT) break;
@@ -377,7 +387,7 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
             if (shared_exp) {
                 uint32_t d = 0;
                 while (di < nd) {
-                    d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, P.exp_limbs, nd, w, di));
+                    d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, J.exp_limbs, nd, w, di));
                     if (d) break;
                     di++;
                 }
@@ -394,7 +404,7 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
         for (;;) {
             if (di >= nd) {
                 phase = EXIT;
-                y = unit;
+                mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
                 break;
             }
             if (s < w) {
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
             di++;
             s = 0;
             if (shared_exp) {
-                const uint32_t d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, P.exp_limbs, nd, w, di - 1));
+                const uint32_t d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, J.exp_limbs, nd, w, di - 1));
                 if (d != 0) {
                     mstate_load<MT, NT>(tw + (size_t)d * estride, y);
                     break;
@@ -415,9 +425,9 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
                 MState<MT, NT> t;
 #pragma unroll
                 for (int nt = 0; nt < NT; nt++) {
-                    const int m = blockIdx.x * S::NM + 16 * nt + (lane & 15);
-                    const uint32_t *__restrict__ ep = ex + (size_t)(m < P.batch ? m : 0) * P.exp_stride;
-                    const uint32_t d = mexp_digit(ep, P.exp_limbs, nd, w, di - 1);
+                    const int m = e0 + 16 * nt + (lane & 15);
+                    const uint32_t *__restrict__ ep = ex + (size_t)(m < J.batch ? m : 0) * J.exp_stride;
+                    const uint32_t d = mexp_digit(ep, J.exp_limbs, nd, w, di - 1);
                     const uint32_t *__restrict__ pe = tw + (size_t)d * estride;
 #pragma unroll
                     for (int mt = 0; mt < MT; mt++) {
@@ -436,21 +446,18 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
     __syncthreads();
     if (wave != 0 || lane >= S::NM) return;
     const int n = lane;
-    const int msg = blockIdx.x * S::NM + n;
+    const int msg = e0 + n;
     uint32_t rr = a.r[0];
 #pragma unroll
     for (int nt = 1; nt < NT; nt++) rr = (n >> 4) == nt ? a.r[nt] : rr;   // lane n holds element n's r in slot n/16
-    const int L = P.L;
+    const int L = J.L;
     constexpr int NM = S::NM;
     uint32_t *X = lds;                               // [K][NM] xi'_j of the exit product
     uint32_t *acc = lds + K * NM;                    // [L+1][NM]
     uint32_t *tmp = acc + (L + 1) * NM;              // [L+1][NM]
     uint32_t s2 = 0;
     for (int jj = 0; jj < K; jj++) {
-        const uint32_t packed = buf2[n * S::BROW + jj];
-        uint32_t v = (packed ^ 0x80808080u) - 0x80808080u;           // centred digit mod 2^32
-        const uint32_t mj = mb[S::LY.mpj() + jj];
-        v = v >= kDigitSplit ? v + mj : v;                            // back to [0, m'_j)
+        const uint32_t v = buf2[n * S::BROW + jj] ^ kDigitBias;       // xi'_j in [0, m'_j)
         X[jj * NM + n] = v;
         s2 += v * mb[S::LY.mplo() + jj];
     }
@@ -494,17 +501,49 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(
         if (!borrow)
             for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
     }
-    if (msg < P.batch)
-        for (int l = 0; l < L; l++) out[(size_t)msg * P.out_stride + l] = acc[l * NM + n];
+    if (msg < J.batch)
+        for (int l = 0; l < L; l++) out[(size_t)msg * J.out_stride + l] = acc[l * NM + n];
+}
+
+// Exponentiation kernel, matrix-core variant: workgroup t runs tile t of the
+// A.njobs jobs of one shape, which belongs to the job j with
+// jobs[j].tile0 <= t < jobs[j+1].tile0.  (A resident loop that takes tiles
+// from a counter costs 15-35 more VGPRs per lane here, as the compiler keeps
+// the per-lane addresses of the tile body live across it; the hardware
+// dispatcher refills the CUs as workgroups finish instead.)
+template <int K, int W, int MT, int NT>
+__global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A) {
+    using S = MShp<K, W, MT, NT>;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
+    const int tile = blockIdx.x;
+    MJob J;
+    if (A.jobs) {
+        int lo = 0, hi = A.njobs - 1;          // last job with tile0 <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.jobs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+        }
+        J = A.jobs[lo];
+    } else {
+        J = (A.njobs > 1 && tile >= A.inl[1].tile0) ? A.inl[1] : A.inl[0];
+    }
+    modexp_mfma_tile<K, W, MT, NT>(J, (tile - J.tile0) * S::NM, lds, A.table, blockIdx.x, A.max_window);
 }
 
 template <int K, int W, int MT, int NT>
 hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s) {
-    const unsigned gx = (unsigned)((a.P.batch + 16 * NT - 1) / (16 * NT));
-    hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT>), dim3(gx, (unsigned)a.njobs), dim3(64 * W), 0, s, a.mb,
-                       a.mk[0], a.mk[1], a.E[0], a.E[1], a.exp[0], a.exp[1], a.in, a.out[0], a.out[1], a.table,
-                       a.P);
+    if (a.tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT>), dim3((unsigned)a.tiles), dim3(64 * W), 0, s, a);
     return hipGetLastError();
+}
+
+// Resident workgroups per CU of the kernel for this shape (occupancy).
+template <int K, int W, int MT, int NT>
+int mfma_blocks_per_cu_t() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, modexp_mfma_kernel<K, W, MT, NT>, 64 * W, 0) != hipSuccess)
+        return 0;
+    return n;
 }
 
 }  // namespace rnsrsa

@@ -9,12 +9,16 @@
 
 namespace rnsrsa {
 
-// Balanced-digit threshold: a residue v >= kDigitSplit of m is stored as the
-// negative value v - m, so that every stored value lies in
-// [kDigitSplit - m, kDigitSplit), inside the range of four signed bytes
-// [-0x80808080, 0x7F7F7F7F].  For m > 2^31 + kDigitSplit that range reaches
-// below -2^31: a stored value is negative exactly when its 32-bit pattern is
-// >= kDigitSplit, never by its int32 sign.
+// Digit bias: a residue v in [0, 2^32) is handed to the matrix core as the
+// word v ^ kDigitBias, whose four bytes read as signed int8 are the balanced
+// digits of v - kDigitBias (each byte b becomes b - 128).  The constant
+// -kDigitBias * sum(C_i) this adds to an extension is cancelled by the offset
+// column of the constant matrix.
+constexpr uint32_t kDigitBias = 0x80808080u;
+
+// Constants of the A matrices are stored balanced: the representative of a
+// residue in [kDigitSplit - m, kDigitSplit), inside [-0x80808080, 0x7F7F7F7F],
+// the range of four signed bytes.
 constexpr uint32_t kDigitSplit = 0x7F7F7F80u;
 
 struct MLayout {

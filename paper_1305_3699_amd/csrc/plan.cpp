@@ -137,12 +137,10 @@ static std::shared_ptr<BaseSet> build_base(int K, int W, const std::vector<uint3
 }
 
 bool bounds_hold(const BaseSet &bs, const Limbs &N, int L) {
-    // (K+2) rather than (K+1): the matrix-core kernel's centred digits put the
-    // first extension's value in [0, (K+1)M), so its values stay below (K+2)N.
-    Limbs k2 = bn_from_u64((uint64_t)bs.K + 2);
-    if (bn_cmp(bn_mul(bn_mul(k2, k2), N), bs.M) > 0) return false;        // M >= (K+2)^2 N
+    Limbs k1 = bn_from_u64((uint64_t)bs.K + 1);
+    if (bn_cmp(bn_mul(bn_mul(k1, k1), N), bs.M) > 0) return false;        // M >= (K+1)^2 N
     if (bn_cmp(bn_shl(Limbs{1}, 32u * L + 1), bs.M) > 0) return false;    // M >= 2^(32L+1)
-    if (bn_cmp(bn_mul(k2, N), bs.Mp) > 0) return false;                   // M' >= (K+2) N
+    if (bn_cmp(bn_mul(k1, N), bs.Mp) > 0) return false;                   // M' >= (K+1) N
     for (uint32_t m : bs.B)
         if (bn_mod_word(N, m) == 0) return false;
     return true;

@@ -1,18 +1,20 @@
 // Host-side tables of the matrix-core exponentiation kernel (plan_mfma.hpp).
 #include "plan_mfma.hpp"
 
-#include <cmath>
 
 namespace rnsrsa {
 
-bool mfma_shape_for(int K, MfmaShape &out) {
-#define RNSRSA_MSHAPE(k, w, mt, nt) \
-    if (K == k) {                   \
-        out = MfmaShape{k, w, mt, nt}; \
-        return true;                \
+bool mfma_shape_for(int K, MfmaShape &out, int group) {
+    // the first shape listed for K with the preferred group, else the first for K
+    for (int pass = group ? 0 : 1; pass < 2; pass++) {
+#define RNSRSA_MSHAPE(k, w, mt, nt)                                    \
+    if (K == k && (pass == 1 || group == 16 * (nt))) {               \
+        out = MfmaShape{k, w, mt, nt};                                 \
+        return true;                                                   \
     }
 #include "kernel_configs_mfma.inc"
 #undef RNSRSA_MSHAPE
+    }
     return false;
 }
 
@@ -28,15 +30,6 @@ int64_t balanced32(uint32_t v) { return v > 0x7F7F7F7Fu ? (int64_t)v - ((int64_t
 int8_t digit(int64_t V, int b) {
     uint32_t u = (uint32_t)(V + 0x80808080ll);
     return (int8_t)((int)((u >> (8 * b)) & 0xFFu) - 128);
-}
-
-// c = ceil(sum_i max(0, 1 - T/m_i)): offset (in multiples of the base product)
-// that makes the extension of centred digits non-negative.
-uint32_t centring_offset(const std::vector<uint32_t> &ms) {
-    double s = 0;
-    for (uint32_t m : ms)
-        if (m > kDigitSplit) s += 1.0 - (double)kDigitSplit / (double)m;
-    return (uint32_t)std::ceil(s);
 }
 
 uint32_t pow2_mod(uint32_t e, uint32_t m) { return powmod32(2, e, m); }
@@ -84,8 +77,6 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
     out.base.assign(ly.base_size(), 0);
     out.key.assign(ly.key_size(), 0);
     const Limbs &N = mp.N;
-    const uint32_t c1 = centring_offset(bs.B), c2 = centring_offset(bs.Bp);
-    const uint32_t Mlo = bn_low(bs.M), Mplo = bn_low(bs.Mp);
 
     // residues of M_i = M / m_i and M'_j = M' / m'_j modulo other moduli
     auto Mi_mod = [&](int i, uint32_t m) { return mulmod32(prod_mod32(bs.B, m), invmod32(bs.B[i] % m, m), m); };
@@ -103,34 +94,44 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
         return w;
     };
 
-    // BE1 (key table): slot t of B' gets q^'' * G_t with G_t = N R^2 M^-2 mod m'_t,
-    // so that one REDC of the extension yields q^'' N M^-1 * (R M^-1).
+    // The digit words carry xi - kDigitBias; the offset column (input channel K,
+    // digit value 1) adds kDigitBias * sum_i C_i back, so each extension is the
+    // exact integer sum_i xi_i C_i.
+    //
+    // BE1 (key table): slot t of B' gets sum_i xi_i M_i * G_t with
+    // G_t = N R^2 M^-2 mod m'_t, so that one REDC yields q N M^-1 * (R M^-1);
+    // the redundant row gets sum_i xi_i M_i mod 2^32.
     std::vector<uint32_t> G(K);
     for (int t = 0; t < K; t++) {
         uint32_t m = bs.Bp[t];
         uint32_t minv = invmod32(prod_mod32(bs.B, m), m);
         G[t] = mulmod32(mulmod32(bn_mod_word(N, m), pow2_64_mod(m), m), mulmod32(minv, minv, m), m);
     }
+    uint32_t sumMi_lo = 0, sumMpj_lo = 0;
+    for (int i = 0; i < K; i++) {
+        sumMi_lo += Mi_lo(i);
+        sumMpj_lo += Mpj_lo(i);
+    }
+    auto sum_mod = [&](auto f, uint32_t m) {
+        uint64_t s = 0;
+        for (int i = 0; i < K; i++) s = (s + f(i, m)) % m;
+        return (uint32_t)s;
+    };
     fill_tiles(sh, out.key.data() + ly.a1(), [&](int t, int i, int a) -> int64_t {
-        if (t < 0) {
-            uint32_t v = i < K ? Mi_lo(i) << (8 * a) : c1 * Mlo;
-            return balanced32(v);
-        }
+        if (t < 0) return balanced32(i < K ? Mi_lo(i) << (8 * a) : kDigitBias * sumMi_lo);
         uint32_t m = bs.Bp[t];
-        uint32_t v = i < K ? mulmod32(mulmod32(Mi_mod(i, m), G[t], m), pow2_mod(8 * a, m), m)
-                           : mulmod32(mulmod32(bn_mod_word(bs.M, m), G[t], m), c1 % m, m);
-        return balanced(v, m);
+        uint32_t v = i < K ? mulmod32(Mi_mod(i, m), pow2_mod(8 * a, m), m)
+                           : mulmod32(kDigitBias % m, sum_mod(Mi_mod, m), m);
+        return balanced(mulmod32(v, G[t], m), m);
     });
-    // BE2 (base table): slot i of B gets (sum xi'_j M'_j + c2 M') R^2 mod m_i.
+    // BE2 (base table): slot i of B gets sum_j xi'_j M'_j R^2 mod m_i; the
+    // redundant row sum_j xi'_j M'_j mod 2^32.
     fill_tiles(sh, out.base.data() + ly.a2(), [&](int t, int j, int a) -> int64_t {
-        if (t < 0) {
-            uint32_t v = j < K ? Mpj_lo(j) << (8 * a) : c2 * Mplo;
-            return balanced32(v);
-        }
+        if (t < 0) return balanced32(j < K ? Mpj_lo(j) << (8 * a) : kDigitBias * sumMpj_lo);
         uint32_t m = bs.B[t];
-        uint32_t v = j < K ? mulmod32(mulmod32(Mpj_mod(j, m), pow2_64_mod(m), m), pow2_mod(8 * a, m), m)
-                           : mulmod32(mulmod32(bn_mod_word(bs.Mp, m), pow2_64_mod(m), m), c2 % m, m);
-        return balanced(v, m);
+        uint32_t v = j < K ? mulmod32(Mpj_mod(j, m), pow2_mod(8 * a, m), m)
+                           : mulmod32(kDigitBias % m, sum_mod(Mpj_mod, m), m);
+        return balanced(mulmod32(v, pow2_64_mod(m), m), m);
     });
 
     // per-slot constants; junk slots use a valid modulus and zero constants
@@ -172,8 +173,8 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
         for (int l = 0; l <= K && l < (int)Mj.size(); l++) out.base[ly.MpL() + (size_t)j * (K + 1) + l] = Mj[l];
     }
     for (int l = 0; l <= K && l < (int)bs.Mp.size(); l++) out.base[ly.MpF() + l] = bs.Mp[l];
-    out.base[ly.bscal() + 0] = inv2_32(Mplo);
-    out.base[ly.bscal() + 1] = inv2_32(Mlo);
+    out.base[ly.bscal() + 0] = inv2_32(bn_low(bs.Mp));
+    out.base[ly.bscal() + 1] = inv2_32(bn_low(bs.M));
 
     // key: c_i = -N^-1 M_i^-1 mod m_i; "one" = M mod N in the kept representation
     fill_slots(sh, out.key.data() + ly.slotC(), 64, [&](int t) -> uint32_t {

@@ -30,7 +30,9 @@ struct MfmaTables {
     std::vector<uint32_t> key;   // per modulus
 };
 
-bool mfma_shape_for(int K, MfmaShape &out);
+// Matrix-core kernel shape for K: the first listed whose workgroup serves
+// `group` elements, else (or for group 0) the first listed for K.
+bool mfma_shape_for(int K, MfmaShape &out, int group = 0);
 
 MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh);
 

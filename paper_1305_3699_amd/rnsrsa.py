@@ -37,13 +37,31 @@ class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("window", ctypes.c_int), ("waves", ctypes.c_int),
                 ("prime_range", ctypes.c_int), ("prime_seed", ctypes.c_uint64),
                 ("primes", ctypes.POINTER(ctypes.c_uint32)), ("n_primes", ctypes.c_size_t),
-                ("engine", ctypes.c_int)]
+                ("engine", ctypes.c_int), ("group", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("waves", ctypes.c_int), ("window", ctypes.c_int),
-                ("mod_limbs", ctypes.c_int), ("mod_bits", ctypes.c_int), ("engine", ctypes.c_int)]
+                ("mod_limbs", ctypes.c_int), ("mod_bits", ctypes.c_int), ("engine", ctypes.c_int),
+                ("group", ctypes.c_int)]
 
+
+class RsaOp(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("kind", ctypes.c_int), ("inp", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("count", ctypes.c_size_t)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("window", ctypes.c_int)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int), ("jobs", ctypes.c_int), ("garner_launches", ctypes.c_int),
+                ("workspace_bytes", ctypes.c_size_t), ("modmuls", ctypes.c_size_t)]
+
+
+OP_ENCRYPT = 0
+OP_DECRYPT = 1
 
 _P = ctypes.c_void_p
 _S = ctypes.c_size_t
@@ -64,6 +82,10 @@ _SIGNATURES = {
     "rsa_decrypt": ([_P, _P, _P, _S, _I, _P], _I),
     "rsa_crt_halves": ([_P, _P, _P, _S, _P], _I),
     "rsa_crt_combine": ([_P, _P, _P, _S, _P], _I),
+    "rsa_batch_create": ([_P, _S, _P, _P, _P], _I),
+    "rsa_batch_run": ([_P, _P], _I),
+    "rsa_batch_info_get": ([_P, _P], _I),
+    "rsa_batch_free": ([_P], None),
     "rns_plan_create": ([_P, _S, _P, _P], _I),
     "rns_plan_free": ([_P], None),
     "rns_plan_info": ([_P, _P], _I),
@@ -73,6 +95,9 @@ _SIGNATURES = {
 }
 
 _lib_handle = None
+
+
+ABI_VERSION = 3           # rns_opts / rns_info layout of include/rnsrsa.h
 
 
 def lib():
@@ -88,6 +113,9 @@ def lib():
         f = getattr(h, name)
         f.argtypes = args
         f.restype = res
+    if h.rns_abi_version() != ABI_VERSION:
+        raise ImportError("librnsrsa.so has ABI %d, this binding needs %d; rebuild it"
+                          % (h.rns_abi_version(), ABI_VERSION))
     _lib_handle = h
     return h
 
@@ -116,10 +144,12 @@ def _host_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _make_opts(k=0, window=0, waves=0, prime_range=PRIMES_HIGH, prime_seed=0, primes=None, engine=ENGINE_AUTO):
+def _make_opts(k=0, window=0, waves=0, prime_range=PRIMES_HIGH, prime_seed=0, primes=None, engine=ENGINE_AUTO,
+               group=0):
     o = Opts()
     o.k, o.window, o.waves, o.prime_range, o.prime_seed = k, window, waves, prime_range, prime_seed
     o.engine = engine
+    o.group = group
     keep = None
     if primes is not None:
         keep = np.ascontiguousarray(primes, dtype=np.uint32)
@@ -151,7 +181,7 @@ def _info(getter, handle, *extra) -> dict:
     inf = Info()
     _check(getter(handle, *extra, ctypes.byref(inf)))
     return {"k": inf.k, "waves": inf.waves, "window": inf.window, "mod_limbs": inf.mod_limbs,
-            "mod_bits": inf.mod_bits, "engine": inf.engine}
+            "mod_bits": inf.mod_bits, "engine": inf.engine, "group": inf.group}
 
 
 class RnsContext:
@@ -357,3 +387,50 @@ class Plan:
         out = np.zeros_like(x)
         _check(lib().rns_emul_mont_mul(self._h, _host_ptr(x), _host_ptr(y), _host_ptr(out), x.shape[1]))
         return out
+
+
+class RsaBatch:
+    """A planned list of RSA operations over many keys (rsa_batch_*).
+
+    ops: list of (key: RsaKey, kind: OP_ENCRYPT | OP_DECRYPT, inp, out) with
+    inp/out int32 CUDA tensors of shape [count, n_limbs(key)].  The tensors and
+    keys are bound at creation and must stay alive; run() enqueues all of the
+    operations on the current stream."""
+
+    def __init__(self, ops, autotune: bool = False, use_graph: bool = True, window: int = 0, stream=None):
+        arr = (RsaOp * max(1, len(ops)))()
+        self._keep = []
+        for i, (key, kind, inp, out) in enumerate(ops):
+            count = inp.shape[0]
+            L = key.L
+            arr[i].key = key._h
+            arr[i].kind = kind
+            arr[i].inp = _dev_ptr(inp, count, L, "inp") if count else None
+            arr[i].out = _dev_ptr(out, count, L, "out") if count else None
+            arr[i].count = count
+            self._keep += [key, inp, out]
+        o = BatchOpts(int(autotune), int(use_graph), int(window))
+        h = ctypes.c_void_p()
+        _check(lib().rsa_batch_create(arr, len(ops), ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().rsa_batch_run(self._h, _stream_handle(stream)))
+
+    @property
+    def info(self) -> dict:
+        inf = BatchInfo()
+        _check(lib().rsa_batch_info_get(self._h, ctypes.byref(inf)))
+        return {"launches": inf.launches, "jobs": inf.jobs, "garner_launches": inf.garner_launches,
+                "workspace_bytes": inf.workspace_bytes, "modmuls": inf.modmuls}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rsa_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -47,3 +47,21 @@ def test_rns_primes():
     assert all(pow(2, p - 1, p) == 1 for p in ps)
     hi = gen.rns_primes(10, seed=9, lo=(1 << 32) - (1 << 24))
     assert all(p >= (1 << 32) - (1 << 24) for p in hi)
+
+
+def test_mixed_batch_spec():
+    keys, ops = gen.mixed_batch_spec()
+    assert len(keys) == 64
+    assert [b for b, _ in keys] == [1024] * 16 + [2048] * 16 + [3072] * 16 + [4096] * 16
+    assert len({s for _, s in keys}) == 64
+    per_key = {}
+    for o in ops:
+        per_key[o.key_index] = per_key.get(o.key_index, 0) + o.count
+        assert o.count >= 1 and o.kind in ("encrypt", "decrypt") and o.bits == keys[o.key_index][0]
+    sizes = sorted(per_key.values())
+    assert 1 <= sizes[0] and sizes[-1] <= 8192
+    assert 60 <= sizes[len(sizes) // 2] <= 260            # median 128 in distribution
+    n_dec = sum(o.count for o in ops if o.kind == "decrypt")
+    total = sum(o.count for o in ops)
+    assert 0.4 < n_dec / total < 0.6
+    assert gen.mixed_batch_spec() == (keys, ops)           # deterministic

@@ -149,12 +149,13 @@ def test_engines_agree(bits):
     assert np.array_equal(outs[1], oracle.modexp_batch(bases, e, gen.to_limbs(N, L)[0]))
 
 
-@pytest.mark.parametrize("engine", [1, 2])
-def test_rsa2048_crt_both_engines(engine):
+@pytest.mark.parametrize("engine,group", [(1, 0), (2, 16), (2, 32)])
+def test_rsa2048_crt_both_engines(engine, group):
     from paper_1305_3699_amd import RsaKey
     key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
-    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, engine=engine)
+    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, engine=engine, group=group)
     assert rk.info(1)["engine"] == engine
+    assert rk.info(1)["group"] == (group or 64)
     c = gen.uniform_below(key.n, 70, seed=12) + [0, 1, key.n - 1, key.p, key.q]
     cl = gen.to_limbs(c, 64)
     got = _host(rk.decrypt(_dev(cl), use_crt=True))
@@ -254,3 +255,86 @@ def test_zero_batch_is_a_no_op():
     empty = torch.zeros((0, 1), dtype=torch.int32, device="cuda")
     out = ctx.modexp(empty, torch.tensor([5], dtype=torch.int32, device="cuda"))
     assert out.shape == (0, 1)
+
+
+@pytest.mark.parametrize("ebits", [4096, 8192, 16128])
+def test_long_exponents_2048_bit_modulus(ebits):
+    """2048-bit modulus (a seeded RSA-2048 n), 1024 bases uniform in [0, n),
+    one seeded exponent of 4096 / 8192 / 16128 bits with the top bit set; the
+    oracle checks sampled rows (its schoolbook loop is slow at these sizes)."""
+    key = gen.rsa_key(2048, seed=gen.config_seed(3, 1))
+    ctx = _ctx(key.n, 64, window=6)
+    B = 1024
+    bases = gen.uniform_below(key.n, B, seed=gen.config_seed(3, 2))
+    e = gen.random_exponent(ebits, seed=gen.config_seed(3, 3) + ebits)
+    el = gen.to_limbs(e, ebits // 32 + (ebits % 32 != 0))[0]
+    bl = gen.to_limbs(bases, 64)
+    got = _run_modexp(ctx, bl, el)
+    idx = sorted(random.Random(ebits).sample(range(1, B - 1), 10)) + [0, B - 1]
+    want = oracle.modexp_batch(bl[idx], el, gen.to_limbs(key.n, 64)[0])
+    assert np.array_equal(got[idx], want)
+
+
+@pytest.mark.parametrize("bits", [3072, 4096])
+def test_rsa_crt_3072_4096_batch_4096(bits):
+    """RSA-3072 and RSA-4096 CRT decryption, 4096 ciphertexts each: sampled
+    rows against the oracle's CRT path, every row by re-encryption."""
+    from paper_1305_3699_amd import RsaKey
+    key = gen.rsa_key(bits, seed=gen.config_seed(3, 10 + bits // 1024))
+    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv)
+    L = bits // 32
+    B = 4096
+    c = gen.uniform_below(key.n, B, seed=gen.config_seed(3, 20 + bits // 1024))
+    cl = gen.to_limbs(c, L)
+    m = rk.decrypt(_dev(cl), use_crt=True)
+    assert np.array_equal(_host(rk.encrypt(m)), cl)
+    mh = _host(m)
+    idx = sorted(random.Random(bits).sample(range(1, B - 1), 14)) + [0, B - 1]
+    want = oracle.rsa_crt_batch(cl[idx], key.p, key.q, key.dp, key.dq, key.qinv)
+    assert np.array_equal(mh[idx], want)
+
+
+def _mixed_setup(n_keys, median, cap):
+    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RsaKey
+    specs, ops = gen.mixed_batch_spec(n_keys=n_keys, median=median, cap=cap)
+    keys = gen.rsa_keys(specs, processes=8)
+    rks = [RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv) for k in keys]
+    items = []
+    for o in ops:
+        k = keys[o.key_index]
+        L = o.bits // 32
+        vals = gen.uniform_below(k.n, o.count, seed=o.msg_seed)
+        inp = _dev(gen.to_limbs(vals, L))
+        out = torch.zeros_like(inp)
+        items.append((o, k, rks[o.key_index], OP_ENCRYPT if o.kind == "encrypt" else OP_DECRYPT, inp, out))
+    return items
+
+
+@pytest.mark.parametrize("use_graph,autotune", [(True, False), (False, True)])
+def test_batched_mixed_sizes(use_graph, autotune):
+    """Mixed-size batch (keys of 1024-4096 bits, lognormal per-key counts,
+    encryptions and CRT decryptions) in one batched run: every output equals
+    the oracle's, and equals the same operation run alone."""
+    from paper_1305_3699_amd import RsaBatch
+    items = _mixed_setup(8, 24, 96)
+    b = RsaBatch([(rk, kind, inp, out) for (o, k, rk, kind, inp, out) in items], autotune=autotune,
+                 use_graph=use_graph)
+    info = b.info
+    assert info["jobs"] == sum(2 if o.kind == "decrypt" else 1 for o, *_ in items)
+    for rep in range(2):                      # a graph is replayed; results must not change
+        for *_, out in items:
+            out.zero_()
+        b.run()
+        torch.cuda.synchronize()
+        for o, k, rk, kind, inp, out in items:
+            x = _host(inp)
+            got = _host(out)
+            if o.kind == "encrypt":
+                want = oracle.modexp_batch(x, gen.to_limbs(k.e, 1)[0], gen.to_limbs(k.n, o.bits // 32)[0])
+                alone = _host(rk.encrypt(inp))
+            else:
+                want = oracle.rsa_crt_batch(x, k.p, k.q, k.dp, k.dq, k.qinv)
+                alone = _host(rk.decrypt(inp, use_crt=True))
+            assert np.array_equal(got, want), (rep, o)
+            assert np.array_equal(alone, got)
+    b.close()

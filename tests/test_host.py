@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(rnsrsa.exported_symbols())
-    assert lib.rns_abi_version() == 2
+    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 3
 
 
 def _check_bounds(plan, N, L):
@@ -48,7 +48,7 @@ def _check_bounds(plan, N, L):
     assert len(set(pr)) == 2 * k
     assert all((1 << 31) < p < (1 << 32) and pow(2, p - 1, p) == 1 for p in pr)
     M, Mp = math.prod(B), math.prod(Bp)
-    assert M >= (k + 2) ** 2 * N and M >= 2 ** (32 * L + 1) and Mp >= (k + 2) * N
+    assert M >= (k + 1) ** 2 * N and M >= 2 ** (32 * L + 1) and Mp >= (k + 1) * N
     assert math.gcd(M, N) == 1
 
 
@@ -157,9 +157,33 @@ def test_emul_rsa1024_config_round_trip(engine):
 def test_engine_selection():
     assert Plan(3233).info["engine"] == rnsrsa.ENGINE_MATRIX          # auto: matrix cores when built
     assert Plan(3233, engine=rnsrsa.ENGINE_CHANNEL).info["engine"] == rnsrsa.ENGINE_CHANNEL
+    assert Plan(3233, engine=rnsrsa.ENGINE_CHANNEL).info["group"] == 64
     with pytest.raises(RnsError) as e:
         Plan(3233, engine=7)
     assert e.value.status == -1
+    with pytest.raises(RnsError) as e:
+        Plan(3233, group=24)
+    assert e.value.status == -1
+
+
+def test_group_selection():
+    N = (1 << 1023) + 1155
+    for g in (16, 32):
+        p = Plan(N, 32, group=g)
+        assert p.info["engine"] == rnsrsa.ENGINE_MATRIX and p.info["group"] == g
+    assert Plan(N, 32).info["group"] == 32                           # default tile for k = 33
+    big = (1 << 2047) + 4095
+    assert Plan(big, 64, group=16).info["group"] == 32               # no 16-element kernel for k = 65
+
+
+@pytest.mark.parametrize("group", [16, 32])
+def test_emul_group_sizes_agree(group):
+    rng = random.Random(group)
+    N = rng.getrandbits(1024) | (1 << 1023) | 1
+    bases = gen.to_limbs([rng.getrandbits(1024) for _ in range(37)] + [0, N - 1], 32)
+    e = gen.to_limbs(rng.getrandbits(100), 4)[0]
+    out = Plan(N, 32, window=3, group=group).emul_modexp(bases, e)
+    assert np.array_equal(out, oracle.modexp_batch(bases, e, gen.to_limbs(N, 32)[0]))
 
 
 @pytest.mark.parametrize("bits", [96, 1536, 3000])
@@ -175,22 +199,16 @@ def test_emul_engines_agree_per_element_exponents(bits):
                                                                          oracle.rows_to_ints(exps))]
 
 
-def test_emul_exit_digit_below_int32_min():
-    """Regression: at the exit, a centred digit of a prime above 2^31 + T
-    (T = 0x7F7F7F80) can lie below -2^31 and must still be recognised as
-    negative.  For this 100-bit modulus the state of a zero base is c N with
-    c = ceil(sum(1 - T/m_i)), and its first B' digit falls in that range."""
-    rng = random.Random(100)
-    N = rng.getrandbits(100) | (1 << 99) | rng.getrandbits(1)
-    T = 0x7F7F7F80
-    p = Plan(N, 4, window=2, engine=rnsrsa.ENGINE_MATRIX)
-    k = p.info["k"]
-    B, Bp = p.primes[:k], p.primes[k:]
-    c = math.ceil(sum(max(0.0, 1 - T / m) for m in B))
-    Mp = math.prod(Bp)
-    digits = [c * N * pow(Mp // m, -1, m) % m for m in Bp]
-    assert any(T <= d < m - (1 << 31) for d, m in zip(digits, Bp))    # the case is exercised
-    bases = [0, N, 2 * N, 1, N - 1]
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("bits", [64, 100, 128, 1000])
+def test_emul_zero_residue_bases(bits, engine):
+    """Bases that are multiples of N (all-zero quotient digits) on moduli
+    including the 100-bit one whose exit once mis-decoded such a state."""
+    rng = random.Random(bits)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | rng.getrandbits(1)
+    L = (bits + 31) // 32
+    p = Plan(N, L, window=2, engine=engine)
+    bases = [b for b in (0, N, 2 * N, 3 * N, 1, N - 1) if b < 1 << (32 * L)]
     for e in (1, 2, 65537):
-        out = p.emul_modexp(gen.to_limbs(bases, 4), gen.to_limbs(e, 1)[0])
+        out = p.emul_modexp(gen.to_limbs(bases, L), gen.to_limbs(e, 1)[0])
         assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]

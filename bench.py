@@ -14,6 +14,7 @@ import argparse
 import hashlib
 import json
 import os
+import random
 import statistics
 import sys
 import time
@@ -42,10 +43,31 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def mm_count(exp: int, exp_bits: int, w: int) -> int:
-    """RNS Montgomery products of one exponentiation as the kernel schedules
-    them: entry, 2^w - 2 table products, w squarings per digit after the
-    leading non-zero one plus one multiply per non-zero digit, exit."""
+def mm_count(exp: int, exp_bits: int, w: int, sliding: bool = True) -> int:
+    """RNS Montgomery products of one exponentiation as the kernels schedule
+    them.  sliding (matrix-core kernel, shared exponent): entry, x^2 and the
+    odd powers up to x^(2^w - 1), then per sliding window after the first its
+    squarings and one multiplication, one squaring per zero bit between
+    windows, exit.  Fixed (channel kernel): entry, 2^w - 2 table products, w
+    squarings per digit after the leading non-zero one plus one multiply per
+    non-zero digit, exit."""
+    if sliding:
+        n = 2 + ((1 << (w - 1)) if w > 1 else 0)
+        i = exp.bit_length() - 1
+        first = True
+        while i >= 0:
+            if not (exp >> i) & 1:
+                n += 1
+                i -= 1
+                continue
+            lo = max(i - w + 1, 0)
+            while not (exp >> lo) & 1:
+                lo += 1
+            if not first:
+                n += (i - lo + 1) + 1
+            first = False
+            i = lo - 1
+        return n
     nd = (exp_bits + w - 1) // w
     digits = [(exp >> (w * (nd - 1 - i))) & ((1 << w) - 1) for i in range(nd)]
     n = 1 + (1 << w) - 2 + 1
@@ -202,7 +224,9 @@ def run(args) -> dict:
     value = B * args.steps / wall
 
     k = info["k"]
-    mms = mm_count(key.dp, 32 * half, info["window"]) + mm_count(key.dq, 32 * half, info["window"])
+    sliding = info["engine"] == 2
+    mms = (mm_count(key.dp, 32 * half, info["window"], sliding)
+           + mm_count(key.dq, 32 * half, info["window"], sliding))
     muls_per_launch = B * mms * wide_muls_per_mm(k)
     mean_modexp_s = statistics.mean(modexp_ms) / 1e3
     achieved = muls_per_launch / mean_modexp_s
@@ -354,6 +378,134 @@ def run_mixed(args) -> dict:
     }
 
 
+def run_served(args) -> dict:
+    """Served form: 256 resident keys (64 each of 2048/1024/3072/4096 bits),
+    open-loop Poisson arrivals at each rate for warm-up + duration seconds,
+    key size 40/30/20/10%, 70% CRT decryptions, 64 GiB admission budget.
+    Latency = completion - arrival on the host clock; requests arriving during
+    the warm-up are excluded.  A sample of each run is checked against the
+    oracle."""
+    import numpy as np
+
+    import gen
+    import oracle
+    from paper_1305_3699_amd import RsaKey, RsaServer
+
+    per = 64
+    specs = gen.served_keys(per_size=per)
+    t0 = time.perf_counter()
+    keys = gen.rsa_keys(specs, processes=cpu_threads())
+    keygen_s = time.perf_counter() - t0
+    rks = [RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv) for k in keys]
+    limbs = [k.n.bit_length() // 32 for k in keys]
+    out = {"keys": len(keys), "keygen_s": round(keygen_s, 1), "budget_gib": 64,
+           "max_inflight": args.served_inflight, "warmup_s": args.served_warmup,
+           "duration_s": args.served_duration, "runs": []}
+    for rate in args.served_rates:
+        total = args.served_warmup + args.served_duration
+        arrival, kidx, kind, seeds = gen.served_trace(rate, total, per_size=per, seed_offset=int(rate) % 1000)
+        n = arrival.size
+        msgs = np.zeros((n, 128), np.uint32)
+        for i in range(n):
+            L = limbs[kidx[i]]
+            msgs[i, :L] = gen.to_limbs(gen.uniform_below_fast(keys[kidx[i]].n, int(seeds[i])), L)[0]
+        srv = RsaServer(rks, hbm_budget=64 << 30, max_inflight=args.served_inflight)
+        res, lat, st = srv.replay(kidx, kind, arrival, msgs)
+        srv.close()
+        sel = arrival >= args.served_warmup
+        lw = np.sort(lat[sel])
+        done_t = arrival + lat
+        in_window = (done_t >= args.served_warmup) & (done_t < total)
+        ok = True
+        for i in random.Random(int(rate)).sample(range(n), min(64, n)):
+            k = keys[kidx[i]]
+            L = limbs[kidx[i]]
+            x = np.ascontiguousarray(msgs[i:i + 1, :L])
+            want = (oracle.modexp_batch(x, gen.to_limbs(k.e, 1)[0], gen.to_limbs(k.n, L)[0]) if kind[i] == 0
+                    else oracle.rsa_crt_batch(x, k.p, k.q, k.dp, k.dq, k.qinv))
+            ok = ok and bool(np.array_equal(res[i:i + 1, :L], want))
+        out["runs"].append({
+            "offered_req_per_s": rate,
+            "requests": int(sel.sum()),
+            "completed_per_s": round(float(in_window.sum()) / args.served_duration, 1),
+            "latency_ms": {"p50": round(float(lw[(lw.size - 1) // 2]) * 1e3, 3),
+                           "p99": round(float(lw[min(lw.size - 1, int(0.99 * (lw.size - 1) + 0.5))]) * 1e3, 3),
+                           "max": round(float(lw[-1]) * 1e3, 3)},
+            "dispatches": st["dispatches"],
+            "mean_dispatch_requests": round(st["mean_dispatch_ops"], 1),
+            "peak_inflight": st["peak_inflight"],
+            "peak_inflight_mb": round(st["peak_inflight_bytes"] / 2 ** 20, 1),
+            "sample_matches_oracle": ok,
+        })
+        print("served rate %g: %s" % (rate, json.dumps(out["runs"][-1])), file=sys.stderr, flush=True)
+    return out
+
+
+def run_modmul_sweep(args) -> list:
+    """RNS modular multiplications of 3072-bit integers per millisecond against
+    the number of operands in flight (the shape of the paper's Fig. 1: 3072-bit
+    modular multiplication over 128 32-bit channels, throughput vs blocks).
+    Two forms: the standalone product (rns_mont_mul_batch, one launch of B
+    independent products on residue vectors) and the products inside an
+    exponentiation by a 3072-bit exponent (rns_modexp_batch, counted from the
+    exponent as the kernel schedules them).  k = 97 is the smallest base for a
+    3072-bit modulus; k = 129 is the closest to the paper's 128 channels."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1305_3699_amd import RnsContext
+
+    rng = random.Random(gen.config_seed(6, 1))
+    N = rng.getrandbits(3072) | (1 << 3071) | 1
+    e = gen.random_exponent(3072, seed=gen.config_seed(6, 3))
+    el = torch.from_numpy(gen.to_limbs(e, 96)[0].view(np.int32)).cuda()
+    lines = []
+    for k in (97, 129):
+        ctx = RnsContext(N, 96, k=k, window=6)
+        info = ctx.info
+        primes = torch.tensor(ctx.primes + [0], dtype=torch.int64, device="cuda")
+        mm_exp = mm_count(e, 3072, info["window"], sliding=info["engine"] == 2)
+        rows = []
+        for B in args.modmul_batches:
+            # standalone product: residues drawn below each channel modulus
+            g = torch.Generator(device="cuda").manual_seed(B)
+            def residues():
+                r = torch.randint(0, 1 << 32, (2 * k + 1, B), dtype=torch.int64, device="cuda", generator=g)
+                m = primes[:, None]
+                r = torch.where(m > 0, r % torch.where(m > 0, m, 1), r)
+                return torch.where(r >= 1 << 31, r - (1 << 32), r).to(torch.int32).contiguous()
+            x, y = residues(), residues()
+            out = torch.empty_like(x)
+
+            def timed(fn, reps):
+                for _ in range(2):
+                    fn()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    fn()
+                b.record()
+                torch.cuda.synchronize()
+                return a.elapsed_time(b) / reps
+
+            ms_mm = timed(lambda: ctx.mont_mul(x, y, out=out), 20)
+            bases = torch.from_numpy(gen.to_limbs([rng.getrandbits(3071) for _ in range(min(B, 64))], 96)
+                                     .view(np.int32)).cuda().repeat((B + 63) // 64, 1)[:B].contiguous()
+            res = torch.empty_like(bases)
+            ms_exp = timed(lambda: ctx.modexp(bases, el, out=res), 2 if B >= 4096 else 5)
+            rows.append({"operands": B, "standalone_per_ms": round(B / ms_mm, 1),
+                         "in_exponentiation_per_ms": round(B * mm_exp / ms_exp, 1),
+                         "standalone_ms": round(ms_mm, 4), "exponentiation_ms": round(ms_exp, 3)})
+            print("modmul k=%d %s" % (k, json.dumps(rows[-1])), file=sys.stderr, flush=True)
+        lines.append({"metric": "3072-bit RNS modular multiplications per ms vs operands in flight",
+                      "k": k, "engine": {1: "channel", 2: "matrix"}[info["engine"]],
+                      "standalone_engine": "channel", "window": info["window"],
+                      "products_per_exponentiation": mm_exp, "rows": rows})
+    return lines
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +519,15 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-sample", type=int, default=16384, help="ciphertexts for the oracle baseline (0: skip)")
     ap.add_argument("--sweep-window", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=5, help="timed runs of the batched-vs-plain mix (0: skip)")
+    ap.add_argument("--served", action="store_true", help="also run the served workload (about 2 minutes)")
+    ap.add_argument("--modmul-sweep", action="store_true",
+                    help="only the 3072-bit modular multiplication sweep (one JSON line per base size)")
+    ap.add_argument("--modmul-batches", type=int, nargs="+",
+                    default=[16, 64, 256, 1024, 4096, 16384, 65536])
+    ap.add_argument("--served-rates", type=float, nargs="+", default=[5000.0, 20000.0, 80000.0])
+    ap.add_argument("--served-duration", type=float, default=10.0)
+    ap.add_argument("--served-warmup", type=float, default=1.0)
+    ap.add_argument("--served-inflight", type=int, default=4)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one elementwise copy of N MiB before the benchmark (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -379,6 +540,10 @@ def main(argv=None) -> int:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
               "(multi-GPU sharding is a design note, not a measured configuration)", file=sys.stderr)
         return 2
+    if args.modmul_sweep:
+        for line in run_modmul_sweep(args):
+            print(json.dumps(line), flush=True)
+        return 0
     if args.sweep_window:
         for w in range(1, 7):
             args.window = w
@@ -388,6 +553,8 @@ def main(argv=None) -> int:
     out = run(args)
     if args.mixed_steps > 0:
         out["batched_vs_plain"] = run_mixed(args)
+    if args.served:
+        out["served"] = run_served(args)
     print(json.dumps(out), flush=True)
     return 0
 

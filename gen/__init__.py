@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "first_primes", "is_probable_prime", "random_prime", "RsaKey", "rsa_key",
     "uniform_below", "random_exponent", "to_limbs", "limbs_needed",
-    "rns_primes", "config_seed", "MixedOp", "mixed_batch_spec", "rsa_keys",
+    "rns_primes", "config_seed", "MixedOp", "mixed_batch_spec", "rsa_keys", "served_keys", "served_trace",
 ]
 
 # Seed streams: config i uses 1000*i + s, s in {1: keys, 2: messages,
@@ -247,3 +247,44 @@ def rsa_keys(specs, processes: int = 1) -> list:
     import multiprocessing as mp
     with mp.get_context("fork").Pool(min(processes, len(specs))) as pool:
         return pool.map(_key_job, specs)
+
+
+# ---------------------------------------------------------------------------
+# Served workload: resident keys and a Poisson request trace.
+
+SERVED_SIZES = (2048, 1024, 3072, 4096)
+SERVED_SIZE_P = (0.4, 0.3, 0.2, 0.1)
+
+
+def served_keys(per_size: int = 64, sizes=SERVED_SIZES, config: int = 5) -> list:
+    """(bits, seed) of the resident keys: per_size keys of each size, grouped
+    by size in the order of ``sizes``."""
+    return [(b, config_seed(config, 1) * 10000 + i * 1000 + j) for i, b in enumerate(sizes) for j in range(per_size)]
+
+
+def served_trace(rate: float, duration: float, per_size: int = 64, p_decrypt: float = 0.7, sizes=SERVED_SIZES,
+                 size_p=SERVED_SIZE_P, config: int = 5, seed_offset: int = 0):
+    """Open-loop Poisson trace: exponential inter-arrival times of mean 1/rate
+    over [0, duration); each request picks a key size with probabilities
+    size_p, a key uniformly within that size, and is a CRT decryption with
+    probability p_decrypt, else an encryption (e = 65537).  Returns numpy
+    arrays (arrival seconds, key index into served_keys, kind 0 = encrypt /
+    1 = decrypt, message seed)."""
+    rng = np.random.default_rng(config_seed(config, 5) + seed_offset)
+    n_max = int(rate * duration * 1.2 + 100)
+    gaps = rng.exponential(1.0 / rate, n_max)
+    arrival = np.cumsum(gaps)
+    while arrival[-1] < duration:                      # extremely unlikely with the 20% margin
+        arrival = np.concatenate([arrival, arrival[-1] + np.cumsum(rng.exponential(1.0 / rate, n_max))])
+    arrival = arrival[arrival < duration]
+    n = arrival.size
+    size_idx = rng.choice(len(sizes), size=n, p=np.asarray(size_p) / np.sum(size_p))
+    key = size_idx * per_size + rng.integers(0, per_size, size=n)
+    kind = (rng.random(n) < p_decrypt).astype(np.int32)
+    msg_seed = config_seed(config, 2) * 10_000_000 + seed_offset * 1_000_000 + np.arange(n)
+    return arrival, key.astype(np.int32), kind, msg_seed
+
+
+def uniform_below_fast(n: int, seed: int) -> int:
+    """One integer uniform in [0, n) (rejection on getrandbits) for seed."""
+    return uniform_below(n, 1, seed)[0]

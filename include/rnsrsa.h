@@ -247,8 +247,8 @@ int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t
  *   window       0: per job, the window width minimising the number of
  *                Montgomery products for its exponent; 1..6: fixed.
  * Errors: RNS_EINVAL (bad op, null buffer), RNS_ENOMEM, RNS_EDEVICE.
- * rsa_batch_create may run work on `hip_stream` (autotuning) and returns
- * after it completed.
+ * rsa_batch_create synchronises `hip_stream` (autotuning runs on an internal
+ * stream) and returns when the batch is ready to run.
  */
 enum rsa_op_kind { RSA_OP_ENCRYPT = 0, RSA_OP_DECRYPT = 1 };
 
@@ -282,6 +282,61 @@ int rsa_batch_run(rsa_batch *b, void *hip_stream);
 int rsa_batch_info_get(const rsa_batch *b, rsa_batch_info *info);
 /* Waits for the batch's device work, then releases it. */
 void rsa_batch_free(rsa_batch *b);
+
+/*
+ * Request server: the served form of the batched path (Sec. 3.3 operations
+ * on resident keys).  Keys stay resident; requests are admitted as dispatch
+ * slots and device memory free up (continuous batching: requests that arrive
+ * while others run on the GPU join the next dispatch), each dispatch plans
+ * grouped launches as rsa_batch does, and up to max_inflight dispatches run
+ * concurrently on their own streams.
+ *
+ *   rsa_server_opts  hbm_budget: device bytes in-flight dispatches may hold
+ *                    (0 = 64 GiB); max_inflight: concurrent dispatches
+ *                    (0 = 4); max_dispatch_ops: requests per dispatch
+ *                    (0 = 16384).
+ *   rsa_request      one RSA operation on key `key` (an index into the
+ *                    server's key list): in and out are HOST buffers of
+ *                    n_limbs(key) limbs; out is written when it completes.
+ *                    arrival: seconds after the start of the replay.
+ * rsa_server_replay runs an open-loop trace: request i is admitted no earlier
+ * than its arrival time on the host's monotonic clock (arrivals must be
+ * non-decreasing); it returns when all have completed.  latency (optional,
+ * n entries) receives completion - arrival in seconds; the completion time is
+ * when the host sees the dispatch's results copied back.
+ * Errors: RNS_EINVAL (bad key index or kind, null buffer, decreasing
+ * arrivals, a request that alone exceeds the budget), RNS_ENOMEM,
+ * RNS_EDEVICE.  The keys must outlive the server.
+ */
+typedef struct rsa_server_opts {
+    size_t hbm_budget;
+    int max_inflight;
+    size_t max_dispatch_ops;
+} rsa_server_opts;
+
+typedef struct rsa_request {
+    int key;
+    int kind;
+    const uint32_t *in;
+    uint32_t *out;
+    double arrival;
+} rsa_request;
+
+typedef struct rsa_server_stats {
+    size_t completed;
+    size_t dispatches;
+    double elapsed;              /* first arrival to last completion, seconds */
+    double p50_latency, p99_latency, max_latency;   /* seconds */
+    double mean_dispatch_ops;
+    size_t peak_inflight_bytes;  /* device bytes held by dispatches at once */
+    int peak_inflight;           /* dispatches in flight at once */
+} rsa_server_stats;
+
+typedef struct rsa_server rsa_server;
+
+int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_server_opts *opts, rsa_server **out);
+int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double *latency, rsa_server_stats *stats);
+void rsa_server_free(rsa_server *srv);
 
 #ifdef __cplusplus
 }

@@ -4,4 +4,5 @@ The HIP library (``_lib/librnsrsa.so``, C ABI in ``include/rnsrsa.h``) does
 all the arithmetic; ``rnsrsa`` is its ctypes binding.
 """
 from .rnsrsa import (ENGINE_AUTO, ENGINE_CHANNEL, ENGINE_MATRIX, OP_DECRYPT, OP_ENCRYPT, PRIMES_FULL,  # noqa: F401
-                     PRIMES_HIGH, Plan, RnsContext, RnsError, RsaBatch, RsaKey, int_to_limbs, lib, nlimbs)
+                     PRIMES_HIGH, Plan, RnsContext, RnsError, RsaBatch, RsaKey, RsaServer, int_to_limbs, lib,
+                     nlimbs)

@@ -31,6 +31,8 @@ struct Scratch {
     }
 };
 int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s);
+// Keep freed stream-ordered blocks in the device pool (once per process).
+void configure_pool_once();
 
 }  // namespace api
 }  // namespace rnsrsa

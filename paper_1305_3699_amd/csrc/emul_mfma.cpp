@@ -202,31 +202,63 @@ void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
         std::vector<MSt> tbl(TT);
         tbl[0] = one;
         tbl[1] = a;
-        for (int j = 2; j < TT; j++) {
-            mm(c, a, tbl[1], dig1, dig2, true);
-            tbl[j] = a;
-        }
-        int di = 0;
         if (exp_stride == 0) {
-            while (di < nd && digit_of(exp, exp_limbs, nd, w, di) == 0) di++;
-            if (di < nd) {
-                a = tbl[digit_of(exp, exp_limbs, nd, w, di)];
-                di++;
-            } else {
+            // sliding windows over odd powers (x^2 kept in slot 2)
+            if (w > 1) {
+                MSt x2 = a, sqr = a;
+                mm(c, x2, sqr, dig1, dig2, true);
+                tbl[2] = x2;
+                for (int j = 3; j < TT; j += 2) {
+                    MSt t = tbl[j - 2];
+                    mm(c, t, x2, dig1, dig2, true);
+                    tbl[j] = t;
+                }
+            }
+            auto bit = [&](int i) { return (exp[i >> 5] >> (i & 31)) & 1u; };
+            int top = -1;
+            for (int i = 32 * exp_limbs - 1; i >= 0 && top < 0; i--)
+                if (bit(i)) top = i;
+            auto window = [&](int i, int *low) {
+                int lo = std::max(i - w + 1, 0);
+                while (!bit(lo)) lo++;
+                uint32_t d = 0;
+                for (int b = i; b >= lo; b--) d = 2 * d + bit(b);
+                *low = lo;
+                return d;
+            };
+            if (top < 0) {
                 a = one;
+            } else {
+                int low;
+                a = tbl[window(top, &low)];
+                int i = low - 1;
+                while (i >= 0) {
+                    if (!bit(i)) {
+                        MSt sqr = a;
+                        mm(c, a, sqr, dig1, dig2, true);
+                        i--;
+                        continue;
+                    }
+                    const uint32_t d = window(i, &low);
+                    for (int q = 0; q < i - low + 1; q++) {
+                        MSt sqr = a;
+                        mm(c, a, sqr, dig1, dig2, true);
+                    }
+                    mm(c, a, tbl[d], dig1, dig2, true);
+                    i = low - 1;
+                }
             }
         } else {
-            a = one;
-        }
-        for (; di < nd; di++) {
-            for (int s = 0; s < w; s++) {
-                MSt sq = a;
-                mm(c, a, sq, dig1, dig2, true);
+            for (int j = 2; j < TT; j++) {
+                tbl[j] = tbl[j - 1];
+                mm(c, tbl[j], tbl[1], dig1, dig2, true);
             }
-            if (exp_stride == 0) {
-                const uint32_t d = digit_of(exp, exp_limbs, nd, w, di);
-                if (d) mm(c, a, tbl[d], dig1, dig2, true);
-            } else {
+            a = one;
+            for (int di = 0; di < nd; di++) {
+                for (int s = 0; s < w; s++) {
+                    MSt sq = a;
+                    mm(c, a, sq, dig1, dig2, true);
+                }
                 MSt y = one;
                 for (int e = 0; e < NM; e++) {
                     const size_t el = std::min(g0 + e, batch - 1);

@@ -242,6 +242,40 @@ __device__ __forceinline__ void mstate_unit(const MConst<MT, MShp<K, W, MT, NT>:
     for (int nt = 0; nt < NT; nt++) y.r[nt] = 1u;
 }
 
+// Limb l of a shared (wave-uniform) exponent.  The builtin returns int: the
+// limb is taken back as unsigned before any widening (a sign extension would
+// fill the upper half of a 64-bit window with ones).
+__device__ __forceinline__ uint32_t mexp_limb(const uint32_t *__restrict__ e, int l) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)e[l]);
+}
+
+// Bit i of a shared exponent.
+__device__ __forceinline__ uint32_t mexp_bit(const uint32_t *__restrict__ e, int i) {
+    return (mexp_limb(e, i >> 5) >> (i & 31)) & 1u;
+}
+
+// Highest set bit of a shared exponent of n limbs, -1 if it is zero.
+__device__ __forceinline__ int mexp_top_bit(const uint32_t *__restrict__ e, int n) {
+    for (int l = n - 1; l >= 0; l--) {
+        const uint32_t v = mexp_limb(e, l);
+        if (v) return 32 * l + 31 - __builtin_clz(v);
+    }
+    return -1;
+}
+
+// Sliding window of a shared exponent whose bit i is set: the bits i..low
+// with low >= i - w + 1 the lowest set bit in that range; returns their value
+// (odd, < 2^w) and low.
+__device__ __forceinline__ uint32_t mexp_window(const uint32_t *__restrict__ e, int n, int i, int w, int *low) {
+    int lo = i - w + 1 > 0 ? i - w + 1 : 0;
+    while (!mexp_bit(e, lo)) lo++;
+    const int l = lo >> 5;
+    uint64_t v = mexp_limb(e, l);
+    if (l + 1 < n) v |= (uint64_t)mexp_limb(e, l + 1) << 32;
+    *low = lo;
+    return (uint32_t)(v >> (lo & 31)) & ((1u << (i - lo + 1)) - 1u);
+}
+
 __device__ __forceinline__ uint32_t mexp_digit(const uint32_t *__restrict__ e, int nlimbs, int nd, int w, int di) {
     const int lo = (nd - 1 - di) * w;
     const int limb = lo >> 5, sh = lo & 31;
@@ -301,7 +335,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     C.N_r = mk[S::LY.kscal() + 0];
 
     // entry: residues of Z = sum_h X_h Y_h in the kept representation
-    MState<MT, NT> a, y;
+    MState<MT, NT> a;
     {
         Acc ab[MT][NT], ap[MT][NT];
         uint32_t zr[NT];
@@ -362,82 +396,131 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         mstate_store<MT, NT>(tw, one);   // T[0] = M mod N
     }
 
-    const int nd = (32 * J.exp_limbs + w - 1) / w;
+    // Exponent schedule.  Shared exponent: left-to-right sliding windows of
+    // at most w bits that start and end with a set bit, over a table of the
+    // odd powers x, x^3, ..., x^(2^w - 1) (built with x^2, kept in slot 2);
+    // the windows are found on the scalar unit.  Per-element exponents: fixed
+    // w-bit digits over the full table x^0 .. x^(2^w - 1).  The control picks
+    // where the next product's second operand comes from; it is fetched at
+    // the top of the loop, so it is not live across iterations.
     const bool shared_exp = J.exp_stride == 0;
-    enum { ENTRY, BUILD, MAIN, EXIT };
+    const int nbits = 32 * J.exp_limbs;
+    const int nd = (nbits + w - 1) / w;
+    enum { ENTRY, SQX, BUILD, MAIN, EXIT };
+    enum { Y_SQUARE, Y_UNIT, Y_TABLE, Y_ELEM };
     int phase = ENTRY, j = 2, di = 0, s = 0;
-    mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
+    int bitpos = -1, sq = 0;
+    uint32_t dm = 0;
+    int ysrc = Y_UNIT, yidx = 0;
     for (;;) {
-        mfma_mm<K, W, MT, NT>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
+        {
+            MState<MT, NT> y;
+            if (ysrc == Y_SQUARE) {
+                y = a;
+            } else if (ysrc == Y_UNIT) {
+                mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
+            } else if (ysrc == Y_TABLE) {
+                mstate_load<MT, NT>(tw + (size_t)yidx * estride, y);
+            } else {
+                // per-element exponents: each lane slot loads the entry of its own element
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) {
+                    const int m = e0 + 16 * nt + (lane & 15);
+                    const uint32_t *__restrict__ ep = ex + (size_t)(m < J.batch ? m : 0) * J.exp_stride;
+                    const uint32_t d = mexp_digit(ep, J.exp_limbs, nd, w, yidx);
+                    const uint32_t *__restrict__ pe = tw + (size_t)d * estride;
+#pragma unroll
+                    for (int mt = 0; mt < MT; mt++) {
+                        y.b[mt][nt] = pe[(mt * NT + nt) * 64];
+                        y.p[mt][nt] = pe[(MT * NT + mt * NT + nt) * 64];
+                    }
+                    y.r[nt] = pe[(2 * MT * NT + nt) * 64];
+                }
+            }
+            mfma_mm<K, W, MT, NT>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
+        }
         if (phase == EXIT) break;
         if (phase == ENTRY) {
-            mstate_store<MT, NT>(tw + estride, a);
-            phase = BUILD;
-        } else if (phase == BUILD) {
-            mstate_store<MT, NT>(tw + (size_t)j * estride, a);
-            j++;
-        }
-        if (phase == BUILD) {
-            if (j < T) {
-                mstate_load<MT, NT>(tw + estride, y);
+            mstate_store<MT, NT>(tw + estride, a);               // T[1] = x
+            if (w > 1) {
+                if (shared_exp) {
+                    phase = SQX;
+                    ysrc = Y_SQUARE;
+                } else {
+                    phase = BUILD;
+                    j = 2;
+                    ysrc = Y_TABLE;
+                    yidx = 1;
+                }
                 continue;
             }
+        } else if (phase == SQX) {
+            mstate_store<MT, NT>(tw + 2 * estride, a);           // x^2, slot 2 (even: unused by the windows)
+            mstate_load<MT, NT>(tw + estride, a);
+            phase = BUILD;
+            j = 3;
+            ysrc = Y_TABLE;
+            yidx = 2;
+            continue;
+        } else if (phase == BUILD) {
+            mstate_store<MT, NT>(tw + (size_t)j * estride, a);  // T[j] = T[j - step] * (x^2 or x)
+            j += shared_exp ? 2 : 1;
+            if (j < T) {
+                ysrc = Y_TABLE;
+                yidx = shared_exp ? 2 : 1;
+                continue;
+            }
+        }
+        if (phase != MAIN) {
             phase = MAIN;
-            s = 0;
             if (shared_exp) {
-                uint32_t d = 0;
-                while (di < nd) {
-                    d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, J.exp_limbs, nd, w, di));
-                    if (d) break;
-                    di++;
-                }
-                if (di < nd) {
-                    mstate_load<MT, NT>(tw + (size_t)d * estride, a);
-                    di++;
+                bitpos = mexp_top_bit(ex, J.exp_limbs);
+                if (bitpos < 0) {
+                    mstate_load<MT, NT>(tw, a);                   // e = 0: the result is 1
                 } else {
-                    mstate_load<MT, NT>(tw, a);
+                    int low;
+                    const uint32_t d = mexp_window(ex, J.exp_limbs, bitpos, w, &low);
+                    mstate_load<MT, NT>(tw + (size_t)d * estride, a);
+                    bitpos = low - 1;
                 }
             } else {
                 mstate_load<MT, NT>(tw, a);
             }
         }
-        for (;;) {
+        if (shared_exp) {
+            if (sq > 0) {                                          // squarings of the current window
+                ysrc = Y_SQUARE;
+                sq--;
+            } else if (dm) {                                       // its multiplication
+                ysrc = Y_TABLE;
+                yidx = (int)dm;
+                dm = 0;
+            } else if (bitpos < 0) {
+                phase = EXIT;
+                ysrc = Y_UNIT;
+            } else {
+                ysrc = Y_SQUARE;                                   // a square in any case
+                if (mexp_bit(ex, bitpos)) {
+                    int low;
+                    dm = mexp_window(ex, J.exp_limbs, bitpos, w, &low);
+                    sq = bitpos - low;
+                    bitpos = low - 1;
+                } else {
+                    bitpos--;
+                }
+            }
+        } else {
             if (di >= nd) {
                 phase = EXIT;
-                mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
-                break;
-            }
-            if (s < w) {
-                y = a;
+                ysrc = Y_UNIT;
+            } else if (s < w) {
+                ysrc = Y_SQUARE;
                 s++;
-                break;
-            }
-            di++;
-            s = 0;
-            if (shared_exp) {
-                const uint32_t d = __builtin_amdgcn_readfirstlane(mexp_digit(ex, J.exp_limbs, nd, w, di - 1));
-                if (d != 0) {
-                    mstate_load<MT, NT>(tw + (size_t)d * estride, y);
-                    break;
-                }
             } else {
-                // per-element exponents: each lane slot loads the entry of its own element
-                MState<MT, NT> t;
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) {
-                    const int m = e0 + 16 * nt + (lane & 15);
-                    const uint32_t *__restrict__ ep = ex + (size_t)(m < J.batch ? m : 0) * J.exp_stride;
-                    const uint32_t d = mexp_digit(ep, J.exp_limbs, nd, w, di - 1);
-                    const uint32_t *__restrict__ pe = tw + (size_t)d * estride;
-#pragma unroll
-                    for (int mt = 0; mt < MT; mt++) {
-                        t.b[mt][nt] = pe[(mt * NT + nt) * 64];
-                        t.p[mt][nt] = pe[(MT * NT + mt * NT + nt) * 64];
-                    }
-                    t.r[nt] = pe[(2 * MT * NT + nt) * 64];
-                }
-                y = t;
-                break;
+                di++;
+                s = 0;
+                ysrc = Y_ELEM;
+                yidx = di - 1;
             }
         }
     }

@@ -63,6 +63,23 @@ class BatchInfo(ctypes.Structure):
 OP_ENCRYPT = 0
 OP_DECRYPT = 1
 
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int),
+                ("max_dispatch_ops", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_size_t), ("dispatches", ctypes.c_size_t), ("elapsed", ctypes.c_double),
+                ("p50_latency", ctypes.c_double), ("p99_latency", ctypes.c_double),
+                ("max_latency", ctypes.c_double), ("mean_dispatch_ops", ctypes.c_double),
+                ("peak_inflight_bytes", ctypes.c_size_t), ("peak_inflight", ctypes.c_int)]
+
+
+# layout of struct rsa_request
+REQUEST_DTYPE = np.dtype([("key", "<i4"), ("kind", "<i4"), ("inp", "<u8"), ("out", "<u8"), ("arrival", "<f8")],
+                         align=True)
+
 _P = ctypes.c_void_p
 _S = ctypes.c_size_t
 _I = ctypes.c_int
@@ -86,6 +103,9 @@ _SIGNATURES = {
     "rsa_batch_run": ([_P, _P], _I),
     "rsa_batch_info_get": ([_P, _P], _I),
     "rsa_batch_free": ([_P], None),
+    "rsa_server_create": ([_P, _S, _P, _P], _I),
+    "rsa_server_replay": ([_P, _P, _S, _P, _P], _I),
+    "rsa_server_free": ([_P], None),
     "rns_plan_create": ([_P, _S, _P, _P], _I),
     "rns_plan_free": ([_P], None),
     "rns_plan_info": ([_P, _P], _I),
@@ -108,6 +128,12 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError("librnsrsa.so not found at %s; build it with "
                           "`python -m paper_1305_3699_amd.build`" % LIB_PATH)
+    try:
+        # torch ships its own HIP runtime; load it first so the library binds
+        # to the same one (two runtimes in a process do not share devices)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     h = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in _SIGNATURES.items():
         f = getattr(h, name)
@@ -427,6 +453,52 @@ class RsaBatch:
     def close(self):
         if getattr(self, "_h", None):
             lib().rsa_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RsaServer:
+    """Request server over resident keys (rsa_server_*): continuous batching
+    of RSA operations admitted by device-memory budget."""
+
+    def __init__(self, keys, hbm_budget: int = 0, max_inflight: int = 0, max_dispatch_ops: int = 0):
+        self._keys = list(keys)
+        arr = (ctypes.c_void_p * len(self._keys))(*[k._h.value for k in self._keys])
+        o = ServerOpts(hbm_budget, max_inflight, max_dispatch_ops)
+        h = ctypes.c_void_p()
+        _check(lib().rsa_server_create(arr, len(self._keys), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def replay(self, key_index, kind, arrival, messages: np.ndarray):
+        """Open-loop replay.  key_index, kind, arrival (seconds, non-decreasing):
+        length-n sequences; messages: uint32 [n, W] host array, row i holding
+        request i's input in its first n_limbs(key) limbs.  Returns (outputs
+        [n, W] uint32, latency [n] seconds, stats dict)."""
+        n = len(key_index)
+        msgs = np.ascontiguousarray(messages, dtype=np.uint32)
+        outs = np.zeros_like(msgs)
+        req = np.zeros(n, dtype=REQUEST_DTYPE)
+        req["key"] = np.asarray(key_index, dtype=np.int32)
+        req["kind"] = np.asarray(kind, dtype=np.int32)
+        req["arrival"] = np.asarray(arrival, dtype=np.float64)
+        stride = msgs.strides[0]
+        req["inp"] = msgs.ctypes.data + stride * np.arange(n, dtype=np.uint64)
+        req["out"] = outs.ctypes.data + stride * np.arange(n, dtype=np.uint64)
+        lat = np.zeros(n, dtype=np.float64)
+        st = ServerStats()
+        _check(lib().rsa_server_replay(self._h, req.ctypes.data_as(ctypes.c_void_p), n,
+                                       lat.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in ServerStats._fields_}
+        return outs, lat, stats
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rsa_server_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -84,10 +84,25 @@ def test_edge_exponents():
     L = 25
     ctx = _ctx(N, L, window=3)
     bases = [0, 1, 2, N - 1, N, N + 1, (1 << (32 * L)) - 1] + [rng.getrandbits(32 * L) for _ in range(9)]
-    for e in (0, 1, 2, 3, 8, 65537, (1 << 64) - 1):
+    for e in (0, 1, 2, 3, 8, 65537, (1 << 64) - 1, (1 << 33) | (1 << 31) | 1, (1 << 63) | (1 << 32) | (1 << 30)):
         el = gen.to_limbs(e, 2)[0]
         got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
         assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases], e
+
+
+@pytest.mark.parametrize("window", [2, 5, 6])
+def test_windows_across_limbs(window):
+    """Sliding windows that straddle two exponent limbs, the lower one with
+    its top bit set (read back as a signed value it would corrupt the
+    window)."""
+    rng = random.Random(window)
+    N = rng.getrandbits(512) | (1 << 511) | 1
+    ctx = _ctx(N, 16, window=window)
+    bases = [rng.getrandbits(512) for _ in range(40)]
+    limbs = [rng.getrandbits(32) | (1 << 31) for _ in range(6)]
+    e = sum(v << (32 * i) for i, v in enumerate(limbs))
+    got = _run_modexp(ctx, gen.to_limbs(bases, 16), gen.to_limbs(e, 6)[0])
+    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
 
 
 def test_per_element_exponents():
@@ -182,6 +197,28 @@ def test_mont_mul_matches_definition():
     out = _host(ctx.mont_mul(_dev(res(X)), _dev(res(Y))))
     want = res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)])
     assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("k", [97, 129])
+def test_mont_mul_3072_bit(k):
+    """The standalone product at the modulus size of the modular
+    multiplication benchmark (3072 bits), with 97 and 129 channels."""
+    rng = random.Random(k)
+    N = rng.getrandbits(3072) | (1 << 3071) | 1
+    ctx = _ctx(N, 96, k=k)
+    assert ctx.info["k"] == k
+    pr = ctx.primes
+    B, Bp = pr[:k], pr[k:]
+    n = 70
+    X = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [(k + 1) * N - 1]
+    Y = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [0]
+
+    def res(vals):
+        return np.array([[v % m for v in vals] for m in B] + [[v % m for v in vals] for m in Bp]
+                        + [[v % (1 << 32) for v in vals]], dtype=np.uint32)
+
+    out = _host(ctx.mont_mul(_dev(res(X)), _dev(res(Y))))
+    assert np.array_equal(out, res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)]))
 
 
 def test_rsa1024_config_bit_exact():
@@ -338,3 +375,48 @@ def test_batched_mixed_sizes(use_graph, autotune):
             assert np.array_equal(got, want), (rep, o)
             assert np.array_equal(alone, got)
     b.close()
+
+
+def test_served_continuous_batching():
+    """Request server: a Poisson trace over resident keys of 1024-4096 bits
+    (70% CRT decryptions) with continuous batching; every result equals the
+    oracle's and, for a sample, the same request run alone."""
+    from paper_1305_3699_amd import RnsError, RsaKey, RsaServer
+    per = 2
+    specs = gen.served_keys(per_size=per)
+    keys = gen.rsa_keys(specs, processes=8)
+    rks = [RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv) for k in keys]
+    arrival, kidx, kind, seeds = gen.served_trace(20000.0, 0.08, per_size=per)
+    n = arrival.size
+    W = 128
+    msgs = np.zeros((n, W), np.uint32)
+    for i in range(n):
+        k = keys[kidx[i]]
+        msgs[i, :k.n.bit_length() // 32] = gen.to_limbs(gen.uniform_below_fast(k.n, int(seeds[i])), k.n.bit_length() // 32)[0]
+    srv = RsaServer(rks, max_inflight=4)
+    outs, lat, stats = srv.replay(kidx, kind, arrival, msgs)
+    assert stats["completed"] == n and stats["dispatches"] >= 1
+    assert np.all(lat > 0) and stats["p99_latency"] >= stats["p50_latency"] > 0
+    for j, k in enumerate(keys):
+        L = k.n.bit_length() // 32
+        for kd in (0, 1):
+            sel = np.nonzero((kidx == j) & (kind == kd))[0]
+            if sel.size == 0:
+                continue
+            x = np.ascontiguousarray(msgs[sel, :L])
+            want = (oracle.modexp_batch(x, gen.to_limbs(k.e, 1)[0], gen.to_limbs(k.n, L)[0]) if kd == 0
+                    else oracle.rsa_crt_batch(x, k.p, k.q, k.dp, k.dq, k.qinv))
+            assert np.array_equal(outs[sel, :L], want), (j, kd)
+            assert not outs[sel, L:].any()
+    for i in random.Random(3).sample(range(n), 24):
+        k, rk = keys[kidx[i]], rks[kidx[i]]
+        L = k.n.bit_length() // 32
+        one = _dev(msgs[i:i + 1, :L])
+        alone = _host(rk.encrypt(one) if kind[i] == 0 else rk.decrypt(one, use_crt=True))
+        assert np.array_equal(alone[0], outs[i, :L])
+    # admission: a budget below one request is refused; a small one still completes
+    with pytest.raises(RnsError):
+        RsaServer(rks, hbm_budget=1024).replay(kidx[:4], kind[:4], arrival[:4], msgs[:4])
+    small = RsaServer(rks, hbm_budget=64 << 20, max_inflight=2)
+    outs2, _, st2 = small.replay(kidx[:300], kind[:300], arrival[:300], msgs[:300])
+    assert np.array_equal(outs2, outs[:300]) and st2["peak_inflight_bytes"] <= 64 << 20

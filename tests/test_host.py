@@ -212,3 +212,14 @@ def test_emul_zero_residue_bases(bits, engine):
     for e in (1, 2, 65537):
         out = p.emul_modexp(gen.to_limbs(bases, L), gen.to_limbs(e, 1)[0])
         assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]
+
+
+def test_batch_and_server_argument_errors():
+    import ctypes
+    lib = rnsrsa.lib()
+    h = ctypes.c_void_p()
+    assert lib.rsa_server_create(None, 0, None, ctypes.byref(h)) == -1          # no keys
+    assert lib.rsa_batch_create(None, 0, None, None, None) == -1                # null handle
+    op = rnsrsa.RsaOp(None, 0, None, None, 1)
+    assert lib.rsa_batch_create(ctypes.byref(op), 1, None, None, ctypes.byref(h)) == -1   # null key
+    assert rnsrsa.REQUEST_DTYPE.itemsize == 32

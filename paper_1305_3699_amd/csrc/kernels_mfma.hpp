@@ -103,6 +103,17 @@ __device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, N
     }
 }
 
+// LDS column of the digit of slot (wave, mt, lane group g): its channel, or
+// for the redundant slot and channels >= K one of the four columns after the
+// last k-step, which the matrix cores never read (so the store needs no mask).
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ int mfma_digit_col(int wave, int mt, int g) {
+    using S = MShp<K, W, MT, NT>;
+    const int ch = wave * S::CH + 4 * mt + g;
+    const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+    return real ? ch : S::LY.KCH() + (wave & 3);
+}
+
 // Step (i) of a product: quotient digits xi = x y c_i of the B slots,
 // published as the B operand of the first extension.
 template <int K, int W, int MT, int NT>
@@ -113,13 +124,12 @@ __device__ __forceinline__ void mfma_publish_xi(const MConst<MT, MShp<K, W, MT, 
     const int g = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
-        const int ch = wave * S::CH + 4 * mt + g;
-        const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+        const int col = mfma_digit_col<K, W, MT, NT>(wave, mt, g);
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
             const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], C.mB[mt], C.uB[mt]);   // x y 2^32
             const uint32_t xi = mulredc(t, C.cB[mt], C.mB[mt], C.uB[mt]);              // x y c_i
-            if (real) buf1[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xi);
+            buf1[(16 * nt + (lane & 15)) * S::BROW + col] = mfma_pack(xi);
         }
     }
 }
@@ -160,8 +170,7 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
     // (iii) r = (XY + q^'' N)/M in B'; publish xi' for the second extension
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
-        const int ch = wave * S::CH + 4 * mt + g;
-        const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+        const int col = mfma_digit_col<K, W, MT, NT>(wave, mt, g);
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
             const uint32_t m = C.mP[mt];
@@ -171,7 +180,7 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
             r = (ov || r >= m) ? r - m : r;
             x.p[mt][nt] = r;
             const uint32_t xip = mulredc(r, C.HP[mt], m, C.uP[mt]);                     // r (M'_t)^-1
-            if (real) buf2[(16 * nt + (lane & 15)) * S::BROW + ch] = mfma_pack(xip);
+            buf2[(16 * nt + (lane & 15)) * S::BROW + col] = mfma_pack(xip);
         }
     }
 #pragma unroll

@@ -527,7 +527,7 @@ def main(argv=None) -> int:
     ap.add_argument("--served-rates", type=float, nargs="+", default=[5000.0, 20000.0, 80000.0])
     ap.add_argument("--served-duration", type=float, default=10.0)
     ap.add_argument("--served-warmup", type=float, default=1.0)
-    ap.add_argument("--served-inflight", type=int, default=4)
+    ap.add_argument("--served-inflight", type=int, default=8)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one elementwise copy of N MiB before the benchmark (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -293,8 +293,12 @@ void rsa_batch_free(rsa_batch *b);
  *
  *   rsa_server_opts  hbm_budget: device bytes in-flight dispatches may hold
  *                    (0 = 64 GiB); max_inflight: concurrent dispatches
- *                    (0 = 4); max_dispatch_ops: requests per dispatch
+ *                    (0 = 8); max_dispatch_ops: requests per dispatch
  *                    (0 = 16384).
+ * A dispatch holds requests of one kernel-shape class (the base size k of
+ * their exponentiations), so short requests never wait for long ones in the
+ * same dispatch; a free slot goes to the class whose oldest pending request
+ * arrived first.
  *   rsa_request      one RSA operation on key `key` (an index into the
  *                    server's key list): in and out are HOST buffers of
  *                    n_limbs(key) limbs; out is written when it completes.

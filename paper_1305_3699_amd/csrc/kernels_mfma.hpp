@@ -44,7 +44,13 @@ struct MShp {
     }
     static constexpr int EXIT_WORDS = (K + 2 * (K + 1)) * NM;
     static constexpr int BUF_WORDS = 2 * NM * BROW;
-    static constexpr int LDS_WORDS = EXIT_WORDS > BUF_WORDS ? EXIT_WORDS : BUF_WORDS;
+    static constexpr int WORK_WORDS = EXIT_WORDS > BUF_WORDS ? EXIT_WORDS : BUF_WORDS;
+    // 16-element tiles keep the second extension's constant tiles (the same
+    // for every key of the base pair) in LDS rather than registers, which
+    // lets 3 waves share a SIMD; 32-element tiles keep them in registers
+    static constexpr bool A2_LDS = NT == 1;
+    static constexpr int A2_WORDS = A2_LDS ? W * MT * KSTEPS * 64 * 4 : 0;
+    static constexpr int LDS_WORDS = WORK_WORDS + A2_WORDS;
 };
 
 template <int MT, int NT>
@@ -58,6 +64,7 @@ struct MState {
 template <int MT, int KSTEPS>
 struct MConst {
     mfma_v4i A1[MT][KSTEPS], A2[MT][KSTEPS];
+    const mfma_v4i *a2lds;   // the wave's second-extension tiles in LDS, [MT][KSTEPS][64]
     uint32_t mB[MT], uB[MT], nuB[MT], cB[MT];
     uint32_t mP[MT], uP[MT], HP[MT];
     uint32_t Mpinv_r, Minv_r, N_r;
@@ -97,7 +104,8 @@ __device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, N
                 *(const mfma_v4i *)(buf + (16 * nt + (lane & 15)) * S::BROW + 16 * ks + 4 * (lane >> 4));
 #pragma unroll
             for (int mt = 0; mt < MT; mt++)
-                D[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(second ? C.A2[mt][ks] : C.A1[mt][ks], bop,
+                D[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                    second ? (S::A2_LDS ? C.a2lds[(mt * S::KSTEPS + ks) * 64 + lane] : C.A2[mt][ks]) : C.A1[mt][ks], bop,
                                                                    D[mt][nt], 0, 0, 0);
         }
     }
@@ -328,7 +336,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         for (int ks = 0; ks < S::KSTEPS; ks++) {
             const size_t ti = ((sl * S::KSTEPS + ks) * 64 + lane) * 4;
             C.A1[mt][ks] = *(const mfma_v4i *)(mk + S::LY.a1() + ti);
-            C.A2[mt][ks] = *(const mfma_v4i *)(mb + S::LY.a2() + ti);
+            if (!S::A2_LDS) C.A2[mt][ks] = *(const mfma_v4i *)(mb + S::LY.a2() + ti);
         }
         C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
         C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
@@ -338,6 +346,14 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         C.HP[mt] = mb[S::LY.slotP() + (sl * 4 + 2) * 64 + lane];
         C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
 
+    }
+    if (S::A2_LDS) {
+        // each wave copies its own tiles; it alone reads them, so program
+        // order suffices (no barrier)
+        mfma_v4i *dst = (mfma_v4i *)(lds + S::WORK_WORDS) + (size_t)wave * MT * S::KSTEPS * 64;
+        const mfma_v4i *src = (const mfma_v4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
+        for (int i = lane; i < MT * S::KSTEPS * 64; i += 64) dst[i] = src[i];
+        C.a2lds = dst;
     }
     C.Mpinv_r = mb[S::LY.bscal() + 0];
     C.Minv_r = mb[S::LY.bscal() + 1];

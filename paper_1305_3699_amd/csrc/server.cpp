@@ -15,7 +15,9 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <deque>
 #include <thread>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -70,6 +72,16 @@ size_t op_bytes(const rsa_key *k, int kind, size_t count) {
     // job descriptors, plus the alignment of the arena's regions (inputs,
     // outputs, CRT scratch, one table per group, job tables: at most 6 per op)
     return words * sizeof(uint32_t) + 2 * sizeof(MJob) + 6 * kAlign;
+}
+
+// Kernel-shape class of a request: the context its exponentiations run on
+// (the p-half for a CRT decryption).  Requests of one class have similar
+// costs and share launches; classes are dispatched separately so that short
+// requests do not wait for long ones.
+std::tuple<int, int, int, int> request_class(const rsa_key *k, int kind) {
+    const rns_ctx *c = (kind == RSA_OP_DECRYPT && k->has_crt) ? k->p : k->n;
+    if (c->engine != RNS_ENGINE_MATRIX) return std::make_tuple(-c->plan.base->K, 0, 0, c->engine);
+    return std::make_tuple(c->mshape.K, c->mshape.W, c->mshape.MT, c->engine);
 }
 
 double now_s(std::chrono::steady_clock::time_point t0) {
@@ -242,7 +254,7 @@ int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_serve
     }
     if (opts && opts->hbm_budget) s->budget = opts->hbm_budget;
     if (opts && opts->max_dispatch_ops) s->max_ops = opts->max_dispatch_ops;
-    const int inflight = (opts && opts->max_inflight > 0) ? opts->max_inflight : 4;
+    const int inflight = (opts && opts->max_inflight > 0) ? opts->max_inflight : 8;
     if (inflight > 32) return fail(RNS_EINVAL, "max_inflight above 32");
     configure_pool_once();
     s->slots.resize((size_t)inflight);
@@ -272,8 +284,16 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
         if (need[i] > srv->budget) return fail(RNS_EINVAL, "a request exceeds the device-memory budget");
     }
     std::vector<double> lat(n, 0.0);
-    std::vector<size_t> pending;
-    size_t head = 0;  // first pending request not yet dispatched
+    // pending requests, one FIFO per kernel-shape class
+    std::map<std::tuple<int, int, int, int>, int> class_id;
+    std::vector<int> cls(n);
+    for (size_t i = 0; i < n; i++) {
+        auto c = request_class(srv->keys[(size_t)reqs[i].key], reqs[i].kind);
+        auto it = class_id.emplace(c, (int)class_id.size()).first;
+        cls[i] = it->second;
+    }
+    std::vector<std::deque<size_t>> pending(class_id.size());
+    size_t n_pending = 0;
     size_t next = 0, done = 0, dispatches = 0, ops_sum = 0, inflight_bytes = 0, peak_bytes = 0;
     int inflight = 0, peak_inflight = 0;
     const auto t0 = std::chrono::steady_clock::now();
@@ -282,7 +302,11 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
     while (done < n) {
         bool progress = false;
         const double now = now_s(t0);
-        while (next < n && reqs[next].arrival <= now) pending.push_back(next++);
+        while (next < n && reqs[next].arrival <= now) {
+            pending[(size_t)cls[next]].push_back(next);
+            next++;
+            n_pending++;
+        }
         // retire finished dispatches
         for (Slot &sl : srv->slots) {
             if (!sl.busy) continue;
@@ -306,8 +330,9 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
             progress = true;
         }
         if (rc) break;
-        // admit pending requests into a free slot, within the budget
-        if (head < pending.size()) {
+        // admit pending requests of one class into a free slot, within the
+        // budget: the class whose oldest pending request arrived first
+        if (n_pending) {
             Slot *free_slot = nullptr;
             for (Slot &sl : srv->slots)
                 if (!sl.busy) {
@@ -315,11 +340,17 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
                     break;
                 }
             if (free_slot) {
+                size_t c_best = pending.size();
+                for (size_t c = 0; c < pending.size(); c++)
+                    if (!pending[c].empty() &&
+                        (c_best == pending.size() || pending[c].front() < pending[c_best].front()))
+                        c_best = c;
+                std::deque<size_t> &q = pending[c_best];
                 // per (key, kind) request counts decide the bytes of a dispatch
                 std::map<std::pair<int, int>, size_t> counts;
                 size_t bytes = 0, take = 0;
-                while (head + take < pending.size() && take < srv->max_ops) {
-                    const rsa_request &r = reqs[pending[head + take]];
+                while (take < q.size() && take < srv->max_ops) {
+                    const rsa_request &r = reqs[q[take]];
                     auto k = std::make_pair(r.key, r.kind);
                     const size_t c = counts[k];
                     const rsa_key *key = srv->keys[(size_t)r.key];
@@ -330,9 +361,10 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
                     take++;
                 }
                 if (take) {
-                    std::vector<size_t> ids(pending.begin() + (long)head, pending.begin() + (long)(head + take));
+                    std::vector<size_t> ids(q.begin(), q.begin() + (long)take);
                     if ((rc = dispatch(srv, *free_slot, reqs, ids))) break;
-                    head += take;
+                    q.erase(q.begin(), q.begin() + (long)take);
+                    n_pending -= take;
                     dispatches++;
                     ops_sum += take;
                     inflight++;
@@ -342,10 +374,6 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
                     progress = true;
                 }
             }
-        }
-        if (head == pending.size() && head > 4096) {  // keep the pending list short
-            pending.clear();
-            head = 0;
         }
         if (!progress) {
             // spin while work is in flight or an arrival is near; otherwise sleep

@@ -312,13 +312,15 @@ def test_long_exponents_2048_bit_modulus(ebits):
     assert np.array_equal(got[idx], want)
 
 
-@pytest.mark.parametrize("bits", [3072, 4096])
-def test_rsa_crt_3072_4096_batch_4096(bits):
-    """RSA-3072 and RSA-4096 CRT decryption, 4096 ciphertexts each: sampled
-    rows against the oracle's CRT path, every row by re-encryption."""
+@pytest.mark.parametrize("bits,group", [(3072, 16), (3072, 32), (4096, 16), (4096, 32)])
+def test_rsa_crt_3072_4096_batch_4096(bits, group):
+    """RSA-3072 and RSA-4096 CRT decryption, 4096 ciphertexts each, with both
+    workgroup tiles: sampled rows against the oracle's CRT path, every row by
+    re-encryption."""
     from paper_1305_3699_amd import RsaKey
     key = gen.rsa_key(bits, seed=gen.config_seed(3, 10 + bits // 1024))
-    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv)
+    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, group=group)
+    assert rk.info(1)["group"] == group
     L = bits // 32
     B = 4096
     c = gen.uniform_below(key.n, B, seed=gen.config_seed(3, 20 + bits // 1024))
@@ -420,3 +422,16 @@ def test_served_continuous_batching():
     small = RsaServer(rks, hbm_budget=64 << 20, max_inflight=2)
     outs2, _, st2 = small.replay(kidx[:300], kind[:300], arrival[:300], msgs[:300])
     assert np.array_equal(outs2, outs[:300]) and st2["peak_inflight_bytes"] <= 64 << 20
+
+
+@pytest.mark.parametrize("group", [16, 32])
+def test_rsa1024_crt_both_tiles(group):
+    """RSA-1024 CRT decryption (k = 17 halves) with both workgroup tiles."""
+    from paper_1305_3699_amd import RsaKey
+    key = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
+    rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, group=group)
+    assert rk.info(1)["group"] == group and rk.info(1)["k"] == 17
+    c = gen.uniform_below(key.n, 300, seed=21) + [0, 1, key.n - 1]
+    cl = gen.to_limbs(c, 32)
+    got = _host(rk.decrypt(_dev(cl), use_crt=True))
+    assert np.array_equal(got, oracle.rsa_crt_batch(cl, key.p, key.q, key.dp, key.dq, key.qinv))

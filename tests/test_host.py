@@ -171,9 +171,9 @@ def test_group_selection():
     for g in (16, 32):
         p = Plan(N, 32, group=g)
         assert p.info["engine"] == rnsrsa.ENGINE_MATRIX and p.info["group"] == g
-    assert Plan(N, 32).info["group"] == 32                           # default tile for k = 33
-    big = (1 << 2047) + 4095
-    assert Plan(big, 64, group=16).info["group"] == 32               # no 16-element kernel for k = 65
+    assert Plan(N, 32).info["group"] == 16                           # default tile for k = 33
+    big = (1 << 4095) + 4095
+    assert Plan(big, 128, group=16).info["group"] == 32              # no 16-element kernel for k = 129
 
 
 @pytest.mark.parametrize("group", [16, 32])

@@ -506,6 +506,49 @@ def run_modmul_sweep(args) -> list:
     return lines
 
 
+def run_tile_sweep(args) -> list:
+    """Both workgroup tiles of the matrix-core kernel (16 and 32 elements) and
+    the library's automatic per-launch choice, for every base size the library
+    builds a kernel for, timed on batches of exponentiations by a full-length
+    exponent modulo a seeded odd modulus of the size that selects that base
+    (512 .. 4096 bits: the CRT halves of RSA-1024 .. RSA-8192, or the whole
+    modulus of RSA-3072 / RSA-4096 with a private-size exponent), at three
+    batch sizes each.  One line per (k, batch)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1305_3699_amd import RnsContext
+
+    lines = []
+    for bits, B in ((512, 16384), (1024, 16384), (1536, 8192), (2048, 8192), (3072, 4096), (4096, 4096)):
+        rng = random.Random(gen.config_seed(7, bits))
+        N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+        L = bits // 32
+        e = gen.random_exponent(bits, seed=gen.config_seed(7, bits + 1))
+        el = torch.from_numpy(gen.to_limbs(e, L)[0].view(np.int32)).cuda()
+        x64 = torch.from_numpy(gen.to_limbs([rng.getrandbits(bits - 1) for _ in range(64)], L)
+                               .view(np.int32)).cuda()
+        ctxs = {g: RnsContext(N, L, group=g, window=6) for g in (16, 32, 0)}
+        for batch in (B // 2, B, 2 * B):
+            x = x64.repeat(batch // 64, 1).contiguous()
+            out = torch.empty_like(x)
+            row = {"modulus_bits": bits, "k": ctxs[0].info["k"], "batch": batch}
+            for g, ctx in ctxs.items():
+                ctx.modexp(x, el, out=out)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(args.tile_reps):
+                    ctx.modexp(x, el, out=out)
+                b.record()
+                torch.cuda.synchronize()
+                row["ms_%s" % (g or "auto")] = round(a.elapsed_time(b) / args.tile_reps, 3)
+            print("tiles %s" % json.dumps(row), file=sys.stderr, flush=True)
+            lines.append(row)
+    return lines
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -524,6 +567,9 @@ def main(argv=None) -> int:
                     help="only the 3072-bit modular multiplication sweep (one JSON line per base size)")
     ap.add_argument("--modmul-batches", type=int, nargs="+",
                     default=[16, 64, 256, 1024, 4096, 16384, 65536])
+    ap.add_argument("--tile-sweep", action="store_true",
+                    help="only the timing of both workgroup tiles per base size (one JSON line per k)")
+    ap.add_argument("--tile-reps", type=int, default=3)
     ap.add_argument("--served-rates", type=float, nargs="+", default=[5000.0, 20000.0, 80000.0])
     ap.add_argument("--served-duration", type=float, default=10.0)
     ap.add_argument("--served-warmup", type=float, default=1.0)
@@ -542,6 +588,10 @@ def main(argv=None) -> int:
         return 2
     if args.modmul_sweep:
         for line in run_modmul_sweep(args):
+            print(json.dumps(line), flush=True)
+        return 0
+    if args.tile_sweep:
+        for line in run_tile_sweep(args):
             print(json.dumps(line), flush=True)
         return 0
     if args.sweep_window:

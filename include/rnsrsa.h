@@ -83,8 +83,11 @@ enum rns_prime_range {
  *   engine      rns_engine (0 = auto).  rns_mont_mul_batch and the Garner
  *               step of CRT decryption always use the channel kernels.
  *   group       matrix-core engine: preferred elements per workgroup, 16 or
- *               32 (0 = default for k); a k without a kernel of that size
- *               uses its default.  rns_info.group reports the size in use.
+ *               32, used by every launch (a k without a kernel of that size
+ *               uses its default).  0: the default for k, except that a
+ *               launch too small to give the GPU 1.5 resident waves per SIMD
+ *               with 32-element workgroups takes 16-element ones.
+ *               rns_info.group reports the requested or default size.
  * Both bases hold k primes; with the redundant channel 2^32 an operand has
  * 2k+1 residues.  A base pair is accepted for modulus N of L limbs when
  *   M >= (k+1)^2 N,  M >= 2^(32L+1),  M' >= (k+1) N,  gcd(N, M) = 1,
@@ -241,7 +244,9 @@ int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t
  * Tuning (rsa_batch_opts, NULL = defaults):
  *   autotune     1: for each kernel shape class, time the candidate tiles
  *                (elements per workgroup) on the device at creation and keep
- *                the faster (cached per process); 0: default tiles.
+ *                the faster (cached per process); 0: each launch's tile
+ *                chosen as for rns_opts.group = 0 (keys set up with an
+ *                explicit group keep it).
  *   use_graph    1: capture into a hipGraph at creation (default 1; not
  *                used when some key runs on the channel engine).
  *   window       0: per job, the window width minimising the number of

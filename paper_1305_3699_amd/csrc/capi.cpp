@@ -181,6 +181,7 @@ int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx *
         std::vector<uint32_t> Em = make_mfma_entry_table(c->plan, c->mshape, {c->plan.R2}, c->plan.L);
         if ((rc = upload(Em, &c->d_mentry))) return rc;
     }
+    c->group_req = group;
     *out = c.release();
     return RNS_OK;
 }
@@ -199,6 +200,27 @@ namespace rnsrsa {
 namespace api {
 
 // Launch one or two exponentiation jobs sharing the inputs.
+MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev) {
+    static std::mutex mu;
+    static std::map<int, int> simds_of;
+    if (sh.NT != 2) return sh;
+    MfmaShape alt;
+    if (!mfma_shape_for(sh.K, alt, 16) || alt.NT != 1 || alt.W != sh.W || alt.MT != sh.MT) return sh;
+    int simds = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = simds_of.find(dev);
+        if (it == simds_of.end()) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                return sh;
+            it = simds_of.emplace(dev, 4 * cus).first;
+        }
+        simds = it->second;
+    }
+    return 2 * tiles * (size_t)sh.W < 3 * (size_t)simds ? alt : sh;
+}
+
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
                uint32_t *out1, int out_stride, size_t batch, hipStream_t s) {
@@ -214,7 +236,8 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
     P.window = c0->window;
     P.batch = (int)batch;
     if (c0->engine == RNS_ENGINE_MATRIX) {
-        const MLayout &sh = c0->mshape;
+        MfmaShape sh = c0->mshape;
+        if (!c0->group_req) sh = auto_tile(sh, (size_t)mfma_tiles(sh, batch) * njobs, c0->device);
         ModexpMfmaLaunch a{};
         const int per_job = mfma_tiles(sh, batch);
         for (int j = 0; j < njobs; j++) {

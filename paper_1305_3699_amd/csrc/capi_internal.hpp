@@ -47,7 +47,8 @@ struct rns_ctx {
     uint32_t *d_mod = nullptr;
     uint32_t *d_entry = nullptr;  // entry table for L-limb inputs (factor M^2 mod N)
     // matrix-core engine
-    rnsrsa::MfmaShape mshape{};
+    rnsrsa::MfmaShape mshape{};  // default tile
+    int group_req = 0;            // tile asked for at set-up (0: chosen per launch)
     uint32_t *d_mbase = nullptr;  // shared, owned by the process-wide cache
     uint32_t *d_mkey = nullptr;
     uint32_t *d_mentry = nullptr;
@@ -93,6 +94,13 @@ namespace api {
 const uint32_t *entry_of(const rns_ctx *c);
 // Garner recombination of [m_p | m_q] rows into m (n_limbs limbs).
 int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s);
+// Tile of one matrix-core launch of `tiles` workgroups of shape sh on device
+// dev: the 16-element tile of the same (K, W, MT) instead of the 32-element one
+// when the latter would leave fewer than 1.5 resident waves per SIMD.  Below
+// that the smaller tile's shorter per-wave work (and twice the workgroups)
+// wins; above it the 32-element tile's shared constant loads do (measured for
+// k = 17 .. 129).  Shapes without that alternative are returned unchanged.
+MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev);
 // One or two exponentiation jobs sharing their inputs (the plain launch).
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,

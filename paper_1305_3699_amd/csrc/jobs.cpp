@@ -95,12 +95,19 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             P.groups.emplace_back();
             JobGroup &g = P.groups.back();
             g.shape = sh;
+            g.device = c->device;
             if (const int nt = tuned_nt(sh)) {
                 MfmaShape t;
                 if (mfma_shape_for(sh.K, t, 16 * nt) && t.W == sh.W && t.MT == sh.MT && t.NT == nt) g.shape = t;
+                g.auto_tile = false;
             }
         }
-        P.groups[it->second].jobs.push_back(J);
+        JobGroup &g = P.groups[it->second];
+        if (c->group_req) {
+            g.auto_tile = false;
+            if (!tuned_nt(sh)) g.shape = sh;
+        }
+        g.jobs.push_back(J);
     };
     for (const PlannedOp &o : ops) {
         if (!o.key || (o.kind != RSA_OP_ENCRYPT && o.kind != RSA_OP_DECRYPT)) return fail(RNS_EINVAL, "bad operation");
@@ -136,7 +143,15 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             }
         }
     }
-    for (JobGroup &g : P.groups) finish_group(g);
+    for (JobGroup &g : P.groups) {
+        finish_group(g);
+        if (!g.auto_tile) continue;
+        const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, g.device);
+        if (t.NT != g.shape.NT) {
+            g.shape = t;
+            finish_group(g);
+        }
+    }
     return RNS_OK;
 }
 

@@ -41,6 +41,8 @@ struct PlannedJob {
 // Jobs of one matrix-core kernel shape: one launch.
 struct JobGroup {
     MLayout shape{};
+    bool auto_tile = true;  // no context asked for a tile and none was tuned
+    int device = 0;
     std::vector<PlannedJob> jobs;
     int tiles = 0;
     int max_window = 1;
@@ -75,7 +77,8 @@ struct JobPlan {
 // CRT scratch words an operation needs (0 unless a CRT decryption).
 size_t op_mpq_words(const rsa_key *key, int kind, size_t count);
 // Jobs of `ops`, grouped by kernel shape (tile: the per-process tuned one for
-// the shape class if any, else the context's), each group's tiles ordered by
+// the shape class if any, else the contexts' if they asked for one, else the
+// one auto_tile picks for the group's size), each group's tiles ordered by
 // decreasing cost.  Validates the operations (RNS_EINVAL).
 int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_window, JobPlan &out);
 // Assign tile0 in cost order and max_window for a group with its final shape.

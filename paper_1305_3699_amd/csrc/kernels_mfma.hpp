@@ -45,11 +45,20 @@ struct MShp {
     static constexpr int EXIT_WORDS = (K + 2 * (K + 1)) * NM;
     static constexpr int BUF_WORDS = 2 * NM * BROW;
     static constexpr int WORK_WORDS = EXIT_WORDS > BUF_WORDS ? EXIT_WORDS : BUF_WORDS;
-    // 16-element tiles keep the second extension's constant tiles (the same
-    // for every key of the base pair) in LDS rather than registers, which
-    // lets 3 waves share a SIMD; 32-element tiles keep them in registers
-    static constexpr bool A2_LDS = NT == 1;
-    static constexpr int A2_WORDS = A2_LDS ? W * MT * KSTEPS * 64 * 4 : 0;
+    // Where the second extension's constant tiles (the same for every key of
+    // the base pair) live: registers for 32-element tiles with few k-steps;
+    // LDS for 16-element tiles (3 waves then share a SIMD) and wherever the
+    // registers would overflow while the tiles still fit LDS; otherwise they
+    // are read from global memory (L2) at each step.
+    static constexpr int A2_TILE_WORDS = W * MT * KSTEPS * 64 * 4;
+    static constexpr bool A2_FITS_LDS = (EXIT_WORDS > BUF_WORDS ? EXIT_WORDS : BUF_WORDS) + A2_TILE_WORDS <= 36 * 1024;
+    static constexpr bool A2_GLOBAL = KSTEPS > 5 || (KSTEPS == 5 && !A2_FITS_LDS);
+    static constexpr bool A2_LDS = !A2_GLOBAL && (NT == 1 || KSTEPS >= 5);
+    // the per-key first-extension tiles follow the second ones to global
+    // memory for those shapes (their workgroups of 9-12 waves leave 168
+    // registers per lane)
+    static constexpr bool A1_GLOBAL = A2_GLOBAL;
+    static constexpr int A2_WORDS = A2_LDS ? A2_TILE_WORDS : 0;
     static constexpr int LDS_WORDS = WORK_WORDS + A2_WORDS;
 };
 
@@ -64,7 +73,8 @@ struct MState {
 template <int MT, int KSTEPS>
 struct MConst {
     mfma_v4i A1[MT][KSTEPS], A2[MT][KSTEPS];
-    const mfma_v4i *a2lds;   // the wave's second-extension tiles in LDS, [MT][KSTEPS][64]
+    const mfma_v4i *a2lds;   // the wave's second-extension tiles in LDS or global memory, [MT][KSTEPS][64]
+    const mfma_v4i *a1mem;   // its first-extension tiles in global memory (A1_GLOBAL shapes)
     uint32_t mB[MT], uB[MT], nuB[MT], cB[MT];
     uint32_t mP[MT], uP[MT], HP[MT];
     uint32_t Mpinv_r, Minv_r, N_r;
@@ -105,9 +115,13 @@ __device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, N
 #pragma unroll
             for (int mt = 0; mt < MT; mt++)
                 D[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                    second ? (S::A2_LDS ? C.a2lds[(mt * S::KSTEPS + ks) * 64 + lane] : C.A2[mt][ks]) : C.A1[mt][ks], bop,
-                                                                   D[mt][nt], 0, 0, 0);
+                    second ? (S::A2_LDS || S::A2_GLOBAL ? C.a2lds[(mt * S::KSTEPS + ks) * 64 + lane] : C.A2[mt][ks])
+                           : (S::A1_GLOBAL ? C.a1mem[(mt * S::KSTEPS + ks) * 64 + lane] : C.A1[mt][ks]),
+                    bop, D[mt][nt], 0, 0, 0);
         }
+        // operands read from memory: keep at most one k-step of them in
+        // flight, or the scheduler hoists all of them and the registers spill
+        if (S::A1_GLOBAL) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -335,8 +349,8 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
 #pragma unroll
         for (int ks = 0; ks < S::KSTEPS; ks++) {
             const size_t ti = ((sl * S::KSTEPS + ks) * 64 + lane) * 4;
-            C.A1[mt][ks] = *(const mfma_v4i *)(mk + S::LY.a1() + ti);
-            if (!S::A2_LDS) C.A2[mt][ks] = *(const mfma_v4i *)(mb + S::LY.a2() + ti);
+            if (!S::A1_GLOBAL) C.A1[mt][ks] = *(const mfma_v4i *)(mk + S::LY.a1() + ti);
+            if (!S::A2_LDS && !S::A2_GLOBAL) C.A2[mt][ks] = *(const mfma_v4i *)(mb + S::LY.a2() + ti);
         }
         C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
         C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
@@ -355,6 +369,8 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         for (int i = lane; i < MT * S::KSTEPS * 64; i += 64) dst[i] = src[i];
         C.a2lds = dst;
     }
+    if (S::A2_GLOBAL) C.a2lds = (const mfma_v4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
+    if (S::A1_GLOBAL) C.a1mem = (const mfma_v4i *)(mk + S::LY.a1()) + (size_t)wave * MT * S::KSTEPS * 64;
     C.Mpinv_r = mb[S::LY.bscal() + 0];
     C.Minv_r = mb[S::LY.bscal() + 1];
     C.N_r = mk[S::LY.kscal() + 0];

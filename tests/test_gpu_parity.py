@@ -221,6 +221,24 @@ def test_mont_mul_3072_bit(k):
     assert np.array_equal(out, res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)]))
 
 
+@pytest.mark.parametrize("bits,group", [(3072, 16), (3072, 32), (4096, 16), (4096, 32)])
+def test_modexp_large_k_both_tiles(bits, group):
+    """Full-length exponents modulo 3072- and 4096-bit moduli (k = 97 and
+    129, whose matrix kernels read their constant tiles from global memory)
+    with both workgroup tiles: 70 bases = several tiles and a ragged tail."""
+    rng = random.Random(bits + group)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = bits // 32
+    ctx = _ctx(N, L, group=group)
+    assert ctx.info["k"] == {3072: 97, 4096: 129}[bits] and ctx.info["group"] == group
+    bases = [rng.getrandbits(32 * L) for _ in range(66)] + [0, 1, N - 1, (1 << (32 * L)) - 1]
+    e = rng.getrandbits(bits) | (1 << (bits - 1))
+    el = gen.to_limbs(e, L)[0]
+    got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
+    want = oracle.modexp_batch(gen.to_limbs(bases, L), el, gen.to_limbs(N, L)[0])
+    assert np.array_equal(got, want)
+
+
 def test_rsa1024_config_bit_exact():
     """One seeded RSA-1024 key, 64 messages, 64 encryptions and 64 plain
     decryptions with bases of 2 x 33 random 32-bit primes."""

@@ -143,7 +143,8 @@ namespace {
 
 // Engine for a plan: the matrix-core kernel when one exists for k (unless the
 // channel engine was asked for).
-int choose_engine(int K, int requested, int group, int *engine) {
+int choose_engine(const BaseSet &bs, int requested, int group, int *engine) {
+    const int K = bs.K;
     if (requested < 0 || requested > RNS_ENGINE_MATRIX) return fail(RNS_EINVAL, "bad engine");
     if (group != 0 && group != 16 && group != 32) return fail(RNS_EINVAL, "group must be 0, 16 or 32");
     if (requested == RNS_ENGINE_CHANNEL) {
@@ -151,11 +152,15 @@ int choose_engine(int K, int requested, int group, int *engine) {
         return RNS_OK;
     }
     MfmaShape sh;
-    if (mfma_shape_for(K, sh, group)) {
+    bool primes_ok = true;
+    for (uint32_t m : bs.Bp) primes_ok = primes_ok && m <= kMaxPrimeP;
+    if (mfma_shape_for(K, sh, group) && primes_ok) {
         *engine = RNS_ENGINE_MATRIX;
         return RNS_OK;
     }
-    if (requested == RNS_ENGINE_MATRIX) return fail(RNS_EUNSUPPORTED, "no matrix-core kernel for this k");
+    if (requested == RNS_ENGINE_MATRIX)
+        return fail(RNS_EUNSUPPORTED, primes_ok ? "no matrix-core kernel for this k"
+                                                : "matrix cores need every B' prime <= 2^32 - 2^18");
     *engine = RNS_ENGINE_CHANNEL;
     return RNS_OK;
 }
@@ -165,7 +170,7 @@ int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx *
     if (!c) return fail(RNS_ENOMEM, "out of host memory");
     c->plan = std::move(mp);
     c->window = window;
-    int rc = choose_engine(c->plan.base->K, engine_req, group, &c->engine);
+    int rc = choose_engine(*c->plan.base, engine_req, group, &c->engine);
     if (rc) return rc;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -594,7 +599,7 @@ int rns_plan_create(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts,
         if (rc) return fail(rc, err);
         p->window = window_or_default(opts);
         const int group = opts ? opts->group : 0;
-        if ((rc = choose_engine(p->plan.base->K, opts ? opts->engine : 0, group, &p->engine))) return rc;
+        if ((rc = choose_engine(*p->plan.base, opts ? opts->engine : 0, group, &p->engine))) return rc;
         if (p->engine == RNS_ENGINE_MATRIX) {
             MfmaShape sh;
             mfma_shape_for(p->plan.base->K, sh, group);

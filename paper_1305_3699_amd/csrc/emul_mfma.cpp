@@ -84,17 +84,14 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
     const int SW = 4 * ly.MT, NM = ly.NM(), KK = 64 * ly.KSTEPS(), BROW = ly.BROW(), K = c.K;
     const uint32_t Mpinv_r = c.T.base[ly.bscal()], Minv_r = c.T.base[ly.bscal() + 1], N_r = c.T.key[ly.kscal()];
     auto idx = [&](int w, int s, int e) { return ((size_t)w * SW + s) * NM + e; };
-    std::vector<uint32_t> a1(x.p.size());
     for (int w = 0; w < ly.W; w++)
         for (int s = 0; s < SW; s++) {
             const uint32_t m = c.slot(ly.slotB(), 3, 0, w, s), u = c.slot(ly.slotB(), 3, 1, w, s);
             const uint32_t ci = c.kslot(ly.slotC(), 1, 0, w, s);
-            const uint32_t mp = c.slot(ly.slotP(), 4, 0, w, s), up = c.slot(ly.slotP(), 4, 1, w, s);
             for (int e = 0; e < NM; e++) {
                 const uint32_t t = mulredc(x.b[idx(w, s, e)], y.b[idx(w, s, e)], m, u);
                 const uint32_t xi = mulredc(t, ci, m, u);
                 if (c.real(w, s)) dig1[(size_t)e * BROW + c.channel(w, s)] = pack_digits(xi);
-                a1[idx(w, s, e)] = mulredc(x.p[idx(w, s, e)], y.p[idx(w, s, e)], mp, up);
             }
         }
     std::vector<uint32_t> rr(NM);
@@ -109,9 +106,9 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
             const uint32_t H = c.slot(ly.slotP(), 4, 2, w, s);
             for (int e = 0; e < NM; e++) {
                 const int64_t S = extension(c.V1, ((size_t)w * SW + s) * KK, dig1, e, KK, BROW);
-                const uint32_t q = reduce_signed(S, m, u);
-                const uint64_t sum = (uint64_t)a1[idx(w, s, e)] + q;
-                const uint32_t r = (uint32_t)(sum >= m ? sum - m : sum);
+                // x' y' + S + m 2^17 < m 2^32 for m <= kMaxPrimeP: one REDC
+                const uint64_t T = (uint64_t)x.p[idx(w, s, e)] * y.p[idx(w, s, e)] + (uint64_t)(S + ((int64_t)m << 17));
+                const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, u);
                 x.p[idx(w, s, e)] = r;
                 if (c.real(w, s)) dig2[(size_t)e * BROW + c.channel(w, s)] = pack_digits(mulredc(r, H, m, u));
             }

@@ -173,11 +173,6 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
     // issue while the matrix cores run
     mfma_v4i D[MT][NT];
     mfma_extension<K, W, MT, NT>(C, false, buf1, lane, D);
-    uint32_t a1[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; mt++)
-#pragma unroll
-        for (int nt = 0; nt < NT; nt++) a1[mt][nt] = mulredc(x.p[mt][nt], y.p[mt][nt], C.mP[mt], C.uP[mt]);
     uint32_t sr[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) sr[nt] = x.r[nt] * y.r[nt];
@@ -196,10 +191,11 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
             const uint32_t m = C.mP[mt];
-            const uint32_t q = mfma_reduce(mfma_combine(D[mt][nt]), m, C.uP[mt]);
-            uint32_t r;
-            const bool ov = __builtin_add_overflow(a1[mt][nt], q, &r);
-            r = (ov || r >= m) ? r - m : r;
+            // x' y' + S in one REDC (S + m 2^17 > 0; the sum stays below
+            // m 2^32 for every B' prime m <= kMaxPrimeP)
+            const uint64_t T = (uint64_t)x.p[mt][nt] * y.p[mt][nt] +
+                               (uint64_t)(mfma_combine(D[mt][nt]) + ((int64_t)m << 17));
+            const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, C.uP[mt]);
             x.p[mt][nt] = r;
             const uint32_t xip = mulredc(r, C.HP[mt], m, C.uP[mt]);                     // r (M'_t)^-1
             buf2[(16 * nt + (lane & 15)) * S::BROW + col] = mfma_pack(xip);

@@ -20,6 +20,10 @@ constexpr uint32_t kDigitBias = 0x80808080u;
 // residue in [kDigitSplit - m, kDigitSplit), inside [-0x80808080, 0x7F7F7F7F],
 // the range of four signed bytes.
 constexpr uint32_t kDigitSplit = 0x7F7F7F80u;
+// Largest B' prime the matrix engine accepts: step (iii) of a product reduces
+// x' y' + S + m 2^17 (|S| < 2^48) in one REDC, whose input must stay below
+// m 2^32; that holds for m <= 2^32 - 2^18.
+constexpr uint32_t kMaxPrimeP = 0xFFFC0000u;
 
 struct MLayout {
     int K, W, MT, NT;

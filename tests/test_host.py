@@ -177,6 +177,26 @@ def test_group_selection():
     assert Plan(small, 8, group=16).info["group"] == 32              # no 16-element kernel for k = 9
 
 
+def test_matrix_engine_prime_limit():
+    """The matrix engine reduces x' y' + S in one step, which needs every B'
+    prime <= 2^32 - 2^18; a base with a larger B' prime takes the channel
+    engine (auto) or is refused (matrix engine requested)."""
+    B = [4293918689, 4293918683]
+    ok = Plan(3233, 1, primes=B + [4293918589, 4293918583])
+    assert ok.info["engine"] == rnsrsa.ENGINE_MATRIX
+    big = B + [4293918589, 4294967291]                   # 2^32 - 5 in B'
+    assert Plan(3233, 1, primes=big).info["engine"] == rnsrsa.ENGINE_CHANNEL
+    with pytest.raises(RnsError) as e:
+        Plan(3233, 1, primes=big, engine=rnsrsa.ENGINE_MATRIX)
+    assert e.value.status == -8
+    # the limit concerns B' only
+    assert Plan(3233, 1, primes=[4294967291, 4294967279, 4293918589, 4293918583]).info["engine"] == rnsrsa.ENGINE_MATRIX
+    edge = Plan(3233, 1, primes=B + [4293918589, 4294705139])    # largest prime <= the limit
+    assert edge.info["engine"] == rnsrsa.ENGINE_MATRIX
+    msgs = np.arange(3233, dtype=np.uint32)[:, None]
+    assert [int(v) for v in edge.emul_modexp(msgs, np.array([17], np.uint32))[:, 0]] == [pow(m, 17, 3233) for m in range(3233)]
+
+
 @pytest.mark.parametrize("group", [16, 32])
 def test_emul_group_sizes_agree(group):
     rng = random.Random(group)

@@ -80,6 +80,8 @@ enum rns_prime_range {
  *   prime_range rns_prime_range; prime_seed seeds the deterministic draw.
  *   primes      optional explicit bases: n_primes = 2k distinct primes in
  *               (2^31, 2^32), B first then B'.  Overrides k and prime_range.
+ *               The matrix-core engine needs every B' prime <= 2^32 - 2^18
+ *               (else: channel engine, or RNS_EUNSUPPORTED if requested).
  *   engine      rns_engine (0 = auto).  rns_mont_mul_batch and the Garner
  *               step of CRT decryption always use the channel kernels.
  *   group       matrix-core engine: preferred elements per workgroup, 16 or

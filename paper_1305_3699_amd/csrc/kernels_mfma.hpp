@@ -78,24 +78,32 @@ struct MConst {
     uint32_t mB[MT], uB[MT], nuB[MT], cB[MT];
     uint32_t mP[MT], uP[MT], HP[MT];
     uint32_t Mpinv_r, Minv_r, N_r;
+    int32_t k16, k1;         // 2^16 and 1, opaque to the compiler (see mfma_accumulate)
 };
 
 // digit word of a residue: its bytes, read as signed int8, are those of v - kDigitBias
 __device__ __forceinline__ uint32_t mfma_pack(uint32_t v) { return v ^ kDigitBias; }
 
-// signed 64-bit value of the four byte partials of one output
-__device__ __forceinline__ int64_t mfma_combine(const mfma_v4i &d) {
-    const int32_t t1 = d[0] + (d[1] << 8);
-    const int32_t t2 = d[2] + (d[3] << 8);
-    return (int64_t)t1 + ((int64_t)t2 << 16);
+// low word of the value of the four byte partials (the redundant row)
+__device__ __forceinline__ uint32_t mfma_combine_lo(const mfma_v4i &d) {
+    const uint32_t t1 = (uint32_t)d[0] + ((uint32_t)d[1] << 8);
+    uint32_t t2 = (uint32_t)d[2] + ((uint32_t)d[3] << 8);
+    asm volatile("" : "+v"(t2));   // keeps the three shift-adds from being reassociated into four ops
+    return t1 + (t2 << 16);
 }
 
-// S * 2^-32 mod m for |S| < 2^48 (at most 4*129+1 terms of |A| <= 0x80808080
-// times |digit byte| <= 128, plus alpha * nu < 2^40): adding m * 2^17 makes
-// the REDC input positive and keeps it below m * 2^32.
-__device__ __forceinline__ uint32_t mfma_reduce(int64_t S, uint32_t m, uint32_t u) {
-    const uint64_t x = (uint64_t)(S + ((int64_t)m << 17));
-    return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
+// acc + the signed value S of the four byte partials, mod 2^64.  |S| < 2^48:
+// at most 4*129+1 terms of |A byte value| <= 0x80808080 times |digit byte|
+// <= 128.  Callers add m 2^17 > 2^48 so that the REDC input is positive.  The factors
+// k16 = 2^16 and k1 = 1 come from scalar registers the compiler cannot see
+// through, so each step is one signed 32x32+64 multiply-add instead of a
+// sign extension, a 64-bit shift and a 64-bit add.
+__device__ __forceinline__ uint64_t mfma_accumulate(const mfma_v4i &d, uint64_t acc, int32_t k16, int32_t k1) {
+    const int32_t t1 = d[0] + (d[1] << 8);
+    const int32_t t2 = d[2] + (d[3] << 8);
+    acc += (uint64_t)((int64_t)t2 * k16);
+    acc += (uint64_t)((int64_t)t1 * k1);
+    return acc;
 }
 
 template <int K, int W, int MT, int NT>
@@ -180,7 +188,7 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
     uint32_t rr[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) {
-        const uint32_t lo = (uint32_t)mfma_combine(D[MT - 1][nt]);
+        const uint32_t lo = mfma_combine_lo(D[MT - 1][nt]);
         const uint32_t qr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)lo);   // q^'' mod 2^32
         rr[nt] = (sr[nt] + qr * C.N_r) * C.Minv_r;
     }
@@ -193,8 +201,8 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
             const uint32_t m = C.mP[mt];
             // x' y' + S in one REDC (S + m 2^17 > 0; the sum stays below
             // m 2^32 for every B' prime m <= kMaxPrimeP)
-            const uint64_t T = (uint64_t)x.p[mt][nt] * y.p[mt][nt] +
-                               (uint64_t)(mfma_combine(D[mt][nt]) + ((int64_t)m << 17));
+            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)x.p[mt][nt] * y.p[mt][nt] + ((uint64_t)m << 17),
+                                               C.k16, C.k1);
             const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, C.uP[mt]);
             x.p[mt][nt] = r;
             const uint32_t xip = mulredc(r, C.HP[mt], m, C.uP[mt]);                     // r (M'_t)^-1
@@ -211,7 +219,7 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
     uint32_t alpha[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) {
-        const uint32_t lo = (uint32_t)mfma_combine(D[MT - 1][nt]);
+        const uint32_t lo = mfma_combine_lo(D[MT - 1][nt]);
         const uint32_t s2 = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)lo);
         alpha[nt] = (s2 - rr[nt]) * C.Mpinv_r;
     }
@@ -219,8 +227,10 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            const int64_t s = mfma_combine(D[mt][nt]) + (int64_t)((uint64_t)alpha[nt] * C.nuB[mt]);
-            x.b[mt][nt] = mfma_reduce(s, C.mB[mt], C.uB[mt]);
+            // S + alpha nu + m 2^17 (alpha nu < 2^40): positive, below m 2^32
+            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)alpha[nt] * C.nuB[mt] + ((uint64_t)C.mB[mt] << 17),
+                                               C.k16, C.k1);
+            x.b[mt][nt] = redc((uint32_t)T, (uint32_t)(T >> 32), C.mB[mt], C.uB[mt]);
         }
 }
 
@@ -370,6 +380,9 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     C.Mpinv_r = mb[S::LY.bscal() + 0];
     C.Minv_r = mb[S::LY.bscal() + 1];
     C.N_r = mk[S::LY.kscal() + 0];
+    C.k16 = 1 << 16;
+    C.k1 = 1;
+    asm volatile("" : "+s"(C.k16), "+s"(C.k1));
 
     // entry: residues of Z = sum_h X_h Y_h in the kept representation
     MState<MT, NT> a;

@@ -442,32 +442,36 @@ def run_served(args) -> dict:
 
 
 def run_modmul_sweep(args) -> list:
-    """RNS modular multiplications of 3072-bit integers per millisecond against
-    the number of operands in flight (the shape of the paper's Fig. 1: 3072-bit
-    modular multiplication over 128 32-bit channels, throughput vs blocks).
-    Two forms: the standalone product (rns_mont_mul_batch, one launch of B
-    independent products on residue vectors) and the products inside an
-    exponentiation by a 3072-bit exponent (rns_modexp_batch, counted from the
-    exponent as the kernel schedules them).  k = 97 is the smallest base for a
-    3072-bit modulus; k = 129 is the closest to the paper's 128 channels."""
+    """RNS modular multiplications per millisecond against the number of
+    operands in flight (the shape of the paper's Fig. 1: 3072-bit modular
+    multiplication over 128 32-bit channels, throughput vs blocks; and its
+    note that doubling the channels reaches 8192-bit products).  Two forms:
+    the standalone product (rns_mont_mul_batch, one launch of B independent
+    products on residue vectors) and the products inside an exponentiation by
+    an exponent as long as the modulus (rns_modexp_batch, counted from the
+    exponent as the kernel schedules them).  3072 bits on k = 97 (the smallest
+    base for that modulus) and k = 129 (the closest to the paper's 128
+    channels); 8192 bits on k = 257 (256 + 1 channels)."""
     import numpy as np
     import torch
 
     import gen
     from paper_1305_3699_amd import RnsContext
 
-    rng = random.Random(gen.config_seed(6, 1))
-    N = rng.getrandbits(3072) | (1 << 3071) | 1
-    e = gen.random_exponent(3072, seed=gen.config_seed(6, 3))
-    el = torch.from_numpy(gen.to_limbs(e, 96)[0].view(np.int32)).cuda()
     lines = []
-    for k in (97, 129):
-        ctx = RnsContext(N, 96, k=k, window=6)
+    for bits, k in ((3072, 97), (3072, 129), (8192, 257)):
+        L = bits // 32
+        rng = random.Random(gen.config_seed(6, 1) if bits == 3072 else gen.config_seed(6, bits))
+        N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+        e = gen.random_exponent(bits, seed=gen.config_seed(6, 3) if bits == 3072 else gen.config_seed(6, bits + 3))
+        el = torch.from_numpy(gen.to_limbs(e, L)[0].view(np.int32)).cuda()
+        ctx = RnsContext(N, L, k=k, window=6)
         info = ctx.info
         primes = torch.tensor(ctx.primes + [0], dtype=torch.int64, device="cuda")
-        mm_exp = mm_count(e, 3072, info["window"], sliding=info["engine"] == 2)
+        mm_exp = mm_count(e, bits, info["window"], sliding=info["engine"] == 2)
         rows = []
-        for B in args.modmul_batches:
+        batches = [B for B in args.modmul_batches if bits == 3072 or B <= 16384]
+        for B in batches:
             # standalone product: residues drawn below each channel modulus
             g = torch.Generator(device="cuda").manual_seed(B)
             def residues():
@@ -491,7 +495,7 @@ def run_modmul_sweep(args) -> list:
                 return a.elapsed_time(b) / reps
 
             ms_mm = timed(lambda: ctx.mont_mul(x, y, out=out), 20)
-            bases = torch.from_numpy(gen.to_limbs([rng.getrandbits(3071) for _ in range(min(B, 64))], 96)
+            bases = torch.from_numpy(gen.to_limbs([rng.getrandbits(bits - 1) for _ in range(min(B, 64))], L)
                                      .view(np.int32)).cuda().repeat((B + 63) // 64, 1)[:B].contiguous()
             res = torch.empty_like(bases)
             ms_exp = timed(lambda: ctx.modexp(bases, el, out=res), 2 if B >= 4096 else 5)
@@ -499,8 +503,8 @@ def run_modmul_sweep(args) -> list:
                          "in_exponentiation_per_ms": round(B * mm_exp / ms_exp, 1),
                          "standalone_ms": round(ms_mm, 4), "exponentiation_ms": round(ms_exp, 3)})
             print("modmul k=%d %s" % (k, json.dumps(rows[-1])), file=sys.stderr, flush=True)
-        lines.append({"metric": "3072-bit RNS modular multiplications per ms vs operands in flight",
-                      "k": k, "engine": {1: "channel", 2: "matrix"}[info["engine"]],
+        lines.append({"metric": "%d-bit RNS modular multiplications per ms vs operands in flight" % bits,
+                      "bits": bits, "k": k, "engine": {1: "channel", 2: "matrix"}[info["engine"]],
                       "standalone_engine": "channel", "window": info["window"],
                       "products_per_exponentiation": mm_exp, "rows": rows})
     return lines

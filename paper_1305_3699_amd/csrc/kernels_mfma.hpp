@@ -59,7 +59,12 @@ struct MShp {
     // registers per lane)
     static constexpr bool A1_GLOBAL = A2_GLOBAL;
     static constexpr int A2_WORDS = A2_LDS ? A2_TILE_WORDS : 0;
-    static constexpr int LDS_WORDS = WORK_WORDS + A2_WORDS;
+    // The widest bases (more than 9 k-steps: 256 channels and up) leave too
+    // few registers for the per-slot constants as well: those shapes keep
+    // them in LDS, [W][MT][4 lane groups][8 words], read where they are used.
+    static constexpr bool C_LDS = KSTEPS > 9;
+    static constexpr int C_WORDS = C_LDS ? W * MT * 4 * 8 : 0;
+    static constexpr int LDS_WORDS = WORK_WORDS + A2_WORDS + C_WORDS;
 };
 
 template <int MT, int NT>
@@ -69,17 +74,55 @@ struct MState {
     uint32_t r[NT];      // redundant channel, replicated over the lane groups
 };
 
-// Per-lane constants held in registers for the whole kernel.
-template <int MT, int KSTEPS>
+// Pointers into global memory (address space 1): accesses through them are
+// global loads and stores, not flat ones (which also count against the LDS
+// wait counter, so every LDS wait would wait for them too).
+#define RNS_GLOBAL __attribute__((address_space(1)))
+typedef RNS_GLOBAL uint32_t gu32;
+typedef const RNS_GLOBAL mfma_v4i gcv4i;
+
+// Constants of one slot: its B prime with -m^-1 mod 2^32, nu = -M' R^2 and
+// c = -N^-1 M_i^-1; its B' prime with -m^-1 mod 2^32 and H = M (M'_t)^-1.
+struct MSlotB {
+    uint32_t m, u, nu, c;
+};
+struct MSlotP {
+    uint32_t m, u, H, pad;
+};
+
+// Per-lane constants: in registers for the whole kernel, except for the
+// shapes whose per-slot constants live in LDS (CL; read at each use).
+template <int MT, int KSTEPS, bool CL>
 struct MConst {
     mfma_v4i A1[MT][KSTEPS], A2[MT][KSTEPS];
-    const mfma_v4i *a2lds;   // the wave's second-extension tiles in LDS or global memory, [MT][KSTEPS][64]
-    const mfma_v4i *a1mem;   // its first-extension tiles in global memory (A1_GLOBAL shapes)
+    const mfma_v4i *a2lds;   // the wave's second-extension tiles in LDS (A2_LDS), [MT][KSTEPS][64]
+    gcv4i *a2mem;            // the same in global memory (A2_GLOBAL shapes)
+    gcv4i *a1mem;            // its first-extension tiles in global memory (A1_GLOBAL shapes)
+    uint32_t loff;           // lane * 16: the lane's byte offset in a tile
     uint32_t mB[MT], uB[MT], nuB[MT], cB[MT];
     uint32_t mP[MT], uP[MT], HP[MT];
+    const uint32_t *cl;      // CL: this lane group's constants in LDS, tile mt at cl + 32 mt
     uint32_t Mpinv_r, Minv_r, N_r;
     int32_t k16, k1;         // 2^16 and 1, opaque to the compiler (see mfma_accumulate)
+
+    __device__ __forceinline__ MSlotB slotB(int mt) const {
+        if (CL) {
+            const uint4 v = *(const uint4 *)(cl + 32 * mt);
+            return MSlotB{v.x, v.y, v.z, v.w};
+        }
+        return MSlotB{mB[mt], uB[mt], nuB[mt], cB[mt]};
+    }
+    __device__ __forceinline__ MSlotP slotP(int mt) const {
+        if (CL) {
+            const uint4 v = *(const uint4 *)(cl + 32 * mt + 4);
+            return MSlotP{v.x, v.y, v.z, 0u};
+        }
+        return MSlotP{mP[mt], uP[mt], HP[mt], 0u};
+    }
 };
+
+template <int K, int W, int MT, int NT>
+using MConstOf = MConst<MT, MShp<K, W, MT, NT>::KSTEPS, MShp<K, W, MT, NT>::C_LDS>;
 
 // digit word of a residue: its bytes, read as signed int8, are those of v - kDigitBias
 __device__ __forceinline__ uint32_t mfma_pack(uint32_t v) { return v ^ kDigitBias; }
@@ -106,10 +149,27 @@ __device__ __forceinline__ uint64_t mfma_accumulate(const mfma_v4i &d, uint64_t 
     return acc;
 }
 
+// Tile t of a wave's constant tiles in global memory, this lane's 16 bytes:
+// a uniform base plus the lane offset, so the load takes the scalar-base
+// form and no per-tile 64-bit address is kept in vector registers.
+__device__ __forceinline__ mfma_v4i mfma_tile_load(gcv4i *base, int t, uint32_t loff) {
+    return *(gcv4i *)((const RNS_GLOBAL char *)(base + (size_t)t * 64) + loff);
+}
+
 template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C, bool second,
+__device__ __forceinline__ void mfma_extension(const MConstOf<K, W, MT, NT> &C, bool second,
                                                const uint32_t *buf, int lane, mfma_v4i (&D)[MT][NT]) {
     using S = MShp<K, W, MT, NT>;
+    // tiles in global memory: re-derive their base at every call (an opaque
+    // zero offset), so the compiler cannot hoist one 64-bit address per tile
+    // out of the exponent loop and keep them all live
+    gcv4i *a1m = C.a1mem, *a2m = C.a2mem;
+    if (S::A1_GLOBAL || S::A2_GLOBAL) {
+        int zo;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zo));
+        a1m += zo;
+        a2m += zo;
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -123,8 +183,10 @@ __device__ __forceinline__ void mfma_extension(const MConst<MT, MShp<K, W, MT, N
 #pragma unroll
             for (int mt = 0; mt < MT; mt++)
                 D[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                    second ? (S::A2_LDS || S::A2_GLOBAL ? C.a2lds[(mt * S::KSTEPS + ks) * 64 + lane] : C.A2[mt][ks])
-                           : (S::A1_GLOBAL ? C.a1mem[(mt * S::KSTEPS + ks) * 64 + lane] : C.A1[mt][ks]),
+                    second ? (S::A2_GLOBAL ? mfma_tile_load(a2m, mt * S::KSTEPS + ks, C.loff)
+                              : S::A2_LDS  ? C.a2lds[(mt * S::KSTEPS + ks) * 64 + lane]
+                                           : C.A2[mt][ks])
+                           : (S::A1_GLOBAL ? mfma_tile_load(a1m, mt * S::KSTEPS + ks, C.loff) : C.A1[mt][ks]),
                     bop, D[mt][nt], 0, 0, 0);
         }
         // operands read from memory: keep at most one k-step of them in
@@ -147,7 +209,7 @@ __device__ __forceinline__ int mfma_digit_col(int wave, int mt, int g) {
 // Step (i) of a product: quotient digits xi = x y c_i of the B slots,
 // published as the B operand of the first extension.
 template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void mfma_publish_xi(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C,
+__device__ __forceinline__ void mfma_publish_xi(const MConstOf<K, W, MT, NT> &C,
                                                 const MState<MT, NT> &x, const MState<MT, NT> &y, uint32_t *buf1,
                                                 int wave, int lane) {
     using S = MShp<K, W, MT, NT>;
@@ -157,8 +219,9 @@ __device__ __forceinline__ void mfma_publish_xi(const MConst<MT, MShp<K, W, MT, 
         const int col = mfma_digit_col<K, W, MT, NT>(wave, mt, g);
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], C.mB[mt], C.uB[mt]);   // x y 2^32
-            const uint32_t xi = mulredc(t, C.cB[mt], C.mB[mt], C.uB[mt]);              // x y c_i
+            const MSlotB sb = C.slotB(mt);
+            const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], sb.m, sb.u);   // x y 2^32
+            const uint32_t xi = mulredc(t, sb.c, sb.m, sb.u);                  // x y c_i
             buf1[(16 * nt + (lane & 15)) * S::BROW + col] = mfma_pack(xi);
         }
     }
@@ -168,7 +231,7 @@ __device__ __forceinline__ void mfma_publish_xi(const MConst<MT, MShp<K, W, MT, 
 // full == false the second extension is skipped (the caller leaves the RNS
 // from the xi' digits in buf2).  x.r receives the new redundant residue.
 template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C, MState<MT, NT> &x,
+__device__ __forceinline__ void mfma_mm(const MConstOf<K, W, MT, NT> &C, MState<MT, NT> &x,
                                         const MState<MT, NT> &y, uint32_t *buf1, uint32_t *buf2, int wave, int lane,
                                         bool full) {
     using S = MShp<K, W, MT, NT>;
@@ -198,14 +261,15 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
         const int col = mfma_digit_col<K, W, MT, NT>(wave, mt, g);
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            const uint32_t m = C.mP[mt];
+            const MSlotP sp = C.slotP(mt);
+            const uint32_t m = sp.m;
             // x' y' + S in one REDC (S + m 2^17 > 0; the sum stays below
             // m 2^32 for every B' prime m <= kMaxPrimeP)
             const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)x.p[mt][nt] * y.p[mt][nt] + ((uint64_t)m << 17),
                                                C.k16, C.k1);
-            const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, C.uP[mt]);
+            const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, sp.u);
             x.p[mt][nt] = r;
-            const uint32_t xip = mulredc(r, C.HP[mt], m, C.uP[mt]);                     // r (M'_t)^-1
+            const uint32_t xip = mulredc(r, sp.H, m, sp.u);                            // r (M'_t)^-1
             buf2[(16 * nt + (lane & 15)) * S::BROW + col] = mfma_pack(xip);
         }
     }
@@ -228,14 +292,15 @@ __device__ __forceinline__ void mfma_mm(const MConst<MT, MShp<K, W, MT, NT>::KST
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
             // S + alpha nu + m 2^17 (alpha nu < 2^40): positive, below m 2^32
-            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)alpha[nt] * C.nuB[mt] + ((uint64_t)C.mB[mt] << 17),
+            const MSlotB sb = C.slotB(mt);
+            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)alpha[nt] * sb.nu + ((uint64_t)sb.m << 17),
                                                C.k16, C.k1);
-            x.b[mt][nt] = redc((uint32_t)T, (uint32_t)(T >> 32), C.mB[mt], C.uB[mt]);
+            x.b[mt][nt] = redc((uint32_t)T, (uint32_t)(T >> 32), sb.m, sb.u);
         }
 }
 
 template <int MT, int NT>
-__device__ __forceinline__ void mstate_store(uint32_t *__restrict__ p, const MState<MT, NT> &a) {
+__device__ __forceinline__ void mstate_store(gu32 *__restrict__ p, const MState<MT, NT> &a) {
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -248,7 +313,7 @@ __device__ __forceinline__ void mstate_store(uint32_t *__restrict__ p, const MSt
 }
 
 template <int MT, int NT>
-__device__ __forceinline__ void mstate_load(const uint32_t *__restrict__ p, MState<MT, NT> &a) {
+__device__ __forceinline__ void mstate_load(const gu32 *__restrict__ p, MState<MT, NT> &a) {
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -263,15 +328,15 @@ __device__ __forceinline__ void mstate_load(const uint32_t *__restrict__ p, MSta
 // y = 1 in the kept representation: 2^32 mod m in B, 2^32 M^-1 mod m' in B'
 // (read from the table when needed rather than held in registers).
 template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void mstate_unit(const MConst<MT, MShp<K, W, MT, NT>::KSTEPS> &C,
-                                            const uint32_t *__restrict__ mb, int wave, int lane, MState<MT, NT> &y) {
+__device__ __forceinline__ void mstate_unit(const MConstOf<K, W, MT, NT> &C,
+                                            const gu32 *__restrict__ mb, int wave, int lane, MState<MT, NT> &y) {
     using S = MShp<K, W, MT, NT>;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
         const uint32_t kap = mb[S::LY.slotP() + (((size_t)wave * MT + mt) * 4 + 3) * 64 + lane];
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            y.b[mt][nt] = 0u - C.mB[mt];
+            y.b[mt][nt] = 0u - C.slotB(mt).m;
             y.p[mt][nt] = kap;
         }
     }
@@ -282,17 +347,17 @@ __device__ __forceinline__ void mstate_unit(const MConst<MT, MShp<K, W, MT, NT>:
 // Limb l of a shared (wave-uniform) exponent.  The builtin returns int: the
 // limb is taken back as unsigned before any widening (a sign extension would
 // fill the upper half of a 64-bit window with ones).
-__device__ __forceinline__ uint32_t mexp_limb(const uint32_t *__restrict__ e, int l) {
+__device__ __forceinline__ uint32_t mexp_limb(const gu32 *__restrict__ e, int l) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)e[l]);
 }
 
 // Bit i of a shared exponent.
-__device__ __forceinline__ uint32_t mexp_bit(const uint32_t *__restrict__ e, int i) {
+__device__ __forceinline__ uint32_t mexp_bit(const gu32 *__restrict__ e, int i) {
     return (mexp_limb(e, i >> 5) >> (i & 31)) & 1u;
 }
 
 // Highest set bit of a shared exponent of n limbs, -1 if it is zero.
-__device__ __forceinline__ int mexp_top_bit(const uint32_t *__restrict__ e, int n) {
+__device__ __forceinline__ int mexp_top_bit(const gu32 *__restrict__ e, int n) {
     for (int l = n - 1; l >= 0; l--) {
         const uint32_t v = mexp_limb(e, l);
         if (v) return 32 * l + 31 - __builtin_clz(v);
@@ -303,7 +368,7 @@ __device__ __forceinline__ int mexp_top_bit(const uint32_t *__restrict__ e, int 
 // Sliding window of a shared exponent whose bit i is set: the bits i..low
 // with low >= i - w + 1 the lowest set bit in that range; returns their value
 // (odd, < 2^w) and low.
-__device__ __forceinline__ uint32_t mexp_window(const uint32_t *__restrict__ e, int n, int i, int w, int *low) {
+__device__ __forceinline__ uint32_t mexp_window(const gu32 *__restrict__ e, int n, int i, int w, int *low) {
     int lo = i - w + 1 > 0 ? i - w + 1 : 0;
     while (!mexp_bit(e, lo)) lo++;
     const int l = lo >> 5;
@@ -313,7 +378,7 @@ __device__ __forceinline__ uint32_t mexp_window(const uint32_t *__restrict__ e, 
     return (uint32_t)(v >> (lo & 31)) & ((1u << (i - lo + 1)) - 1u);
 }
 
-__device__ __forceinline__ uint32_t mexp_digit(const uint32_t *__restrict__ e, int nlimbs, int nd, int w, int di) {
+__device__ __forceinline__ uint32_t mexp_digit(const gu32 *__restrict__ e, int nlimbs, int nd, int w, int di) {
     const int lo = (nd - 1 - di) * w;
     const int limb = lo >> 5, sh = lo & 31;
     uint64_t v = e[limb];
@@ -329,12 +394,12 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     using S = MShp<K, W, MT, NT>;
     uint32_t *buf1 = lds;
     uint32_t *buf2 = lds + S::NM * S::BROW;
-    const uint32_t *__restrict__ mb = J.mb;
-    const uint32_t *__restrict__ mk = J.mk;
-    const uint32_t *__restrict__ E = J.E;
-    const uint32_t *__restrict__ ex = J.exp;
-    const uint32_t *__restrict__ in = J.in;
-    uint32_t *__restrict__ out = J.out;
+    const gu32 *__restrict__ mb = (const gu32 *)J.mb;
+    const gu32 *__restrict__ mk = (const gu32 *)J.mk;
+    const gu32 *__restrict__ E = (const gu32 *)J.E;
+    const gu32 *__restrict__ ex = (const gu32 *)J.exp;
+    const gu32 *__restrict__ in = (const gu32 *)J.in;
+    gu32 *__restrict__ out = (gu32 *)J.out;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
@@ -348,35 +413,55 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     }
 
     // per-lane constants
-    MConst<MT, S::KSTEPS> C;
+    MConstOf<K, W, MT, NT> C;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
         const size_t sl = (size_t)wave * MT + mt;
 #pragma unroll
         for (int ks = 0; ks < S::KSTEPS; ks++) {
             const size_t ti = ((sl * S::KSTEPS + ks) * 64 + lane) * 4;
-            if (!S::A1_GLOBAL) C.A1[mt][ks] = *(const mfma_v4i *)(mk + S::LY.a1() + ti);
-            if (!S::A2_LDS && !S::A2_GLOBAL) C.A2[mt][ks] = *(const mfma_v4i *)(mb + S::LY.a2() + ti);
+            if (!S::A1_GLOBAL) C.A1[mt][ks] = *(gcv4i *)(mk + S::LY.a1() + ti);
+            if (!S::A2_LDS && !S::A2_GLOBAL) C.A2[mt][ks] = *(gcv4i *)(mb + S::LY.a2() + ti);
         }
-        C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
-        C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
-        C.mP[mt] = mb[S::LY.slotP() + (sl * 4 + 0) * 64 + lane];
-        C.uP[mt] = mb[S::LY.slotP() + (sl * 4 + 1) * 64 + lane];
-        C.nuB[mt] = mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
-        C.HP[mt] = mb[S::LY.slotP() + (sl * 4 + 2) * 64 + lane];
-        C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
-
+        if (!S::C_LDS) {
+            C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
+            C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
+            C.mP[mt] = mb[S::LY.slotP() + (sl * 4 + 0) * 64 + lane];
+            C.uP[mt] = mb[S::LY.slotP() + (sl * 4 + 1) * 64 + lane];
+            C.nuB[mt] = mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
+            C.HP[mt] = mb[S::LY.slotP() + (sl * 4 + 2) * 64 + lane];
+            C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
+        }
+    }
+    if (S::C_LDS) {
+        // [W][MT][group][m, u, nu, c, m', u', H, 0]; a slot's constants are
+        // the same for the 16 lanes of its lane group
+        uint32_t *cl = lds + S::WORK_WORDS + S::A2_WORDS;
+        for (int i = threadIdx.x; i < W * MT * 4 * 8; i += 64 * W) {
+            const int f = i & 7, gi = (i >> 3) & 3;
+            const size_t sl = (size_t)(i >> 5);
+            const int ln = 16 * gi;
+            uint32_t v = 0;
+            if (f < 3) v = mb[S::LY.slotB() + (sl * 3 + f) * 64 + ln];
+            else if (f == 3) v = mk[S::LY.slotC() + sl * 64 + ln];
+            else if (f < 7) v = mb[S::LY.slotP() + (sl * 4 + (f - 4)) * 64 + ln];
+            cl[i] = v;
+        }
+        C.cl = cl + ((size_t)wave * MT * 4 + g) * 8;
+        __syncthreads();
     }
     if (S::A2_LDS) {
         // each wave copies its own tiles; it alone reads them, so program
         // order suffices (no barrier)
         mfma_v4i *dst = (mfma_v4i *)(lds + S::WORK_WORDS) + (size_t)wave * MT * S::KSTEPS * 64;
-        const mfma_v4i *src = (const mfma_v4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
+        gcv4i *src = (gcv4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
         for (int i = lane; i < MT * S::KSTEPS * 64; i += 64) dst[i] = src[i];
         C.a2lds = dst;
     }
-    if (S::A2_GLOBAL) C.a2lds = (const mfma_v4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
-    if (S::A1_GLOBAL) C.a1mem = (const mfma_v4i *)(mk + S::LY.a1()) + (size_t)wave * MT * S::KSTEPS * 64;
+    if (S::A2_GLOBAL) C.a2mem = (gcv4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
+    if (S::A1_GLOBAL) C.a1mem = (gcv4i *)(mk + S::LY.a1()) + (size_t)wave * MT * S::KSTEPS * 64;
+    C.loff = 16u * lane;
+    asm volatile("" : "+v"(C.loff));   // one offset register for every tile load
     C.Mpinv_r = mb[S::LY.bscal() + 0];
     C.Minv_r = mb[S::LY.bscal() + 1];
     C.N_r = mk[S::LY.kscal() + 0];
@@ -397,7 +482,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         }
         const int colB = wave * 4 * MT + g, colP = W * 4 * MT + wave * 4 * MT + g;
         for (int l = 0; l < J.in_limbs; l++) {
-            const uint32_t *__restrict__ row = E + (size_t)l * S::ECOLS;
+            const gu32 *__restrict__ row = E + (size_t)l * S::ECOLS;
             uint32_t v[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; nt++)
@@ -419,8 +504,10 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         for (int mt = 0; mt < MT; mt++)
 #pragma unroll
             for (int nt = 0; nt < NT; nt++) {
-                a.b[mt][nt] = acc_redc(ab[mt][nt], C.mB[mt], C.uB[mt]);
-                a.p[mt][nt] = acc_redc(ap[mt][nt], C.mP[mt], C.uP[mt]);
+                const MSlotB sb = C.slotB(mt);
+                const MSlotP sp = C.slotP(mt);
+                a.b[mt][nt] = acc_redc(ab[mt][nt], sb.m, sb.u);
+                a.p[mt][nt] = acc_redc(ap[mt][nt], sp.m, sp.u);
             }
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) a.r[nt] = zr[nt];
@@ -428,7 +515,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     const int w = J.window;
     const int T = 1 << w;
     const size_t estride = (size_t)W * S::SLOTS * 64;
-    uint32_t *__restrict__ tw = table + ((slot << max_window) * W + wave) * (size_t)(S::SLOTS * 64) + lane;
+    gu32 *__restrict__ tw = (gu32 *)table + ((slot << max_window) * W + wave) * (size_t)(S::SLOTS * 64) + lane;
     {
         MState<MT, NT> one;
 #pragma unroll
@@ -476,9 +563,9 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
 #pragma unroll
                 for (int nt = 0; nt < NT; nt++) {
                     const int m = e0 + 16 * nt + (lane & 15);
-                    const uint32_t *__restrict__ ep = ex + (size_t)(m < J.batch ? m : 0) * J.exp_stride;
+                    const gu32 *__restrict__ ep = ex + (size_t)(m < J.batch ? m : 0) * J.exp_stride;
                     const uint32_t d = mexp_digit(ep, J.exp_limbs, nd, w, yidx);
-                    const uint32_t *__restrict__ pe = tw + (size_t)d * estride;
+                    const gu32 *__restrict__ pe = tw + (size_t)d * estride;
 #pragma unroll
                     for (int mt = 0; mt < MT; mt++) {
                         y.b[mt][nt] = pe[(mt * NT + nt) * 64];

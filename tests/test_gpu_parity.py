@@ -239,6 +239,46 @@ def test_modexp_large_k_both_tiles(bits, group):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("engine", [1, 2])
+def test_modexp_8192_bit(engine):
+    """8192-bit moduli on bases of 256 + 1 channels (k = 257): 20 bases (a
+    full 16-element tile and a ragged one) including 0, 1, N - 1 and
+    2^8192 - 1, a 64-bit exponent; the matrix engine also takes a full-length
+    exponent on 17 bases."""
+    rng = random.Random(8192 + engine)
+    N = rng.getrandbits(8192) | (1 << 8191) | 1
+    ctx = _ctx(N, 256, engine=engine)
+    assert ctx.info["k"] == 257 and ctx.info["engine"] == engine
+    bases = gen.to_limbs([rng.getrandbits(8192) for _ in range(16)] + [0, 1, N - 1, (1 << 8192) - 1], 256)
+    nl = gen.to_limbs(N, 256)[0]
+    e = gen.to_limbs(rng.getrandbits(64) | (1 << 63), 2)[0]
+    assert np.array_equal(_run_modexp(ctx, bases, e), oracle.modexp_batch(bases, e, nl))
+    if engine == 2:
+        e = gen.to_limbs(rng.getrandbits(8192) | (1 << 8191), 256)[0]
+        assert np.array_equal(_run_modexp(ctx, bases[:17], e), oracle.modexp_batch(bases[:17], e, nl))
+
+
+def test_mont_mul_8192_bit():
+    """The standalone product at 8192 bits (k = 257, channel kernels)."""
+    rng = random.Random(257)
+    N = rng.getrandbits(8192) | (1 << 8191) | 1
+    ctx = _ctx(N, 256)
+    k = ctx.info["k"]
+    assert k == 257
+    pr = ctx.primes
+    B, Bp = pr[:k], pr[k:]
+    n = 70
+    X = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [(k + 1) * N - 1]
+    Y = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [0]
+
+    def res(vals):
+        return np.array([[v % m for v in vals] for m in B] + [[v % m for v in vals] for m in Bp]
+                        + [[v % (1 << 32) for v in vals]], dtype=np.uint32)
+
+    out = _host(ctx.mont_mul(_dev(res(X)), _dev(res(Y))))
+    assert np.array_equal(out, res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)]))
+
+
 def test_rsa1024_config_bit_exact():
     """One seeded RSA-1024 key, 64 messages, 64 encryptions and 64 plain
     decryptions with bases of 2 x 33 random 32-bit primes."""

@@ -172,7 +172,7 @@ def test_group_selection():
         p = Plan(N, 32, group=g)
         assert p.info["engine"] == rnsrsa.ENGINE_MATRIX and p.info["group"] == g
     assert Plan(N, 32).info["group"] == 16                           # default tile for k = 33
-    assert Plan((1 << 4095) + 4095, 128).info["group"] == 16         # default tile for k = 129
+    assert Plan((1 << 4095) + 4095, 128).info["group"] == 32         # default tile for k = 129
     small = (1 << 255) + 4095
     assert Plan(small, 8, group=16).info["group"] == 32              # no 16-element kernel for k = 9
 
@@ -233,6 +233,20 @@ def test_emul_zero_residue_bases(bits, engine):
     for e in (1, 2, 65537):
         out = p.emul_modexp(gen.to_limbs(bases, L), gen.to_limbs(e, 1)[0])
         assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_emul_8192_bit_modulus(engine):
+    """256 + 1 channels per base (k = 257): an 8192-bit modulus, the doubled
+    base the paper names for 8192-bit modular multiplication."""
+    rng = random.Random(8192)
+    N = rng.getrandbits(8192) | (1 << 8191) | 1
+    p = Plan(N, 256, window=3, engine=engine)
+    assert p.info["k"] == 257 and p.info["engine"] == engine
+    bases = [rng.getrandbits(8192) for _ in range(3)] + [0, 1, N - 1]
+    e = rng.getrandbits(40) | (1 << 39)
+    out = p.emul_modexp(gen.to_limbs(bases, 256), gen.to_limbs(e, 2)[0])
+    assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]
 
 
 def test_batch_and_server_argument_errors():

@@ -39,6 +39,11 @@ struct Shp {
     }
     // unroll factor of the K-long base-extension loops (bounds code size)
     static constexpr int UNR = 4;
+    // output channels accumulated per pass over a base extension's inputs:
+    // all of them, except in workgroups of more than 8 waves (at most 128
+    // registers per lane), where 17 channels' accumulators would spill; those
+    // make several passes, re-reading the digits from LDS
+    static constexpr int KC = W > 8 ? 6 : KS;
 };
 
 template <int KS>
@@ -89,58 +94,77 @@ __device__ __forceinline__ uint32_t rns_mm(const uint32_t *__restrict__ bc,
         const uint32_t t = mulredc(x.b[c], y.b[c], m, u);              // x y R^-1
         xi[(c0 + c) * 64 + lane] = mulredc(t, mw[LY.c2B() + c], m, u); // x y c_i
     }
-    uint32_t a1[KS];
+    // x y R^-1 in B', ahead of the barrier when one pass serves all channels
+    constexpr int KC = S::KC;
+    constexpr bool ONE_PASS = KC == KS;
+    uint32_t a1pre[ONE_PASS ? KS : 1];
+    if (ONE_PASS) {
 #pragma unroll
-    for (int c = 0; c < KS; c++)
-        a1[c] = mulredc(x.p[c], y.p[c], bw[LY.mBp() + c], bw[LY.uBp() + c]);  // x y R^-1
+        for (int c = 0; c < KS; c++)
+            a1pre[c] = mulredc(x.p[c], y.p[c], bw[LY.mBp() + c], bw[LY.uBp() + c]);
+    }
     const uint32_t sr = x.r * y.r;
     __syncthreads();
 
-    // (ii) first base extension: q^ in the owned channels of B' and in m_r
-    Acc acc[KS];
+    // (ii) first base extension: q^ in the owned channels of B' and in m_r,
+    // in passes of KC channels; (iii) r = (XY + q^ N)/M in B' and m_r,
+    // publishing xi' for the second extension
     uint64_t qr = 0;
+#pragma unroll
+    for (int cc = 0; cc < KS; cc += KC) {
+        Acc acc[KC];
 #pragma unroll S::UNR
-    for (int i = 0; i < K; i++) {
-        const uint32_t v = xi[i * 64 + lane];
-        const uint32_t *__restrict__ row = bw + LY.C1() + i * LY.crow();
+        for (int i = 0; i < K; i++) {
+            const uint32_t v = xi[i * 64 + lane];
+            const uint32_t *__restrict__ row = bw + LY.C1() + i * LY.crow() + cc;
 #pragma unroll
-        for (int c = 0; c < KS; c++) acc_mac(acc[c], v, row[c]);
-        qr += (uint64_t)v * bc[LY.C1() + i * LY.crow() + KP];
-    }
-
-    // (iii) r = (XY + q^ N)/M in B' and m_r; publish xi' for the second extension
+            for (int c = 0; c < KC; c++)
+                if (cc + c < KS) acc_mac(acc[c], v, row[c]);
+            if (cc == 0) qr += (uint64_t)v * bc[LY.C1() + i * LY.crow() + KP];
+        }
 #pragma unroll
-    for (int c = 0; c < KS; c++) {
-        const uint32_t m = bw[LY.mBp() + c], u = bw[LY.uBp() + c];
-        const uint32_t q = acc_redc(acc[c], m, u);                     // q^ mod m'_t
-        const uint32_t a2 = mulredc(q, mw[LY.NnBp() + c], m, u);       // -q^ N R^-1
-        uint32_t s = a1[c] - a2;
-        s = a1[c] < a2 ? s + m : s;                                     // (XY + q^ N) R^-1
-        const uint32_t r = mulredc(s, mw[LY.MiBp() + c], m, u);        // (XY + q^ N) M^-1
-        x.p[c] = r;
-        xip[(c0 + c) * 64 + lane] = mulredc(r, bw[LY.MpInv() + c], m, u);  // r (M'_t)^-1
+        for (int c = 0; c < KC; c++) {
+            const int ch = cc + c;
+            if (ch >= KS) break;
+            const uint32_t m = bw[LY.mBp() + ch], u = bw[LY.uBp() + ch];
+            const uint32_t a1 = ONE_PASS ? a1pre[ONE_PASS ? ch : 0] : mulredc(x.p[ch], y.p[ch], m, u);
+            const uint32_t q = acc_redc(acc[c], m, u);                     // q^ mod m'_t
+            const uint32_t a2 = mulredc(q, mw[LY.NnBp() + ch], m, u);      // -q^ N R^-1
+            uint32_t s = a1 - a2;
+            s = a1 < a2 ? s + m : s;                                        // (XY + q^ N) R^-1
+            const uint32_t r = mulredc(s, mw[LY.MiBp() + ch], m, u);       // (XY + q^ N) M^-1
+            x.p[ch] = r;
+            xip[(c0 + ch) * 64 + lane] = mulredc(r, bw[LY.MpInv() + ch], m, u);  // r (M'_t)^-1
+        }
     }
     const uint32_t rr = (sr + (uint32_t)qr * mc[LY.mscal()]) * bc[LY.scal() + 1];
     __syncthreads();
 
-    // (iv) second base extension, exact thanks to alpha from m_r
-    uint32_t alpha;
+    // (iv) second base extension, exact thanks to alpha from m_r (the first
+    // pass also sums the redundant channel, which fixes alpha)
+    uint32_t alpha = 0;
     if (full) {
-        Acc acc2[KS];
-        uint64_t s2 = 0;
+#pragma unroll
+        for (int cc = 0; cc < KS; cc += KC) {
+            Acc acc2[KC];
+            uint64_t s2 = 0;
 #pragma unroll S::UNR
-        for (int j = 0; j < K; j++) {
-            const uint32_t v = xip[j * 64 + lane];
-            const uint32_t *__restrict__ row = bw + LY.C2() + j * LY.crow();
+            for (int j = 0; j < K; j++) {
+                const uint32_t v = xip[j * 64 + lane];
+                const uint32_t *__restrict__ row = bw + LY.C2() + j * LY.crow() + cc;
 #pragma unroll
-            for (int c = 0; c < KS; c++) acc_mac(acc2[c], v, row[c]);
-            s2 += (uint64_t)v * bc[LY.C2() + j * LY.crow() + KP];
-        }
-        alpha = ((uint32_t)s2 - rr) * bc[LY.scal()];
+                for (int c = 0; c < KC; c++)
+                    if (cc + c < KS) acc_mac(acc2[c], v, row[c]);
+                if (cc == 0) s2 += (uint64_t)v * bc[LY.C2() + j * LY.crow() + KP];
+            }
+            if (cc == 0) alpha = ((uint32_t)s2 - rr) * bc[LY.scal()];
 #pragma unroll
-        for (int c = 0; c < KS; c++) {
-            acc_mac16(acc2[c], alpha, bw[LY.negMp() + c]);              // alpha < K < 2^16
-            x.b[c] = acc_redc(acc2[c], bw[LY.mB() + c], bw[LY.uB() + c]);
+            for (int c = 0; c < KC; c++) {
+                const int ch = cc + c;
+                if (ch >= KS) break;
+                acc_mac16(acc2[c], alpha, bw[LY.negMp() + ch]);         // alpha < K < 2^16
+                x.b[ch] = acc_redc(acc2[c], bw[LY.mB() + ch], bw[LY.uB() + ch]);
+            }
         }
     } else {
         uint64_t s2 = 0;

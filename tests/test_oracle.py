@@ -215,3 +215,56 @@ def test_rns_ref_montgomery_identity():
             assert r * M % N == X * Y % N
             assert 0 <= r < (k + 1) * N
             assert rns_ref.crt(rns_ref.residues(r, B), B) == r % M
+
+
+# ---------------------------------------------------------------------------
+# Primality steps of key generation (trial division, Miller-Rabin)
+
+def test_small_primes_pins():
+    from oracle import primality
+    pr = primality.small_primes(10000)
+    assert len(pr) == 10000 and pr[:10] == [2, 3, 5, 7, 11, 13, 17, 19, 23, 29]
+    assert pr[-1] == 104729                       # the 10,000th prime
+    # brute force below 2000
+    brute = [n for n in range(2, 2000) if all(n % d for d in range(2, int(n ** 0.5) + 1))]
+    assert pr[:len(brute)] == brute
+
+
+def test_trial_division_pins():
+    from oracle import primality
+    pr = primality.small_primes(10000)
+    assert primality.trial_division(104729, primes=pr)            # equal to a listed prime
+    assert not primality.trial_division(104729 * 104723, primes=pr)
+    assert primality.trial_division(104743 * 104759, primes=pr)   # smallest factors past the list
+    big = (1 << 1023) + 1
+    want = all(big % p for p in pr)
+    assert primality.trial_division(big, primes=pr) == want
+    assert not primality.trial_division(3 * ((1 << 1000) + 7), primes=pr)
+
+
+def test_miller_rabin_pins():
+    from oracle import primality
+    # Mersenne primes pass every base
+    for e in (61, 89, 107, 127, 521, 607):
+        n = (1 << e) - 1
+        assert primality.miller_rabin(n, [2, 3, 5, 7, 11, 1 << 40, n - 2])
+    # Carmichael numbers fool Fermat but not the strong test to base 2
+    for n in (561, 1105, 1729, 2465, 2821, 6601, 8911, 41041, 825265):
+        assert pow(2, n - 1, n) == 1 or math.gcd(2, n) > 1
+        assert not primality.miller_rabin(n, [2])
+    # strong pseudoprimes: 2047 = 23 * 89 passes base 2 only; 3215031751 =
+    # 151 * 751 * 28351 passes bases 2, 3, 5, 7 and fails 11
+    assert primality.strong_probable_prime(2047, 2) and not primality.strong_probable_prime(2047, 3)
+    assert 151 * 751 * 28351 == 3215031751
+    assert primality.miller_rabin(3215031751, [2, 3, 5, 7])
+    assert not primality.miller_rabin(3215031751, [2, 3, 5, 7, 11])
+    # agreement with brute force for every odd n in [5, 3000) with bases 2, 3
+    for n in range(5, 3000, 2):
+        prime = all(n % d for d in range(3, int(n ** 0.5) + 1, 2))
+        if prime:
+            assert primality.miller_rabin(n, [2, 3])
+        elif primality.miller_rabin(n, [2, 3]):
+            raise AssertionError(n)                # no spsp(2, 3) below 1,373,653
+    # a product of two 512-bit primes is composite for random bases
+    p, q = (1 << 521) - 1, (1 << 607) - 1
+    assert not primality.miller_rabin(p * q, [2, 3])

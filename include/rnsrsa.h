@@ -184,6 +184,11 @@ int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint3
  *   opts       host or NULL; applied to every context of the key, except that
  *              an explicit k too small for n (one sized for the CRT halves)
  *              leaves the full-modulus context sized automatically
+ * A key with CRT parts whose modulus no base covers (above 8192 bits; the
+ * halves of keys up to 16384 bits fit the 257-channel bases) loads as a
+ * CRT-only key: CRT decryption works; encryption, decryption with use_crt = 0
+ * and rsa_key_info(key, 0) return RNS_EUNSUPPORTED, as do batched operations
+ * and served requests that need the full modulus.
  * The private parts stay in library-owned memory (the paper keeps private keys
  * on the GPU, Sec. 4.3).  Release with rsa_key_free.
  */

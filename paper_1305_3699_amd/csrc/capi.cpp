@@ -458,8 +458,15 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
                 po.waves = 0;
                 rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, po, mp, err);
             }
-            if (rc) return fail(rc, err);
-            if ((rc = ctx_from_plan(std::move(mp), window, engine, group, &key->n))) return rc;
+            if (rc == RNS_ERANGE && all_crt) {
+                // no base covers the full modulus: a CRT-only key (decryption
+                // through the halves; encryption is unsupported)
+                rc = RNS_OK;
+            } else if (rc) {
+                return fail(rc, err);
+            } else if ((rc = ctx_from_plan(std::move(mp), window, engine, group, &key->n))) {
+                return rc;
+            }
         }
         key->h_e.assign(e, e + e_limbs);
         if (d) key->h_d.assign(d, d + n_limbs);
@@ -527,6 +534,7 @@ void rsa_key_free(rsa_key *key) { delete key; }
 
 int rsa_key_info(const rsa_key *key, int which, rns_info *info) {
     if (!key || !info) return fail(RNS_EINVAL, "null argument");
+    if (which == 0 && !key->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
     const rns_ctx *c = which == 0 ? key->n : which == 1 ? key->p : which == 2 ? key->q : nullptr;
     if (!c) return fail(RNS_EINVAL, "no such context in this key");
     return rns_get_info(c, info);
@@ -537,6 +545,7 @@ int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch
     if (batch == 0) return ok();
     if (!m || !c) return fail(RNS_EINVAL, "null buffer");
     if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
+    if (!key->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
     const rns_ctx *x = key->n;
     int rc = run_modexp(x, nullptr, entry_of(x), nullptr, m, x->plan.L, key->d_e, nullptr, (int)key->e_limbs, 0, c,
                         nullptr, x->plan.L, batch, (hipStream_t)hip_stream);
@@ -551,6 +560,7 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
     hipStream_t s = (hipStream_t)hip_stream;
     if (!use_crt) {
         if (!key->d_d) return fail(RNS_EINVAL, "key has no private exponent");
+        if (!key->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
         const rns_ctx *x = key->n;
         int rc = run_modexp(x, nullptr, entry_of(x), nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
                             nullptr, x->plan.L, batch, s);

@@ -131,6 +131,7 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             P.garners.push_back(GarnerJob{k, o.mpq, o.out, o.count});
         } else {
             const bool enc = o.kind == RSA_OP_ENCRYPT;
+            if (!k->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
             const rns_ctx *c = k->n;
             const uint32_t *x = enc ? k->d_e : k->d_d;
             const std::vector<uint32_t> &hx = enc ? k->h_e : k->h_d;

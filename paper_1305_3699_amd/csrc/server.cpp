@@ -280,6 +280,8 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
         if (i && r.arrival < reqs[i - 1].arrival) return fail(RNS_EINVAL, "arrivals must be non-decreasing");
         const rsa_key *k = srv->keys[(size_t)r.key];
         if (r.kind == RSA_OP_DECRYPT && !k->has_crt && !k->d_d) return fail(RNS_EINVAL, "key has no private exponent");
+        if ((r.kind == RSA_OP_ENCRYPT || !k->has_crt) && !k->n)
+            return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
         need[i] = op_bytes(k, r.kind, 1);
         if (need[i] > srv->budget) return fail(RNS_EINVAL, "a request exceeds the device-memory budget");
     }

@@ -4,7 +4,9 @@ All calls go through the C ABI (ctypes binding) on torch-allocated device
 buffers.  Inputs are seeded and synthetic (gen); expected values come from
 the oracle only.
 """
+import json
 import math
+import os
 import random
 
 import numpy as np
@@ -277,6 +279,38 @@ def test_mont_mul_8192_bit():
 
     out = _host(ctx.mont_mul(_dev(res(X)), _dev(res(Y))))
     assert np.array_equal(out, res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)]))
+
+
+def test_rsa16384_crt_only_key():
+    """RSA-16384 CRT decryption: 8192-bit halves on bases of 257 channels.  No
+    base covers the 16384-bit modulus, so the key loads CRT-only: decryption
+    through the halves works, encryption is refused.  20 ciphertexts (a full
+    16-element tile and a ragged one) against the oracle's CRT path, two of
+    them also by m^e = c.  The key is the stored seeded fixture."""
+    from paper_1305_3699_amd import RnsError, RsaKey
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rsa16384_key.json")) as fh:
+        fx = json.load(fh)
+    p, q, e = int(fx["p"], 16), int(fx["q"], 16), int(fx["e"])
+    n = p * q
+    assert n.bit_length() == 16384
+    d = pow(e, -1, (p - 1) * (q - 1))
+    dp, dq, qinv = d % (p - 1), d % (q - 1), pow(q, -1, p)
+    rk = RsaKey(n, e, d, p, q, dp, dq, qinv)
+    assert rk.info(1)["k"] == 257 and rk.info(2)["k"] == 257
+    with pytest.raises(RnsError) as err:
+        rk.info(0)
+    assert err.value.status == -8
+    B = 20
+    c = gen.uniform_below(n, B, seed=gen.config_seed(8, 17))
+    cl = gen.to_limbs(c, 512)
+    m = _host(rk.decrypt(_dev(cl), use_crt=True))
+    assert np.array_equal(m, oracle.rsa_crt_batch(cl, p, q, dp, dq, qinv))
+    mi = oracle.rows_to_ints(m)
+    for i in (0, B - 1):
+        assert pow(mi[i], e, n) == c[i]
+    with pytest.raises(RnsError) as err:
+        rk.encrypt(_dev(cl))
+    assert err.value.status == -8
 
 
 def test_rsa1024_config_bit_exact():

@@ -354,6 +354,46 @@ int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_serve
 int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double *latency, rsa_server_stats *stats);
 void rsa_server_free(rsa_server *srv);
 
+/* ------------------------------------------------------------------------ */
+/* Primality steps of key generation                                         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * rsa_trial_division -- the small-primes step of key generation (Sec. 4.3:
+ * testing candidates against the first 10,000 primes): flags[i] = 0 when one
+ * of the first n_primes primes divides candidate i and differs from it (i is
+ * then composite), else 1.
+ *   cand       device, count x limbs little-endian 32-bit limbs
+ *   n_primes   1..10000
+ *   flags      device, count bytes
+ * Asynchronous on hip_stream.  Errors: RNS_EINVAL (null buffer, limbs
+ * outside 1..4096, n_primes outside 1..10000), RNS_EDEVICE.
+ */
+int rsa_trial_division(const uint32_t *cand, size_t count, int limbs, int n_primes, uint8_t *flags,
+                       void *hip_stream);
+
+/*
+ * rsa_miller_rabin -- the Miller-Rabin test of key generation (Sec. 3.2, with
+ * the number of rounds the caller chooses, e.g. FIPS 186's, Sec. 4.3): with
+ * N - 1 = 2^s d, d odd, base a passes when a^d = 1 or a^(2^j d) = N - 1 for
+ * some j < s (mod N); verdict[i] = 1 when every base of candidate i passes
+ * (a probable prime), 0 when one fails (N composite).  The exponentiations
+ * run in RNS in the Montgomery domain: one context per candidate (constants
+ * computed on the host from the candidate), all candidates of a kernel
+ * shape in one grouped launch per step (a^d, then squarings until every
+ * base is decided); the comparisons with 1 and N - 1 run on the host.
+ *   cand       host, count x limbs, odd candidates > 3
+ *   bases      host, count x rounds x limbs, each in [2, N - 2]
+ *   rounds     1..64
+ *   verdict    host, count bytes
+ * Synchronises hip_stream.  Errors: RNS_EINVAL (null buffer, limbs outside
+ * 1..4096, rounds outside 1..64, an even or small candidate, a base out of
+ * range), RNS_ERANGE (no base size for the candidates), RNS_ENOMEM,
+ * RNS_EDEVICE.
+ */
+int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32_t *bases, int rounds,
+                     uint8_t *verdict, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,13 @@ inline Limbs bn_shl(const Limbs &a, unsigned bits) {
     return r;
 }
 
+inline Limbs bn_shr1(const Limbs &a) {
+    Limbs r(a.size(), 0);
+    for (size_t i = 0; i < a.size(); i++) r[i] = (a[i] >> 1) | (i + 1 < a.size() ? a[i + 1] << 31 : 0u);
+    bn_trim(r);
+    return r;
+}
+
 // x mod n by bit-serial shift-and-subtract (n > 0).
 inline Limbs bn_mod(const Limbs &x, const Limbs &n) {
     Limbs r;

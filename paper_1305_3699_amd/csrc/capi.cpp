@@ -336,11 +336,17 @@ int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t bat
     return RNS_OK;
 }
 
+int make_context(const Limbs &N, int L, rns_ctx **out) {
+    *out = nullptr;
+    ModPlan mp;
+    std::string err;
+    int rc = make_modplan(N, L, PlanOptions{}, mp, err);
+    if (rc) return fail(rc, err);
+    return ctx_from_plan(std::move(mp), 5, 0, 0, out);
+}
+
 }  // namespace api
 }  // namespace rnsrsa
-
-namespace {
-}  // namespace
 
 extern "C" {
 

@@ -101,6 +101,9 @@ int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t bat
 // wins; above it the 32-element tile's shared constant loads do (measured for
 // k = 17 .. 129).  Shapes without that alternative are returned unchanged.
 MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev);
+// A context for odd modulus N of L limbs with the default options (smallest
+// base, default engine and tile).  Owned by the caller (delete).
+int make_context(const Limbs &N, int L, rns_ctx **out);
 // One or two exponentiation jobs sharing their inputs (the plain launch).
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,

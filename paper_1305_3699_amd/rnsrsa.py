@@ -106,6 +106,8 @@ _SIGNATURES = {
     "rsa_server_create": ([_P, _S, _P, _P], _I),
     "rsa_server_replay": ([_P, _P, _S, _P, _P], _I),
     "rsa_server_free": ([_P], None),
+    "rsa_trial_division": ([_P, _S, _I, _I, _P, _P], _I),
+    "rsa_miller_rabin": ([_P, _S, _I, _P, _I, _P, _P], _I),
     "rns_plan_create": ([_P, _S, _P, _P], _I),
     "rns_plan_free": ([_P], None),
     "rns_plan_info": ([_P, _P], _I),
@@ -506,3 +508,33 @@ class RsaServer:
             self.close()
         except Exception:
             pass
+
+
+def trial_division(cand, n_primes: int = 10000, out=None, stream=None):
+    """rsa_trial_division: one flag byte per row of ``cand`` (a [count, limbs]
+    int32 device tensor of 32-bit limbs), 0 when one of the first n_primes
+    primes divides the row and differs from it."""
+    import torch
+    count, limbs = cand.shape
+    if out is None:
+        out = torch.empty(count, dtype=torch.uint8, device=cand.device)
+    if out.dtype != torch.uint8 or out.numel() != count or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 tensor of %d flags" % count)
+    _check(lib().rsa_trial_division(_dev_ptr(cand, count, limbs, "cand"), count, limbs, n_primes, out.data_ptr(),
+                                    _stream_handle(stream)))
+    return out
+
+
+def miller_rabin(cand: np.ndarray, bases: np.ndarray, stream=None) -> np.ndarray:
+    """rsa_miller_rabin: ``cand`` [count, limbs] and ``bases`` [count, rounds,
+    limbs] host uint32 limbs; returns one verdict byte per candidate (1: every
+    base passes the strong test)."""
+    cand = np.ascontiguousarray(cand, dtype=np.uint32)
+    bases = np.ascontiguousarray(bases, dtype=np.uint32)
+    if cand.ndim != 2 or bases.ndim != 3 or bases.shape[0] != cand.shape[0] or bases.shape[2] != cand.shape[1]:
+        raise ValueError("cand must be [count, limbs] and bases [count, rounds, limbs]")
+    count, limbs = cand.shape
+    verdict = np.zeros(count, dtype=np.uint8)
+    _check(lib().rsa_miller_rabin(_host_ptr(cand), count, limbs, _host_ptr(bases), bases.shape[1],
+                                  _host_ptr(verdict), _stream_handle(stream)))
+    return verdict

@@ -14,7 +14,7 @@ import pytest
 
 import gen
 import oracle
-from oracle import rns_ref
+from oracle import primality, rns_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -527,3 +527,79 @@ def test_rsa1024_crt_both_tiles(group):
     cl = gen.to_limbs(c, 32)
     got = _host(rk.decrypt(_dev(cl), use_crt=True))
     assert np.array_equal(got, oracle.rsa_crt_batch(cl, key.p, key.q, key.dp, key.dq, key.qinv))
+
+
+# ---------------------------------------------------------------------------
+# Primality steps of key generation
+
+def _flags(t) -> np.ndarray:
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_trial_division_flags():
+    """Flags of the small-primes step against the oracle: every integer in
+    [2, 3000) (one-limb rows, including the listed primes themselves),
+    seeded 1024-bit candidates with crafted multiples of listed primes and
+    of primes just past the list, with the first 10,000 and the first 100
+    primes, and ragged 4096-bit rows."""
+    from paper_1305_3699_amd import trial_division
+    pr = primality.small_primes(10000)
+    small = list(range(2, 3000))
+    got = _flags(trial_division(_dev(gen.to_limbs(small, 1))))
+    assert [int(v) for v in got] == [int(primality.trial_division(n, primes=pr)) for n in small]
+    rng = random.Random(1024)
+    vals = [rng.getrandbits(1024) | (1 << 1023) | 1 for _ in range(500)]
+    vals += [104729 * (rng.getrandbits(1000) | 1), 3 * (rng.getrandbits(1020) | 1),
+             104743 * 104759 * (rng.getrandbits(900) | 1), 541 * 547 * (rng.getrandbits(1000) | 1)]
+    cl = _dev(gen.to_limbs(vals, 32))
+    for n_primes in (10000, 100):
+        got = _flags(trial_division(cl, n_primes=n_primes))
+        assert [int(v) for v in got] == [int(primality.trial_division(n, primes=pr[:n_primes])) for n in vals]
+    big = [rng.getrandbits(4096) | 1 for _ in range(21)]
+    got = _flags(trial_division(_dev(gen.to_limbs(big, 128))))
+    assert [int(v) for v in got] == [int(primality.trial_division(n, primes=pr)) for n in big]
+
+
+def _mr_case(cands, rounds, limbs, seed):
+    from paper_1305_3699_amd import miller_rabin
+    rng = random.Random(seed)
+    bases = [[rng.randrange(2, n - 1) for _ in range(rounds)] for n in cands]
+    got = miller_rabin(gen.to_limbs(cands, limbs), np.stack([gen.to_limbs(b, limbs) for b in bases]))
+    want = [int(primality.miller_rabin(n, b)) for n, b in zip(cands, bases)]
+    assert [int(v) for v in got] == want
+    return want
+
+
+@pytest.mark.parametrize("bits", [512, 1024])
+def test_miller_rabin_verdicts(bits):
+    """Verdicts of the Miller-Rabin step (exponentiations in RNS, one
+    context per candidate) against the oracle: seeded primes, products of
+    two seeded primes and seeded random odd numbers, 5 random bases each."""
+    rng = random.Random(bits)
+    primes = [gen.random_prime(bits, rng) for _ in range(6)]
+    semis = [gen.random_prime(bits // 2, rng) * gen.random_prime(bits // 2, rng) for _ in range(4)]
+    semis = [n for n in semis if n.bit_length() == bits]
+    odd = [rng.getrandbits(bits) | (1 << (bits - 1)) | 1 for _ in range(6)]
+    want = _mr_case(primes + semis + odd, 5, bits // 32, bits + 1)
+    assert want[:6] == [1] * 6 and want[6:6 + len(semis)] == [0] * len(semis)
+
+
+def test_miller_rabin_small_cases():
+    """Strong pseudoprimes, a Carmichael number, and primes and composites
+    whose N - 1 has many factors of two (the squaring loop)."""
+    from paper_1305_3699_amd import miller_rabin
+
+    def mr(n, bases, limbs):
+        return int(miller_rabin(gen.to_limbs([n], limbs), np.stack([gen.to_limbs(bases, limbs)]))[0])
+
+    assert mr(2047, [2], 1) == 1 and mr(2047, [3], 1) == 0
+    assert mr(3215031751, [2, 3, 5, 7], 1) == 1 and mr(3215031751, [2, 3, 5, 7, 11], 1) == 0
+    assert mr(41041, [2], 1) == 0
+    assert mr(65537, [3, 5, 65535], 1) == 1                  # s = 16
+    gold = (1 << 64) - (1 << 32) + 1                          # prime, s = 32
+    assert mr(gold, [2, 3, 12345678901, gold - 2], 2) == 1
+    f6 = (1 << 64) + 1                                        # 274177 * 67280421310721, s = 64
+    assert mr(f6, [3, 5], 3) == 0
+    for n, bases, limbs in ((gold, [7, 11], 2), (f6, [2], 3), (2047, [2, 3], 1)):
+        assert mr(n, bases, limbs) == int(primality.miller_rabin(n, bases))

@@ -8,6 +8,8 @@ import os
 import random
 import re
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -247,6 +249,26 @@ def test_emul_8192_bit_modulus(engine):
     e = rng.getrandbits(40) | (1 << 39)
     out = p.emul_modexp(gen.to_limbs(bases, 256), gen.to_limbs(e, 2)[0])
     assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]
+
+
+def test_keygen_argument_errors():
+    """Argument checks of the primality entry points that fail before any
+    device work (a nonzero count with null buffers, an even candidate, a
+    base outside [2, N - 2], rounds out of range)."""
+    lib = rnsrsa.lib()
+    assert lib.rsa_trial_division(None, 0, 1, 10000, None, None) == 0         # nothing to do
+    assert lib.rsa_trial_division(None, 1, 1, 10000, None, None) == -1
+    cand = np.array([[101]], np.uint32)
+    flags = np.zeros(1, np.uint8)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.rsa_trial_division(ptr(cand), 1, 1, 10001, ptr(flags), None) == -1
+    assert lib.rsa_trial_division(ptr(cand), 1, 0, 10000, ptr(flags), None) == -1
+    bases = np.array([[[2]]], np.uint32)
+    assert lib.rsa_miller_rabin(ptr(np.array([[100]], np.uint32)), 1, 1, ptr(bases), 1, ptr(flags), None) == -1
+    assert lib.rsa_miller_rabin(ptr(cand), 1, 1, ptr(np.array([[[100]]], np.uint32)), 1, ptr(flags), None) == -1
+    assert lib.rsa_miller_rabin(ptr(cand), 1, 1, ptr(np.array([[[1]]], np.uint32)), 1, ptr(flags), None) == -1
+    assert lib.rsa_miller_rabin(ptr(cand), 1, 1, ptr(bases), 0, ptr(flags), None) == -1
+    assert lib.rsa_miller_rabin(ptr(cand), 1, 1, ptr(bases), 65, ptr(flags), None) == -1
 
 
 def test_batch_and_server_argument_errors():

@@ -510,6 +510,67 @@ def run_modmul_sweep(args) -> list:
     return lines
 
 
+def run_keygen(args) -> dict:
+    """The primality steps of key generation on 1024-bit candidates (the
+    primes of an RSA-2048 key; Sec. 4.3): trial division by the first 10,000
+    primes over a batch of seeded odd candidates (one launch, HIP events on
+    its stream), then Miller-Rabin with 5 random bases (FIPS 186-4's count
+    for 1024-bit primes) over the candidates that survive it (wall clock of
+    the synchronous call: per-candidate contexts built on the host, grouped
+    launches, read-backs).  The oracle runs the same steps on a CPU sample."""
+    import numpy as np
+    import torch
+
+    import gen
+    from oracle import primality
+    from paper_1305_3699_amd import miller_rabin, trial_division
+
+    rng = random.Random(gen.config_seed(9, 1))
+    n = args.keygen_candidates
+    cands = [rng.getrandbits(1024) | (3 << 1022) | 1 for _ in range(n)]
+    cl = torch.from_numpy(gen.to_limbs(cands, 32).view(np.int32)).cuda()
+    stream = torch.cuda.current_stream()
+    flags = trial_division(cl, stream=stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(5):
+        trial_division(cl, out=flags, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    td_ms = a.elapsed_time(b) / 5
+    keep = [c for c, f in zip(cands, flags.cpu().numpy()) if f]
+    m = min(args.keygen_mr, len(keep))
+    mr_c = keep[:m]
+    brng = random.Random(gen.config_seed(9, 2))
+    bases = [[brng.randrange(2, c - 1) for _ in range(5)] for c in mr_c]
+    cl_mr, bl_mr = gen.to_limbs(mr_c, 32), np.stack([gen.to_limbs(x, 32) for x in bases])
+    miller_rabin(cl_mr[:4], bl_mr[:4])                     # warm-up (kernels loaded, pools grown)
+    t0 = time.perf_counter()
+    verdict = miller_rabin(cl_mr, bl_mr)
+    mr_s = time.perf_counter() - t0
+    # oracle on a CPU sample of each step
+    pr = primality.small_primes(10000)
+    ns = min(2000, n)
+    t0 = time.perf_counter()
+    td_cpu = [primality.trial_division(c, primes=pr) for c in cands[:ns]]
+    td_cpu_s = time.perf_counter() - t0
+    nm = min(32, m)
+    t0 = time.perf_counter()
+    mr_cpu = [primality.miller_rabin(c, bs) for c, bs in zip(mr_c[:nm], bases[:nm])]
+    mr_cpu_s = time.perf_counter() - t0
+    return {"metric": "1024-bit prime candidates per second, trial division (10,000 primes) and Miller-Rabin (5 bases)",
+            "data": "synthetic", "candidates": n, "survive_trial_division": len(keep),
+            "trial_division": {"ms": round(td_ms, 4), "candidates_per_s": round(n / td_ms * 1e3, 1)},
+            "miller_rabin": {"candidates": m, "probable_primes": int(verdict.sum()), "s": round(mr_s, 4),
+                             "candidates_per_s": round(m / mr_s, 1)},
+            "cpu_oracle": {"trial_division_per_s": round(ns / td_cpu_s, 1),
+                           "miller_rabin_per_s": round(nm / mr_cpu_s, 1), "cores": 1,
+                           "sample": "%d and %d of the same candidates" % (ns, nm),
+                           "matches_gpu": [bool(f) for f in flags.cpu().numpy()[:ns]] == td_cpu
+                           and [bool(v) for v in verdict[:nm]] == mr_cpu}}
+
+
 def run_tile_sweep(args) -> list:
     """Both workgroup tiles of the matrix-core kernel (16 and 32 elements) and
     the library's automatic per-launch choice, for every base size the library
@@ -574,6 +635,10 @@ def main(argv=None) -> int:
     ap.add_argument("--tile-sweep", action="store_true",
                     help="only the timing of both workgroup tiles per base size (one JSON line per k)")
     ap.add_argument("--tile-reps", type=int, default=3)
+    ap.add_argument("--keygen", action="store_true",
+                    help="only the primality steps of key generation (trial division, Miller-Rabin)")
+    ap.add_argument("--keygen-candidates", type=int, default=65536)
+    ap.add_argument("--keygen-mr", type=int, default=512, help="candidates given to Miller-Rabin")
     ap.add_argument("--served-rates", type=float, nargs="+", default=[5000.0, 20000.0, 80000.0])
     ap.add_argument("--served-duration", type=float, default=10.0)
     ap.add_argument("--served-warmup", type=float, default=1.0)
@@ -593,6 +658,9 @@ def main(argv=None) -> int:
     if args.modmul_sweep:
         for line in run_modmul_sweep(args):
             print(json.dumps(line), flush=True)
+        return 0
+    if args.keygen:
+        print(json.dumps(run_keygen(args)), flush=True)
         return 0
     if args.tile_sweep:
         for line in run_tile_sweep(args):

@@ -5,9 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -114,7 +117,8 @@ struct Candidate {
 // each) or the shared `shared_exp` of one limb.
 int exponentiate(const std::vector<Candidate> &cs, const std::vector<size_t> &which, uint32_t *d_x,
                  const uint32_t *d_exps, const uint32_t *d_shared_exp, uint32_t shared_exp, int L, int rounds,
-                 hipStream_t s, std::vector<std::unique_ptr<Scratch>> &keep) {
+                 hipStream_t s, std::vector<std::unique_ptr<Scratch>> &keep,
+                 std::vector<std::vector<MJob>> &host_jobs) {
     std::map<std::tuple<int, int, int>, JobGroup> groups;
     for (size_t i : which) {
         const rns_ctx *c = cs[i].ctx.get();
@@ -161,7 +165,9 @@ int exponentiate(const std::vector<Candidate> &cs, const std::vector<size_t> &wh
             g.shape = t;
             finish_group(g);
         }
-        std::vector<MJob> js;
+        // the job table's host copy lives until the caller synchronises
+        host_jobs.emplace_back();
+        std::vector<MJob> &js = host_jobs.back();
         for (const PlannedJob &J : g.jobs) js.push_back(J.j);
         keep.emplace_back(new Scratch);
         Scratch &jt = *keep.back();
@@ -237,10 +243,33 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
                 c.s++;
             }
             c.d.resize((size_t)L, 0u);
-            rns_ctx *ctx = nullptr;
-            int rc = make_context(N, L, &ctx);
-            if (rc) return rc;
-            c.ctx.reset(ctx);
+        }
+        // one context per candidate, built on a pool of host threads (each
+        // on the caller's device); errors are reported on this thread
+        int dev = 0;
+        hipError_t de = hipGetDevice(&dev);
+        if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
+        std::vector<int> crc(count, RNS_OK);
+        std::atomic<size_t> next{0};
+        auto work = [&] {
+            if (hipSetDevice(dev) != hipSuccess) return;
+            for (size_t i; (i = next.fetch_add(1)) < count;) {
+                Limbs N = bn_from_ptr(cand + i * L, (size_t)L);
+                bn_trim(N);
+                rns_ctx *ctx = nullptr;
+                crc[i] = make_context(N, L, &ctx);
+                cs[i].ctx.reset(ctx);
+            }
+        };
+        const unsigned nthreads =
+            (unsigned)std::min<size_t>(count, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nthreads; t++) pool.emplace_back(work);
+        work();
+        for (std::thread &t : pool) t.join();
+        for (size_t i = 0; i < count; i++) {
+            if (crc[i] == RNS_OK && !cs[i].ctx) crc[i] = RNS_EDEVICE;
+            if (crc[i] != RNS_OK) return fail(crc[i], "context set-up failed for candidate " + std::to_string(i));
         }
         // device: per-candidate exponents d, the rows of x (the bases first)
         std::vector<uint32_t> hd(count * (size_t)L);
@@ -261,20 +290,22 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
         std::vector<uint8_t> st(count * (size_t)rounds, 0);
         std::vector<uint32_t> hx(count * row);
         std::vector<std::unique_ptr<Scratch>> keep;
+        std::vector<std::vector<MJob>> host_jobs;
         std::vector<size_t> which(count);
         for (size_t i = 0; i < count; i++) which[i] = i;
         for (int j = 0; !which.empty(); j++) {
             // j = 0: x = a^d; j > 0: x = x^2
             rc = j == 0 ? exponentiate(cs, which, (uint32_t *)d_x.p, (const uint32_t *)d_exps.p, nullptr, 0, L,
-                                       rounds, s, keep)
+                                       rounds, s, keep, host_jobs)
                         : exponentiate(cs, which, (uint32_t *)d_x.p, nullptr, (const uint32_t *)d_two.p, 2u, L,
-                                       rounds, s, keep);
+                                       rounds, s, keep, host_jobs);
             if (rc) return rc;
             if ((e = hipMemcpyAsync(hx.data(), d_x.p, hx.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
                     hipSuccess ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)
                 return hip_fail(e, "miller-rabin read-back");
             keep.clear();
+            host_jobs.clear();
             std::vector<size_t> next;
             for (size_t i : which) {
                 const Candidate &c = cs[i];

@@ -78,22 +78,12 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
     out.key.assign(ly.key_size(), 0);
     const Limbs &N = mp.N;
 
-    // residues of M_i = M / m_i and M'_j = M' / m'_j modulo other moduli
-    auto Mi_mod = [&](int i, uint32_t m) { return mulmod32(prod_mod32(bs.B, m), invmod32(bs.B[i] % m, m), m); };
-    auto Mpj_mod = [&](int j, uint32_t m) { return mulmod32(prod_mod32(bs.Bp, m), invmod32(bs.Bp[j] % m, m), m); };
-    auto Mi_lo = [&](int i) {
-        uint32_t w = 1;
-        for (int j = 0; j < K; j++)
-            if (j != i) w *= bs.B[j];
-        return w;
-    };
-    auto Mpj_lo = [&](int j) {
-        uint32_t w = 1;
-        for (int t = 0; t < K; t++)
-            if (t != j) w *= bs.Bp[t];
-        return w;
-    };
-
+    // Values of the two extensions' constant matrices, [t + 1][i][a] for output
+    // channel t (-1: the redundant row), input channel i (K: the offset
+    // column, digit a = 0 only) and digit a, computed once: the residues of
+    // M_i = M / m_i modulo a prime m are prod(B) mod m times (m_i mod m)^-1,
+    // and modulo 2^32 prod(B) times m_i^-1 (m_i odd).
+    //
     // The digit words carry xi - kDigitBias; the offset column (input channel K,
     // digit value 1) adds kDigitBias * sum_i C_i back, so each extension is the
     // exact integer sum_i xi_i C_i.
@@ -101,38 +91,53 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
     // BE1 (key table): slot t of B' gets sum_i xi_i M_i * G_t with
     // G_t = N R^2 M^-2 mod m'_t, so that one REDC yields q N M^-1 * (R M^-1);
     // the redundant row gets sum_i xi_i M_i mod 2^32.
+    // BE2 (base table): slot i of B gets sum_j xi'_j M'_j R^2 mod m_i; the
+    // redundant row sum_j xi'_j M'_j mod 2^32.
+    const size_t KK = (size_t)(K + 1) * 4;
+    auto ext_values = [&](const std::vector<uint32_t> &in, const std::vector<uint32_t> &outm, auto scale) {
+        std::vector<int64_t> V((size_t)(K + 1) * KK, 0);
+        uint32_t prod_lo = 1;
+        for (uint32_t m : in) prod_lo *= m;
+        uint32_t sum_lo = 0;
+        for (int i = 0; i < K; i++) {
+            const uint32_t mi_lo = prod_lo * inv2_32(in[i]);
+            sum_lo += mi_lo;
+            for (int a = 0; a < 4; a++) V[(size_t)i * 4 + a] = balanced32(mi_lo << (8 * a));
+        }
+        V[(size_t)K * 4] = balanced32(kDigitBias * sum_lo);
+        for (int t = 0; t < K; t++) {
+            const uint32_t m = outm[t], f = scale(t);
+            const uint32_t P = prod_mod32(in, m);
+            uint64_t sum = 0;
+            int64_t *row = V.data() + (size_t)(t + 1) * KK;
+            for (int i = 0; i < K; i++) {
+                const uint32_t mi = mulmod32(P, invmod32(in[i] % m, m), m);
+                sum = (sum + mi) % m;
+                for (int a = 0; a < 4; a++)
+                    row[(size_t)i * 4 + a] = balanced(mulmod32(mulmod32(mi, pow2_mod(8 * a, m), m), f, m), m);
+            }
+            row[(size_t)K * 4] = balanced(mulmod32(mulmod32(kDigitBias % m, (uint32_t)sum, m), f, m), m);
+        }
+        return V;
+    };
     std::vector<uint32_t> G(K);
     for (int t = 0; t < K; t++) {
         uint32_t m = bs.Bp[t];
         uint32_t minv = invmod32(prod_mod32(bs.B, m), m);
         G[t] = mulmod32(mulmod32(bn_mod_word(N, m), pow2_64_mod(m), m), mulmod32(minv, minv, m), m);
     }
-    uint32_t sumMi_lo = 0, sumMpj_lo = 0;
-    for (int i = 0; i < K; i++) {
-        sumMi_lo += Mi_lo(i);
-        sumMpj_lo += Mpj_lo(i);
-    }
-    auto sum_mod = [&](auto f, uint32_t m) {
-        uint64_t s = 0;
-        for (int i = 0; i < K; i++) s = (s + f(i, m)) % m;
-        return (uint32_t)s;
+    const std::vector<int64_t> V1 = ext_values(bs.B, bs.Bp, [&](int t) { return G[t]; });
+    const std::vector<int64_t> V2 = ext_values(bs.Bp, bs.B, [&](int t) { return pow2_64_mod(bs.B[t]); });
+    fill_tiles(sh, out.key.data() + ly.a1(),
+               [&](int t, int i, int a) -> int64_t { return V1[(size_t)(t + 1) * KK + (size_t)i * 4 + a]; });
+    fill_tiles(sh, out.base.data() + ly.a2(),
+               [&](int t, int j, int a) -> int64_t { return V2[(size_t)(t + 1) * KK + (size_t)j * 4 + a]; });
+    auto Mpj_lo = [&](int j) {
+        uint32_t w = 1;
+        for (int t = 0; t < K; t++)
+            if (t != j) w *= bs.Bp[t];
+        return w;
     };
-    fill_tiles(sh, out.key.data() + ly.a1(), [&](int t, int i, int a) -> int64_t {
-        if (t < 0) return balanced32(i < K ? Mi_lo(i) << (8 * a) : kDigitBias * sumMi_lo);
-        uint32_t m = bs.Bp[t];
-        uint32_t v = i < K ? mulmod32(Mi_mod(i, m), pow2_mod(8 * a, m), m)
-                           : mulmod32(kDigitBias % m, sum_mod(Mi_mod, m), m);
-        return balanced(mulmod32(v, G[t], m), m);
-    });
-    // BE2 (base table): slot i of B gets sum_j xi'_j M'_j R^2 mod m_i; the
-    // redundant row sum_j xi'_j M'_j mod 2^32.
-    fill_tiles(sh, out.base.data() + ly.a2(), [&](int t, int j, int a) -> int64_t {
-        if (t < 0) return balanced32(j < K ? Mpj_lo(j) << (8 * a) : kDigitBias * sumMpj_lo);
-        uint32_t m = bs.B[t];
-        uint32_t v = j < K ? mulmod32(Mpj_mod(j, m), pow2_mod(8 * a, m), m)
-                           : mulmod32(kDigitBias % m, sum_mod(Mpj_mod, m), m);
-        return balanced(mulmod32(v, pow2_64_mod(m), m), m);
-    });
 
     // per-slot constants; junk slots use a valid modulus and zero constants
     const uint32_t mB0 = bs.B[K - 1], mP0 = bs.Bp[K - 1];

@@ -394,6 +394,28 @@ int rsa_trial_division(const uint32_t *cand, size_t count, int limbs, int n_prim
 int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32_t *bases, int rounds,
                      uint8_t *verdict, void *hip_stream);
 
+/*
+ * rsa_keygen -- RSA key generation (Sec. 3.3 and Sec. 4.3): p is the first
+ * candidate of cand_p, in stream order, that passes rsa_trial_division
+ * (first 10,000 primes), has gcd(e, p - 1) = 1 and passes rsa_miller_rabin
+ * with its bases; q likewise from cand_q (q != p).  n = p q;
+ * d = e^-1 mod (p-1)(q-1) by Arazi's formula d = (1 + f (-f^-1 mod e)) / e
+ * with f = (p-1)(q-1) (Sec. 3.1), evaluated on the host's bignums;
+ * dp = d mod (p-1), dq = d mod (q-1), qinv = q^-1 mod p.  The key is loaded
+ * as by rsa_key_load with opts; only n (n_out) and the handle come back, p,
+ * q and d stay in library memory.
+ *   cand_p, cand_q    host, count x half_limbs limbs each
+ *   bases_p, bases_q  host, count x rounds x half_limbs (the Miller-Rabin
+ *                     bases of each candidate, each in [2, c - 2])
+ *   e                 odd, >= 3
+ *   n_out             host, 2 * half_limbs limbs
+ * Synchronises hip_stream.  Errors: RNS_EINVAL (bad argument, a base out of
+ * range), RNS_ERANGE (a stream holds no probable prime), as rsa_key_load.
+ */
+int rsa_keygen(const uint32_t *cand_p, const uint32_t *bases_p, const uint32_t *cand_q, const uint32_t *bases_q,
+               size_t count, int half_limbs, int rounds, uint32_t e, const rns_opts *opts, uint32_t *n_out,
+               rsa_key **out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

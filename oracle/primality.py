@@ -62,3 +62,27 @@ def strong_probable_prime(n: int, a: int) -> bool:
 def miller_rabin(n: int, bases) -> bool:
     """Probable prime iff every base passes the strong test."""
     return all(strong_probable_prime(n, a) for a in bases)
+
+
+def first_prime(cands, bases, e: int, exclude: int = 0, primes: list | None = None) -> int:
+    """The selection rule of key generation from a candidate stream: the
+    first candidate, in order, that is odd and > 3, differs from
+    ``exclude``, survives trial division by the first 10,000 primes, has
+    gcd(e, c - 1) = 1 and passes the strong test to each of its bases.
+    Returns 0 when none does."""
+    pr = primes if primes is not None else small_primes(10000)
+    for c, bs in zip(cands, bases):
+        if c % 2 == 0 or c <= 3 or c == exclude:
+            continue
+        if not trial_division(c, primes=pr) or math.gcd(e, c - 1) != 1:
+            continue
+        if miller_rabin(c, bs):
+            return c
+    return 0
+
+
+def rsa_key_from_primes(p: int, q: int, e: int) -> dict:
+    """n = p q, d = e^-1 mod (p-1)(q-1) (the library's modular inverse), and
+    the CRT parts dp, dq, qinv = q^-1 mod p."""
+    d = pow(e, -1, (p - 1) * (q - 1))
+    return {"n": p * q, "d": d, "dp": d % (p - 1), "dq": d % (q - 1), "qinv": pow(q, -1, p)}

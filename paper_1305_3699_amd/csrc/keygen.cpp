@@ -184,6 +184,54 @@ int exponentiate(const std::vector<Candidate> &cs, const std::vector<size_t> &wh
     return RNS_OK;
 }
 
+// a / w for a word w that divides a.
+Limbs bn_div_word_exact(const Limbs &a, uint32_t w) {
+    Limbs q(a.size(), 0);
+    uint64_t r = 0;
+    for (size_t i = a.size(); i-- > 0;) {
+        const uint64_t x = (r << 32) | a[i];
+        q[i] = (uint32_t)(x / w);
+        r = x % w;
+    }
+    bn_trim(q);
+    return q;
+}
+
+// a^-1 mod p for odd p > 1 by the binary extended Euclidean algorithm
+// (invariants x1 a = u and x2 a = v mod p); false when gcd(a, p) > 1.
+bool bn_modinv_odd(const Limbs &a, const Limbs &p, Limbs &out) {
+    const Limbs one{1};
+    Limbs u = bn_mod(a, p), v = p, x1 = one, x2;
+    auto half = [&](Limbs &x) {
+        if (bn_low(x) & 1u) x = bn_add(x, p);
+        x = bn_shr1(x);
+    };
+    auto sub_mod = [&](const Limbs &x, const Limbs &y) {
+        return bn_cmp(x, y) >= 0 ? bn_sub(x, y) : bn_sub(bn_add(x, p), y);
+    };
+    if (bn_is_zero(u)) return false;
+    while (bn_cmp(u, one) != 0 && bn_cmp(v, one) != 0) {
+        while (!(bn_low(u) & 1u)) {
+            u = bn_shr1(u);
+            half(x1);
+        }
+        while (!(bn_low(v) & 1u)) {
+            v = bn_shr1(v);
+            half(x2);
+        }
+        if (bn_cmp(u, v) >= 0) {
+            u = bn_sub(u, v);
+            x1 = sub_mod(x1, x2);
+        } else {
+            v = bn_sub(v, u);
+            x2 = sub_mod(x2, x1);
+        }
+        if (bn_is_zero(u) || bn_is_zero(v)) return false;
+    }
+    out = bn_cmp(u, one) == 0 ? x1 : x2;
+    return true;
+}
+
 bool rows_equal(const uint32_t *a, const Limbs &b, int L) {
     for (int l = 0; l < L; l++)
         if (a[l] != (l < (int)b.size() ? b[l] : 0u)) return false;
@@ -331,6 +379,116 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
             for (int r = 0; r < rounds; r++) v &= st[i * rounds + r] == 1;
             verdict[i] = v;
         }
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
+    }
+    return ok();
+}
+
+
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kMrChunk = 64;
+
+// The first candidate of a stream (host, count x L limbs, in order) that
+// passes trial division on the GPU, has gcd(e, c - 1) = 1, differs from
+// `exclude` and passes Miller-Rabin with its bases (chunks of up to 64
+// eligible candidates, in order).
+int first_prime(const uint32_t *cand, const uint32_t *bases, size_t count, int L, int rounds, uint32_t e,
+                const Limbs &exclude, hipStream_t s, Limbs &out) {
+    Scratch dc, df;
+    int rc = scratch_alloc(dc, count * (size_t)L * sizeof(uint32_t), s);
+    if (!rc) rc = scratch_alloc(df, count, s);
+    if (rc) return rc;
+    hipError_t he = hipMemcpyAsync(dc.p, cand, count * (size_t)L * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (he != hipSuccess) return hip_fail(he, "hipMemcpyAsync");
+    if ((rc = rsa_trial_division((const uint32_t *)dc.p, count, L, kMaxSmallPrimes, (uint8_t *)df.p, s))) return rc;
+    std::vector<uint8_t> flags(count);
+    if ((he = hipMemcpyAsync(flags.data(), df.p, count, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (he = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(he, "trial division read-back");
+    std::vector<size_t> elig;
+    for (size_t i = 0; i < count; i++) {
+        if (!flags[i]) continue;
+        Limbs c = bn_from_ptr(cand + i * L, (size_t)L);
+        bn_trim(c);
+        if (!(bn_low(c) & 1u) || bn_cmp(c, Limbs{3}) <= 0 || bn_cmp(c, exclude) == 0) continue;
+        const uint32_t cm1 = bn_mod_word(bn_sub(c, Limbs{1}), e);
+        uint32_t a = e, b = cm1;
+        while (b) {
+            const uint32_t t = a % b;
+            a = b;
+            b = t;
+        }
+        if (a == 1) elig.push_back(i);
+    }
+    const size_t row = (size_t)rounds * L;
+    for (size_t start = 0; start < elig.size(); start += kMrChunk) {
+        const size_t n = std::min(kMrChunk, elig.size() - start);
+        std::vector<uint32_t> cc(n * (size_t)L), bb(n * row);
+        for (size_t k = 0; k < n; k++) {
+            std::copy(cand + elig[start + k] * L, cand + (elig[start + k] + 1) * L, cc.begin() + k * L);
+            std::copy(bases + elig[start + k] * row, bases + (elig[start + k] + 1) * row, bb.begin() + k * row);
+        }
+        std::vector<uint8_t> verdict(n);
+        if ((rc = rsa_miller_rabin(cc.data(), n, L, bb.data(), rounds, verdict.data(), s))) return rc;
+        for (size_t k = 0; k < n; k++)
+            if (verdict[k]) {
+                out = bn_from_ptr(cc.data() + k * L, (size_t)L);
+                bn_trim(out);
+                return RNS_OK;
+            }
+    }
+    return fail(RNS_ERANGE, "no probable prime among the candidates");
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsa_keygen(const uint32_t *cand_p, const uint32_t *bases_p, const uint32_t *cand_q, const uint32_t *bases_q,
+               size_t count, int half_limbs, int rounds, uint32_t e, const rns_opts *opts, uint32_t *n_out,
+               rsa_key **out, void *hip_stream) {
+    if (!out) return fail(RNS_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!cand_p || !bases_p || !cand_q || !bases_q || !n_out || count == 0)
+        return fail(RNS_EINVAL, "null buffer or empty candidate streams");
+    if (half_limbs <= 0 || half_limbs > 2048) return fail(RNS_EINVAL, "half_limbs must be in 1..2048");
+    if (rounds <= 0 || rounds > kMaxRounds) return fail(RNS_EINVAL, "rounds must be in 1..64");
+    if (e < 3 || !(e & 1u)) return fail(RNS_EINVAL, "e must be odd and >= 3");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int H = half_limbs;
+    try {
+        Limbs p, q;
+        int rc = first_prime(cand_p, bases_p, count, H, rounds, e, Limbs{}, s, p);
+        if (!rc) rc = first_prime(cand_q, bases_q, count, H, rounds, e, p, s, q);
+        if (rc) return rc;
+        const Limbs one{1};
+        const Limbs pm1 = bn_sub(p, one), qm1 = bn_sub(q, one);
+        const Limbs n = bn_mul(p, q), f = bn_mul(pm1, qm1);
+        // Arazi: d = (1 + f (-f^-1 mod e)) / e
+        const uint32_t fe = bn_mod_word(f, e);
+        const uint32_t fi = invmod32(fe, e);
+        if (!fi) return fail(RNS_EINVAL, "e not coprime to (p-1)(q-1)");
+        const uint32_t t = (e - fi) % e;
+        const Limbs d = bn_div_word_exact(bn_add(one, bn_mul_word(f, t)), e);
+        const Limbs dp = bn_mod(d, pm1), dq = bn_mod(d, qm1);
+        Limbs qinv;
+        if (!bn_modinv_odd(q, p, qinv)) return fail(RNS_EINVAL, "q not invertible mod p");
+        auto limbs = [](const Limbs &x, int k) {
+            Limbs r = x;
+            r.resize((size_t)k, 0u);
+            return r;
+        };
+        const Limbs nl = limbs(n, 2 * H), dl = limbs(d, 2 * H);
+        const Limbs pl = limbs(p, H), ql = limbs(q, H), dpl = limbs(dp, H), dql = limbs(dq, H), qil = limbs(qinv, H);
+        const uint32_t el[1] = {e};
+        if ((rc = rsa_key_load(nl.data(), (size_t)(2 * H), el, 1, dl.data(), pl.data(), ql.data(), dpl.data(),
+                               dql.data(), qil.data(), (size_t)H, opts, out)))
+            return rc;
+        std::copy(nl.begin(), nl.end(), n_out);
     } catch (const std::bad_alloc &) {
         return fail(RNS_ENOMEM, "out of host memory");
     }

@@ -108,6 +108,7 @@ _SIGNATURES = {
     "rsa_server_free": ([_P], None),
     "rsa_trial_division": ([_P, _S, _I, _I, _P, _P], _I),
     "rsa_miller_rabin": ([_P, _S, _I, _P, _I, _P, _P], _I),
+    "rsa_keygen": ([_P, _P, _P, _P, _S, _I, _I, ctypes.c_uint32, _P, _P, _P, _P], _I),
     "rns_plan_create": ([_P, _S, _P, _P], _I),
     "rns_plan_free": ([_P], None),
     "rns_plan_info": ([_P, _P], _I),
@@ -307,6 +308,16 @@ class RsaKey:
         self.has_crt = p is not None
         self._half = half
         del keep
+
+    @classmethod
+    def _adopt(cls, handle, n: int, e: int, n_limbs: int, half: int) -> "RsaKey":
+        """Wrap a key the library built (rsa_keygen)."""
+        k = cls.__new__(cls)
+        k.n, k.e, k.L = n, e, n_limbs
+        k._h = handle
+        k.has_crt = True
+        k._half = half
+        return k
 
     def close(self):
         if getattr(self, "_h", None):
@@ -538,3 +549,23 @@ def miller_rabin(cand: np.ndarray, bases: np.ndarray, stream=None) -> np.ndarray
     _check(lib().rsa_miller_rabin(_host_ptr(cand), count, limbs, _host_ptr(bases), bases.shape[1],
                                   _host_ptr(verdict), _stream_handle(stream)))
     return verdict
+
+
+def keygen(cand_p: np.ndarray, bases_p: np.ndarray, cand_q: np.ndarray, bases_q: np.ndarray, e: int = 65537,
+           stream=None, **opts) -> "RsaKey":
+    """rsa_keygen: candidate streams [count, half_limbs] and their bases
+    [count, rounds, half_limbs] (host uint32 limbs); returns the loaded key,
+    of which only n and e are known to the caller."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in (cand_p, bases_p, cand_q, bases_q)]
+    cp, bp, cq, bq = arrs
+    if cp.ndim != 2 or cp.shape != cq.shape or bp.shape != bq.shape or bp.shape[0] != cp.shape[0] \
+            or bp.shape[2] != cp.shape[1]:
+        raise ValueError("candidates must be [count, half_limbs] and bases [count, rounds, half_limbs]")
+    count, half = cp.shape
+    nl = np.zeros(2 * half, dtype=np.uint32)
+    o, keep = _make_opts(**opts)
+    h = ctypes.c_void_p()
+    _check(lib().rsa_keygen(_host_ptr(cp), _host_ptr(bp), _host_ptr(cq), _host_ptr(bq), count, half, bp.shape[1],
+                            int(e), ctypes.byref(o), _host_ptr(nl), ctypes.byref(h), _stream_handle(stream)))
+    del keep
+    return RsaKey._adopt(h, int.from_bytes(nl.astype("<u4").tobytes(), "little"), int(e), 2 * half, half)

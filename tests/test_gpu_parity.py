@@ -603,3 +603,35 @@ def test_miller_rabin_small_cases():
     assert mr(f6, [3, 5], 3) == 0
     for n, bases, limbs in ((gold, [7, 11], 2), (f6, [2], 3), (2047, [2, 3], 1)):
         assert mr(n, bases, limbs) == int(primality.miller_rabin(n, bases))
+
+
+@pytest.mark.parametrize("bits,count", [(1024, 1500), (2048, 2500)])
+def test_keygen_agrees_with_oracle(bits, count):
+    """RSA key generation from two seeded candidate streams: the primes the
+    library picks (trial division and Miller-Rabin on the GPU) are the
+    oracle's first primes of each stream; n matches, and the key works:
+    encryption against the oracle, decryption with and without CRT back to
+    the messages."""
+    from paper_1305_3699_amd import keygen
+    half = bits // 64
+    rng = random.Random(bits * 7 + count)
+    cp = [rng.getrandbits(32 * half) | (3 << (32 * half - 2)) | 1 for _ in range(count)]
+    cq = [rng.getrandbits(32 * half) | (3 << (32 * half - 2)) | 1 for _ in range(count)]
+    bp = [[rng.randrange(2, c - 1) for _ in range(5)] for c in cp]
+    bq = [[rng.randrange(2, c - 1) for _ in range(5)] for c in cq]
+    stack = lambda bs: np.stack([gen.to_limbs(b, half) for b in bs])
+    key = keygen(gen.to_limbs(cp, half), stack(bp), gen.to_limbs(cq, half), stack(bq), e=65537)
+    p = primality.first_prime(cp, bp, 65537)
+    q = primality.first_prime(cq, bq, 65537, exclude=p)
+    assert p and q and key.n == p * q
+    ref = primality.rsa_key_from_primes(p, q, 65537)
+    L = bits // 32
+    msgs = gen.uniform_below(key.n, 40, seed=bits + 3)
+    ml = gen.to_limbs(msgs, L)
+    c = key.encrypt(_dev(ml))
+    ch = _host(c)
+    assert np.array_equal(ch, oracle.modexp_batch(ml, gen.to_limbs(65537, 1)[0], gen.to_limbs(key.n, L)[0]))
+    assert np.array_equal(_host(key.decrypt(c, use_crt=True)), ml)
+    assert np.array_equal(_host(key.decrypt(c, use_crt=False)), ml)
+    assert oracle.rows_to_ints(ch[:2]) == [pow(m, 65537, key.n) for m in msgs[:2]]
+    assert pow(pow(msgs[0], 65537, key.n), ref["d"], key.n) == msgs[0]

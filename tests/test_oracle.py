@@ -268,3 +268,24 @@ def test_miller_rabin_pins():
     # a product of two 512-bit primes is composite for random bases
     p, q = (1 << 521) - 1, (1 << 607) - 1
     assert not primality.miller_rabin(p * q, [2, 3])
+
+
+def test_first_prime_pins():
+    from oracle import primality
+    # small odd stream: the first prime with gcd(e, p - 1) = 1, by brute force
+    stream = list(range(10001, 11001, 2))
+    bases = [[2, 3] for _ in stream]
+    isprime = lambda n: all(n % d for d in range(2, int(n ** 0.5) + 1))
+    for e in (3, 17, 65537):
+        want = next(c for c in stream if isprime(c) and math.gcd(e, c - 1) == 1)
+        assert primality.first_prime(stream, bases, e, primes=primality.small_primes(10)) == want
+    # exclude skips a prime; an all-composite stream gives 0
+    p0 = primality.first_prime(stream, bases, 65537, primes=primality.small_primes(10))
+    p1 = primality.first_prime(stream, bases, 65537, exclude=p0, primes=primality.small_primes(10))
+    assert p1 > p0 and isprime(p1)
+    assert primality.first_prime([9, 15, 21, 25], [[2]] * 4, 3) == 0
+    # the key from two primes satisfies Euler's theorem for every tested m
+    k = primality.rsa_key_from_primes((1 << 89) - 1, (1 << 61) - 1, 65537)
+    for m in (2, 3, 12345678901234567, k["n"] - 1):
+        assert pow(pow(m, 65537, k["n"]), k["d"], k["n"]) == m
+    assert (k["qinv"] * ((1 << 61) - 1)) % ((1 << 89) - 1) == 1

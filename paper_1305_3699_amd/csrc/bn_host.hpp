@@ -114,18 +114,39 @@ inline Limbs bn_shr1(const Limbs &a) {
     return r;
 }
 
-// x mod n by bit-serial shift-and-subtract (n > 0).
-inline Limbs bn_mod(const Limbs &x, const Limbs &n) {
-    Limbs r;
-    unsigned nb = bn_bits(x);
-    for (unsigned b = nb; b-- > 0;) {
-        r = bn_shl(r, 1);
-        if ((x[b / 32] >> (b % 32)) & 1u) {
-            if (r.empty()) r.push_back(0);
-            r[0] |= 1u;
+// x mod n by bit-serial shift-and-subtract (n > 0), in place on a buffer of
+// n's length plus one limb (the running remainder stays below 2n).
+inline Limbs bn_mod(const Limbs &x, const Limbs &n_in) {
+    Limbs n = n_in;
+    bn_trim(n);
+    const size_t L = n.size();
+    Limbs r(L + 1, 0);
+    for (unsigned b = bn_bits(x); b-- > 0;) {
+        uint32_t carry = (x[b / 32] >> (b % 32)) & 1u;
+        for (size_t i = 0; i <= L; i++) {
+            const uint32_t t = r[i];
+            r[i] = (t << 1) | carry;
+            carry = t >> 31;
         }
-        if (bn_cmp(r, n) >= 0) r = bn_sub(r, n);
+        bool ge = r[L] != 0;
+        if (!ge) {
+            ge = true;
+            for (size_t i = L; i-- > 0;)
+                if (r[i] != n[i]) {
+                    ge = r[i] > n[i];
+                    break;
+                }
+        }
+        if (ge) {
+            int64_t br = 0;
+            for (size_t i = 0; i <= L; i++) {
+                const int64_t t = (int64_t)r[i] - (i < L ? n[i] : 0u) - br;
+                br = t < 0;
+                r[i] = (uint32_t)t;
+            }
+        }
     }
+    bn_trim(r);
     return r;
 }
 

@@ -91,6 +91,15 @@ int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const std::vector
     return RNS_OK;
 }
 
+// The device's copy of a base's matrix-engine table, if one was uploaded.
+uint32_t *resident_mfma_base(const BaseSet *bs) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev_mbases.find(std::make_pair(bs, dev));
+    return it == g_dev_mbases.end() ? nullptr : it->second.second;
+}
+
 int device_base(const std::shared_ptr<const BaseSet> &bs, uint32_t **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -180,8 +189,13 @@ int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx *
     if ((rc = upload(E, &c->d_entry))) return rc;
     if (c->engine == RNS_ENGINE_MATRIX) {
         mfma_shape_for(c->plan.base->K, c->mshape, group);
-        MfmaTables t = make_mfma_tables(c->plan, c->mshape);
-        if ((rc = device_mfma_base(c->plan.base, t.base, &c->d_mbase))) return rc;
+        // the base table is built only when no context has uploaded it yet
+        uint32_t *resident = resident_mfma_base(c->plan.base.get());
+        MfmaTables t = make_mfma_tables(c->plan, c->mshape, resident == nullptr);
+        if (resident)
+            c->d_mbase = resident;
+        else if ((rc = device_mfma_base(c->plan.base, t.base, &c->d_mbase)))
+            return rc;
         if ((rc = upload(t.key, &c->d_mkey))) return rc;
         std::vector<uint32_t> Em = make_mfma_entry_table(c->plan, c->mshape, {c->plan.R2}, c->plan.L);
         if ((rc = upload(Em, &c->d_mentry))) return rc;

@@ -263,18 +263,21 @@ std::vector<uint32_t> make_entry_table(const ModPlan &mp, const std::vector<Limb
     const Layout ly{K, KP};
     const int rows = (int)Y.size() * L, cols = ly.ecols();
     std::vector<uint32_t> e((size_t)rows * cols, 0);
-    for (int j = 0; j < rows; j++) {
-        Limbs v = bn_shl(Y[j / L], 32u * (j % L));   // 2^(32 (j mod L)) * Y_h
-        for (int i = 0; i < K; i++) {
-            uint32_t m = bs.B[i];
-            e[(size_t)j * cols + i] = mulmod32(bn_mod_word(v, m), pow2_64_mod(m), m);
+    // row j: residues of 2^(32 (j mod L)) Y_h (h = j / L) times 2^64, chained
+    // per channel through the factor 2^32 mod m
+    auto fill = [&](uint32_t m, size_t col) {
+        const uint32_t w32 = pow2_32_mod(m), r2 = pow2_64_mod(m);
+        for (size_t h = 0; h < Y.size(); h++) {
+            uint32_t v = mulmod32(bn_mod_word(Y[h], m), r2, m);
+            for (int l = 0; l < L; l++) {
+                e[(h * (size_t)L + l) * cols + col] = v;
+                v = mulmod32(v, w32, m);
+            }
         }
-        for (int t = 0; t < K; t++) {
-            uint32_t m = bs.Bp[t];
-            e[(size_t)j * cols + KP + t] = mulmod32(bn_mod_word(v, m), pow2_64_mod(m), m);
-        }
-        e[(size_t)j * cols + 2 * KP] = bn_low(v);
-    }
+    };
+    for (int i = 0; i < K; i++) fill(bs.B[i], (size_t)i);
+    for (int t = 0; t < K; t++) fill(bs.Bp[t], (size_t)KP + t);
+    for (int j = 0; j < rows; j++) e[(size_t)j * cols + 2 * KP] = (j % L) ? 0u : bn_low(Y[j / L]);
     return e;
 }
 

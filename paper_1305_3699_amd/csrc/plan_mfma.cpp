@@ -68,13 +68,13 @@ void fill_slots(const MfmaShape &sh, uint32_t *dst, size_t field_stride, F f) {
 
 }  // namespace
 
-MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
+MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh, bool with_base) {
     const BaseSet &bs = *mp.base;
     const int K = bs.K;
     const MLayout &ly = sh;
     MfmaTables out;
     out.shape = sh;
-    out.base.assign(ly.base_size(), 0);
+    if (with_base) out.base.assign(ly.base_size(), 0);
     out.key.assign(ly.key_size(), 0);
     const Limbs &N = mp.N;
 
@@ -127,9 +127,11 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
         G[t] = mulmod32(mulmod32(bn_mod_word(N, m), pow2_64_mod(m), m), mulmod32(minv, minv, m), m);
     }
     const std::vector<int64_t> V1 = ext_values(bs.B, bs.Bp, [&](int t) { return G[t]; });
-    const std::vector<int64_t> V2 = ext_values(bs.Bp, bs.B, [&](int t) { return pow2_64_mod(bs.B[t]); });
     fill_tiles(sh, out.key.data() + ly.a1(),
                [&](int t, int i, int a) -> int64_t { return V1[(size_t)(t + 1) * KK + (size_t)i * 4 + a]; });
+    auto okc = [&](int t) { return t >= 0 && t < K; };
+    if (with_base) {
+    const std::vector<int64_t> V2 = ext_values(bs.Bp, bs.B, [&](int t) { return pow2_64_mod(bs.B[t]); });
     fill_tiles(sh, out.base.data() + ly.a2(),
                [&](int t, int j, int a) -> int64_t { return V2[(size_t)(t + 1) * KK + (size_t)j * 4 + a]; });
     auto Mpj_lo = [&](int j) {
@@ -142,7 +144,6 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
     // per-slot constants; junk slots use a valid modulus and zero constants
     const uint32_t mB0 = bs.B[K - 1], mP0 = bs.Bp[K - 1];
     const size_t fs = (size_t)3 * 64;      // [W][MT][3][64]
-    auto okc = [&](int t) { return t >= 0 && t < K; };
     fill_slots(sh, out.base.data() + ly.slotB() + 0 * 64, fs, [&](int t) { return okc(t) ? bs.B[t] : mB0; });
     fill_slots(sh, out.base.data() + ly.slotB() + 1 * 64, fs, [&](int t) { return inv2_32(okc(t) ? bs.B[t] : mB0); });
     fill_slots(sh, out.base.data() + ly.slotB() + 2 * 64, fs, [&](int t) -> uint32_t {
@@ -180,6 +181,7 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh) {
     for (int l = 0; l <= K && l < (int)bs.Mp.size(); l++) out.base[ly.MpF() + l] = bs.Mp[l];
     out.base[ly.bscal() + 0] = inv2_32(bn_low(bs.Mp));
     out.base[ly.bscal() + 1] = inv2_32(bn_low(bs.M));
+    }
 
     // key: c_i = -N^-1 M_i^-1 mod m_i; "one" = M mod N in the kept representation
     fill_slots(sh, out.key.data() + ly.slotC(), 64, [&](int t) -> uint32_t {
@@ -218,23 +220,31 @@ std::vector<uint32_t> make_mfma_entry_table(const ModPlan &mp, const MfmaShape &
     const int rows = (int)Y.size() * L;
     const int SW = 4 * sh.MT;    // slots per wave
     std::vector<uint32_t> e((size_t)rows * cols, 0);
-    for (int j = 0; j < rows; j++) {
-        Limbs v = bn_shl(Y[j / L], 32u * (j % L));
-        for (int w = 0; w < sh.W; w++)
-            for (int s = 0; s < SW; s++) {
-                const int t = mfma_slot_channel(sh, w, s / 4, s % 4);
-                if (t < 0 || t >= K) continue;
-                uint32_t m = bs.B[t];
-                uint32_t r3 = mulmod32(pow2_64_mod(m), pow2_32_mod(m), m);
-                e[(size_t)j * cols + (size_t)w * SW + s] = mulmod32(bn_mod_word(v, m), r3, m);
-                uint32_t mp2 = bs.Bp[t];
-                uint32_t r3p = mulmod32(pow2_64_mod(mp2), pow2_32_mod(mp2), mp2);
-                uint32_t minv = invmod32(prod_mod32(bs.B, mp2), mp2);
-                e[(size_t)j * cols + (size_t)sh.W * SW + (size_t)w * SW + s] =
-                    mulmod32(mulmod32(bn_mod_word(v, mp2), r3p, mp2), minv, mp2);
+    // row j holds the residues of v = Y_h 2^(32 (j mod L)), h = j / L: per
+    // channel, (Y_h mod m) times (2^32 mod m)^(j mod L), times the channel's
+    // constant factor
+    for (int w = 0; w < sh.W; w++)
+        for (int s = 0; s < SW; s++) {
+            const int t = mfma_slot_channel(sh, w, s / 4, s % 4);
+            if (t < 0 || t >= K) continue;
+            const uint32_t m = bs.B[t], mp2 = bs.Bp[t];
+            const uint32_t r3 = mulmod32(pow2_64_mod(m), pow2_32_mod(m), m);
+            const uint32_t r3p = mulmod32(mulmod32(pow2_64_mod(mp2), pow2_32_mod(mp2), mp2),
+                                          invmod32(prod_mod32(bs.B, mp2), mp2), mp2);
+            const uint32_t w32 = pow2_32_mod(m), w32p = pow2_32_mod(mp2);
+            for (size_t h = 0; h < Y.size(); h++) {
+                uint32_t vm = mulmod32(bn_mod_word(Y[h], m), r3, m);
+                uint32_t vp = mulmod32(bn_mod_word(Y[h], mp2), r3p, mp2);
+                for (int l = 0; l < L; l++) {
+                    const size_t j = h * (size_t)L + l;
+                    e[j * cols + (size_t)w * SW + s] = vm;
+                    e[j * cols + (size_t)sh.W * SW + (size_t)w * SW + s] = vp;
+                    vm = mulmod32(vm, w32, m);
+                    vp = mulmod32(vp, w32p, mp2);
+                }
             }
-        e[(size_t)j * cols + cols - 1] = bn_low(v);
-    }
+        }
+    for (int j = 0; j < rows; j++) e[(size_t)j * cols + cols - 1] = (j % L) ? 0u : bn_low(Y[j / L]);
     return e;
 }
 

@@ -34,7 +34,9 @@ struct MfmaTables {
 // `group` elements, else (or for group 0) the first listed for K.
 bool mfma_shape_for(int K, MfmaShape &out, int group = 0);
 
-MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh);
+// with_base = false leaves `base` empty (for a base whose table is already
+// resident) and builds the per-modulus part only.
+MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh, bool with_base = true);
 
 // Entry table: row j = input limb j (value 2^(32 (j mod L)) * Y_(j div L)),
 // columns [B slots | B' slots | redundant], scaled for the representation the

@@ -287,15 +287,10 @@ def test_rsa16384_crt_only_key():
     through the halves works, encryption is refused.  20 ciphertexts (a full
     16-element tile and a ragged one) against the oracle's CRT path, two of
     them also by m^e = c.  The key is the stored seeded fixture."""
-    from paper_1305_3699_amd import RnsError, RsaKey
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rsa16384_key.json")) as fh:
-        fx = json.load(fh)
-    p, q, e = int(fx["p"], 16), int(fx["q"], 16), int(fx["e"])
-    n = p * q
+    from paper_1305_3699_amd import RnsError
+    rk, parts = _rsa16384_key()
+    n, e, p, q, dp, dq, qinv = (parts[k] for k in ("n", "e", "p", "q", "dp", "dq", "qinv"))
     assert n.bit_length() == 16384
-    d = pow(e, -1, (p - 1) * (q - 1))
-    dp, dq, qinv = d % (p - 1), d % (q - 1), pow(q, -1, p)
-    rk = RsaKey(n, e, d, p, q, dp, dq, qinv)
     assert rk.info(1)["k"] == 257 and rk.info(2)["k"] == 257
     with pytest.raises(RnsError) as err:
         rk.info(0)
@@ -310,6 +305,43 @@ def test_rsa16384_crt_only_key():
         assert pow(mi[i], e, n) == c[i]
     with pytest.raises(RnsError) as err:
         rk.encrypt(_dev(cl))
+    assert err.value.status == -8
+
+
+def _rsa16384_key():
+    from paper_1305_3699_amd import RsaKey
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rsa16384_key.json")) as fh:
+        fx = json.load(fh)
+    p, q, e = int(fx["p"], 16), int(fx["q"], 16), int(fx["e"])
+    d = pow(e, -1, (p - 1) * (q - 1))
+    parts = dict(n=p * q, e=e, d=d, p=p, q=q, dp=d % (p - 1), dq=d % (q - 1), qinv=pow(q, -1, p))
+    return RsaKey(**parts), parts
+
+
+def test_batched_with_rsa16384_crt_only_key():
+    """A batch mixing RSA-16384 CRT decryptions (halves on 257-channel bases,
+    a CRT-only key) with RSA-2048 encryptions and decryptions: every output
+    equals the oracle's; an encryption with the CRT-only key is refused at
+    creation."""
+    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RnsError, RsaBatch, RsaKey
+    big, bp = _rsa16384_key()
+    k2 = gen.rsa_key(2048, seed=gen.config_seed(3, 12))
+    small = RsaKey(k2.n, k2.e, k2.d, k2.p, k2.q, k2.dp, k2.dq, k2.qinv)
+    c_big = gen.to_limbs(gen.uniform_below(bp["n"], 18, seed=gen.config_seed(8, 18)), 512)
+    x2 = gen.to_limbs(gen.uniform_below(k2.n, 40, seed=gen.config_seed(8, 19)), 64)
+    ins = [_dev(c_big), _dev(x2), _dev(x2)]
+    outs = [torch.zeros_like(t) for t in ins]
+    ops = [(big, OP_DECRYPT, ins[0], outs[0]), (small, OP_ENCRYPT, ins[1], outs[1]),
+           (small, OP_DECRYPT, ins[2], outs[2])]
+    b = RsaBatch(ops)
+    b.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(_host(outs[0]), oracle.rsa_crt_batch(c_big, bp["p"], bp["q"], bp["dp"], bp["dq"], bp["qinv"]))
+    assert np.array_equal(_host(outs[1]), oracle.modexp_batch(x2, gen.to_limbs(k2.e, 1)[0], gen.to_limbs(k2.n, 64)[0]))
+    assert np.array_equal(_host(outs[2]), oracle.rsa_crt_batch(x2, k2.p, k2.q, k2.dp, k2.dq, k2.qinv))
+    b.close()
+    with pytest.raises(RnsError) as err:
+        RsaBatch([(big, OP_ENCRYPT, ins[0], outs[0])])
     assert err.value.status == -8
 
 

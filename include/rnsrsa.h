@@ -400,8 +400,10 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
  * (first 10,000 primes), has gcd(e, p - 1) = 1 and passes rsa_miller_rabin
  * with its bases; q likewise from cand_q (q != p).  n = p q;
  * d = e^-1 mod (p-1)(q-1) by Arazi's formula d = (1 + f (-f^-1 mod e)) / e
- * with f = (p-1)(q-1) (Sec. 3.1), evaluated on the host's bignums;
- * dp = d mod (p-1), dq = d mod (q-1), qinv = q^-1 mod p.  The key is loaded
+ * with f = (p-1)(q-1), in RNS channel by channel on the GPU (Sec. 3.1; the
+ * scalar -f^-1 mod e from f mod e on the host), back to binary through the
+ * base's exit, and checked (d e = 1 mod f, else RNS_EVERIFY);
+ * dp = d mod (p-1), dq = d mod (q-1), qinv = q^-1 mod p (host).  The key is loaded
  * as by rsa_key_load with opts; only n (n_out) and the handle come back, p,
  * q and d stay in library memory.
  *   cand_p, cand_q    host, count x half_limbs limbs each
@@ -410,7 +412,8 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
  *   e                 odd, >= 3
  *   n_out             host, 2 * half_limbs limbs
  * Synchronises hip_stream.  Errors: RNS_EINVAL (bad argument, a base out of
- * range), RNS_ERANGE (a stream holds no probable prime), as rsa_key_load.
+ * range), RNS_ERANGE (a stream holds no probable prime), RNS_EUNSUPPORTED
+ * (e equal to a channel prime), RNS_EVERIFY, as rsa_key_load.
  */
 int rsa_keygen(const uint32_t *cand_p, const uint32_t *bases_p, const uint32_t *cand_q, const uint32_t *bases_q,
                size_t count, int half_limbs, int rounds, uint32_t e, const rns_opts *opts, uint32_t *n_out,

@@ -16,6 +16,7 @@
 
 #include "bn_host.hpp"
 #include "jobs.hpp"
+#include "kernels_impl.hpp"
 
 using namespace rnsrsa;
 using namespace rnsrsa::api;
@@ -184,17 +185,86 @@ int exponentiate(const std::vector<Candidate> &cs, const std::vector<size_t> &wh
     return RNS_OK;
 }
 
-// a / w for a word w that divides a.
-Limbs bn_div_word_exact(const Limbs &a, uint32_t w) {
-    Limbs q(a.size(), 0);
-    uint64_t r = 0;
-    for (size_t i = a.size(); i-- > 0;) {
-        const uint64_t x = (r << 32) | a[i];
-        q[i] = (uint32_t)(x / w);
-        r = x % w;
+// Arazi's inversion in RNS (Sec. 3.1): d = (1 + f t) / e with t = -f^-1 mod e
+// (a scalar), channel by channel on the owned B' channels and the redundant
+// one: d_j = (1 + f_j t) e^-1 mod m'_j, then d in binary through the base's
+// exit (CRT over B' with alpha from the redundant channel; exact since
+// d < n).  One element per lane (f of fl limbs, d of L limbs).
+template <int K, int W>
+__global__ __launch_bounds__(64 * W) void arazi_kernel(const uint32_t *__restrict__ bc, const uint32_t *__restrict__ mc,
+                                                       const uint32_t *__restrict__ f, int fl, uint32_t t, uint32_t e,
+                                                       uint32_t einv32, int L, uint32_t *__restrict__ d, int batch) {
+    using S = Shp<K, W>;
+    constexpr int KS = S::KS, KP = S::KP;
+    constexpr Layout LY{K, KP};
+    __shared__ uint32_t lds[2 * KP * 64];
+    uint32_t *xip = lds + KP * 64;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int msg = blockIdx.x * 64 + lane;
+    const bool active = msg < batch;
+    const uint32_t *__restrict__ fr = f + (size_t)(active ? msg : 0) * fl;
+    for (int c = 0; c < KS; c++) {
+        const int j = wave * KS + c;
+        if (j >= K) break;
+        const uint32_t m = bc[LY.mBp() + j];
+        uint64_t r = 0;
+        for (int l = fl - 1; l >= 0; l--) r = ((r << 32) | fr[l]) % m;
+        // e^-1 mod m' by Fermat (m' prime, e not a multiple of it)
+        uint64_t inv = 1, b = e % m;
+        for (uint32_t x = m - 2; x; x >>= 1) {
+            if (x & 1u) inv = inv * b % m;
+            b = b * b % m;
+        }
+        const uint64_t dj = (1 + r * t % m) % m * inv % m;
+        xip[j * 64 + lane] = mulredc((uint32_t)dj, bc[LY.MpInv() + j], m, bc[LY.uBp() + j]);   // d_j (M'_j)^-1
     }
-    bn_trim(q);
-    return q;
+    const uint32_t dr = (1u + fr[0] * t) * einv32;                                               // d mod 2^32
+    __syncthreads();
+    uint64_t s2 = 0;
+    for (int j = 0; j < K; j++) s2 += (uint64_t)xip[j * 64 + lane] * bc[LY.C2() + j * LY.crow() + KP];
+    const uint32_t alpha = ((uint32_t)s2 - dr) * bc[LY.scal()];
+    __syncthreads();
+    if (wave != 0) return;
+    rns_exit<K, W>(bc, mc, lds, lds + (L + 1) * 64, xip, alpha, L, lane);
+    if (active)
+        for (int l = 0; l < L; l++) d[(size_t)msg * L + l] = lds[l * 64 + lane];
+}
+
+// d = e^-1 mod f by arazi_kernel on the channel tables of context c (whose
+// modulus exceeds f); returns false on a device error.
+int arazi_inverse(const rns_ctx *c, const Limbs &f, uint32_t e, Limbs &d, hipStream_t s) {
+    const int K = c->plan.base->K, W = c->plan.base->W, L = c->plan.L;
+    for (uint32_t m : c->plan.base->Bp)
+        if (e % m == 0) return fail(RNS_EUNSUPPORTED, "e is a channel prime");
+    const uint32_t fe = bn_mod_word(f, e), fi = invmod32(fe, e);
+    if (!fi) return fail(RNS_EINVAL, "e not coprime to (p-1)(q-1)");
+    const uint32_t t = (e - fi) % e;
+    Limbs fl = f;
+    fl.resize((size_t)L, 0u);
+    Scratch df, dd;
+    int rc = scratch_alloc(df, (size_t)L * sizeof(uint32_t), s);
+    if (!rc) rc = scratch_alloc(dd, (size_t)L * sizeof(uint32_t), s);
+    if (rc) return rc;
+    hipError_t he = hipMemcpyAsync(df.p, fl.data(), (size_t)L * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (he != hipSuccess) return hip_fail(he, "hipMemcpyAsync");
+    bool launched = false;
+#define RNSRSA_SHAPE(k, w)                                                                                        \
+    if (!launched && K == k && W == w) {                                                                      \
+        hipLaunchKernelGGL((arazi_kernel<k, w>), dim3(1), dim3(64 * w), 0, s, c->d_base, c->d_mod,              \
+                           (const uint32_t *)df.p, L, t, e, inv2_32(e), L, (uint32_t *)dd.p, 1);               \
+        launched = true;                                                                                          \
+    }
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+    if (!launched) return fail(RNS_EUNSUPPORTED, "no channel kernel for this k");
+    if ((he = hipGetLastError()) != hipSuccess) return hip_fail(he, "arazi launch");
+    d.assign((size_t)L, 0u);
+    if ((he = hipMemcpyAsync(d.data(), dd.p, (size_t)L * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (he = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(he, "arazi read-back");
+    bn_trim(d);
+    return RNS_OK;
 }
 
 // a^-1 mod p for odd p > 1 by the binary extended Euclidean algorithm
@@ -468,12 +538,15 @@ int rsa_keygen(const uint32_t *cand_p, const uint32_t *bases_p, const uint32_t *
         const Limbs one{1};
         const Limbs pm1 = bn_sub(p, one), qm1 = bn_sub(q, one);
         const Limbs n = bn_mul(p, q), f = bn_mul(pm1, qm1);
-        // Arazi: d = (1 + f (-f^-1 mod e)) / e
-        const uint32_t fe = bn_mod_word(f, e);
-        const uint32_t fi = invmod32(fe, e);
-        if (!fi) return fail(RNS_EINVAL, "e not coprime to (p-1)(q-1)");
-        const uint32_t t = (e - fi) % e;
-        const Limbs d = bn_div_word_exact(bn_add(one, bn_mul_word(f, t)), e);
+        // d = e^-1 mod f by Arazi's formula in RNS on the GPU, on the channel
+        // tables of a context for n (n > f > d), checked on the host
+        rns_ctx *nc = nullptr;
+        if ((rc = make_context(n, 2 * H, &nc))) return rc;
+        std::unique_ptr<rns_ctx> nctx(nc);
+        Limbs d;
+        if ((rc = arazi_inverse(nc, f, e, d, s))) return rc;
+        if (bn_cmp(bn_mod(bn_mul_word(d, e), f), one) != 0)
+            return fail(RNS_EVERIFY, "d e != 1 mod (p-1)(q-1)");
         const Limbs dp = bn_mod(d, pm1), dq = bn_mod(d, qm1);
         Limbs qinv;
         if (!bn_modinv_odd(q, p, qinv)) return fail(RNS_EINVAL, "q not invertible mod p");

@@ -232,7 +232,8 @@ __global__ __launch_bounds__(64 * W) void arazi_kernel(const uint32_t *__restric
 }
 
 // d = e^-1 mod f by arazi_kernel on the channel tables of context c (whose
-// modulus exceeds f); returns false on a device error.
+// modulus exceeds f).  Returns RNS_OK or the error code (also recorded for
+// rns_last_error).
 int arazi_inverse(const rns_ctx *c, const Limbs &f, uint32_t e, Limbs &d, hipStream_t s) {
     const int K = c->plan.base->K, W = c->plan.base->W, L = c->plan.L;
     for (uint32_t m : c->plan.base->Bp)

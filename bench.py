@@ -594,6 +594,85 @@ def run_keygen(args) -> dict:
                            and [bool(v) for v in verdict[:nm]] == mr_cpu}}
 
 
+def run_configs(args) -> list:
+    """The other measured configurations, one line each: the RSA-1024 round
+    trip (64 encryptions, 64 plain decryptions, one launch each), RSA-2048
+    CRT decryption of 16384 ciphertexts per fixed window width w = 1..6,
+    exponents of 4096 / 8192 / 16128 bits on 1024 bases modulo a 2048-bit n,
+    and RSA-3072 / RSA-4096 CRT decryption of 4096 ciphertexts.  HIP-event
+    means over `--config-reps` launches after one untimed."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1305_3699_amd import RnsContext, RsaKey
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = args.config_reps
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+    lines = []
+    # RSA-1024 round trip
+    k1 = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
+    r1 = RsaKey(k1.n, k1.e, k1.d, k1.p, k1.q, k1.dp, k1.dq, k1.qinv)
+    m1 = dev(gen.to_limbs(gen.uniform_below(k1.n, 64, seed=gen.config_seed(1, 2)), 32))
+    c1 = r1.encrypt(m1)
+    enc_ms = timed(lambda: r1.encrypt(m1, out=c1), reps)
+    out1 = torch.empty_like(c1)
+    dec_ms = timed(lambda: r1.decrypt(c1, use_crt=False, out=out1), reps)
+    torch.cuda.synchronize()
+    lines.append({"config": "RSA-1024, 64 messages: encrypt then plain (non-CRT) decrypt, one launch each",
+                  "encrypt_ms": round(enc_ms, 4), "decrypt_ms": round(dec_ms, 4),
+                  "round_trip_ok": bool(torch.equal(out1, m1))})
+    # RSA-2048 CRT per window
+    k2 = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
+    c2 = dev(gen.to_limbs(gen.uniform_below(k2.n, 16384, seed=gen.config_seed(2, 2)), 64))
+    row = {"config": "RSA-2048 CRT decryption of 16384 ciphertexts, fixed window width w", "decrypts_per_s": {}}
+    for w in range(1, 7):
+        rk = RsaKey(k2.n, k2.e, k2.d, k2.p, k2.q, k2.dp, k2.dq, k2.qinv, window=w)
+        out = torch.empty_like(c2)
+        ms = timed(lambda: rk.decrypt(c2, use_crt=True, out=out), reps)
+        row["decrypts_per_s"][str(w)] = round(16384 / ms * 1e3, 1)
+        rk.close()
+    lines.append(row)
+    # long exponents modulo a 2048-bit n
+    k3 = gen.rsa_key(2048, seed=gen.config_seed(3, 1))
+    ctx = RnsContext(k3.n, 64, window=6)
+    x3 = dev(gen.to_limbs(gen.uniform_below(k3.n, 1024, seed=gen.config_seed(3, 2)), 64))
+    row = {"config": "1024 bases modulo a 2048-bit n (k = %d), one shared exponent" % ctx.info["k"],
+           "modexps_per_s": {}, "ms": {}}
+    for eb in (4096, 8192, 16128):
+        e = gen.random_exponent(eb, seed=gen.config_seed(3, 3) + eb)
+        el = dev(gen.to_limbs(e, (eb + 31) // 32)[0])
+        out = torch.empty_like(x3)
+        ms = timed(lambda: ctx.modexp(x3, el, out=out), reps)
+        row["modexps_per_s"][str(eb)] = round(1024 / ms * 1e3, 1)
+        row["ms"][str(eb)] = round(ms, 3)
+    lines.append(row)
+    # RSA-3072 / RSA-4096 CRT
+    row = {"config": "RSA-3072 and RSA-4096 CRT decryption of 4096 ciphertexts", "decrypts_per_s": {}, "ms": {}}
+    for bits in (3072, 4096):
+        k = gen.rsa_key(bits, seed=gen.config_seed(3, 10 + bits // 1024))
+        rk = RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv)
+        c = dev(gen.to_limbs(gen.uniform_below(k.n, 4096, seed=gen.config_seed(3, 20 + bits // 1024)), bits // 32))
+        out = torch.empty_like(c)
+        ms = timed(lambda: rk.decrypt(c, use_crt=True, out=out), reps)
+        row["decrypts_per_s"][str(bits)] = round(4096 / ms * 1e3, 1)
+        row["ms"][str(bits)] = round(ms, 3)
+        rk.close()
+    lines.append(row)
+    return lines
+
+
 def run_tile_sweep(args) -> list:
     """Both workgroup tiles of the matrix-core kernel (16 and 32 elements) and
     the library's automatic per-launch choice, for every base size the library
@@ -658,6 +737,10 @@ def main(argv=None) -> int:
     ap.add_argument("--tile-sweep", action="store_true",
                     help="only the timing of both workgroup tiles per base size (one JSON line per k)")
     ap.add_argument("--tile-reps", type=int, default=3)
+    ap.add_argument("--configs", action="store_true",
+                    help="only the other measured configurations (RSA-1024 round trip, windows, long exponents, "
+                         "RSA-3072/4096 CRT)")
+    ap.add_argument("--config-reps", type=int, default=5)
     ap.add_argument("--keygen", action="store_true",
                     help="only the primality steps of key generation (trial division, Miller-Rabin)")
     ap.add_argument("--keygen-candidates", type=int, default=65536)
@@ -681,6 +764,10 @@ def main(argv=None) -> int:
         return 2
     if args.modmul_sweep:
         for line in run_modmul_sweep(args):
+            print(json.dumps(line), flush=True)
+        return 0
+    if args.configs:
+        for line in run_configs(args):
             print(json.dumps(line), flush=True)
         return 0
     if args.keygen:

@@ -667,3 +667,47 @@ def test_keygen_agrees_with_oracle(bits, count):
     assert np.array_equal(_host(key.decrypt(c, use_crt=False)), ml)
     assert oracle.rows_to_ints(ch[:2]) == [pow(m, 65537, key.n) for m in msgs[:2]]
     assert pow(pow(msgs[0], 65537, key.n), ref["d"], key.n) == msgs[0]
+
+
+def test_keygen_and_primality_edges():
+    """Edges of the key generation entry points: a stream without a prime
+    (RNS_ERANGE), trial division at the 4096-limb maximum, Miller-Rabin with
+    the maximum of 64 rounds."""
+    from paper_1305_3699_amd import RnsError, keygen, miller_rabin, trial_division
+    half = 16
+    base = (3 << 510) + 1
+    base += (3 - base % 3) % 3
+    base += 3 if base % 2 == 0 else 0
+    comp = [base + 6 * i for i in range(32)]                          # odd multiples of 3: no prime
+    assert all(c % 3 == 0 and c % 2 == 1 and c.bit_length() == 512 for c in comp)
+    b = np.stack([gen.to_limbs([2, 3, 5, 7, 11], half) for _ in comp])
+    cl = gen.to_limbs(comp, half)
+    with pytest.raises(RnsError) as err:
+        keygen(cl, b, cl, b)
+    assert err.value.status == -2
+    rng = random.Random(4096)
+    big = [rng.getrandbits(4096 * 32) | 1 for _ in range(3)] + [3 * ((1 << (4096 * 32 - 3)) + 1)]
+    got = _flags(trial_division(_dev(gen.to_limbs(big, 4096))))
+    pr = primality.small_primes(10000)
+    assert [int(v) for v in got] == [int(primality.trial_division(n, primes=pr)) for n in big]
+    p = (1 << 127) - 1
+    bases = [rng.randrange(2, p - 1) for _ in range(64)]
+    assert int(miller_rabin(gen.to_limbs([p], 4), np.stack([gen.to_limbs(bases, 4)]))[0]) == 1
+
+
+def test_served_refuses_encryption_with_crt_only_key():
+    """A served trace that asks a CRT-only key (RSA-16384) to encrypt is
+    refused before any work (RNS_EUNSUPPORTED); its CRT decryptions are
+    served and match the oracle."""
+    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RnsError, RsaServer
+    big, bp = _rsa16384_key()
+    srv = RsaServer([big], max_inflight=2)
+    msgs = gen.to_limbs(gen.uniform_below(bp["n"], 4, seed=gen.config_seed(8, 21)), 512)
+    kidx = np.zeros(4, np.int32)
+    arrival = np.linspace(0.0, 0.001, 4)
+    with pytest.raises(RnsError) as err:
+        srv.replay(kidx, np.array([OP_DECRYPT, OP_ENCRYPT, OP_DECRYPT, OP_DECRYPT], np.int32), arrival, msgs)
+    assert err.value.status == -8
+    outs, lat, stats = srv.replay(kidx, np.full(4, OP_DECRYPT, np.int32), arrival, msgs)
+    assert np.array_equal(outs, oracle.rsa_crt_batch(msgs, bp["p"], bp["q"], bp["dp"], bp["dq"], bp["qinv"]))
+    srv.close()

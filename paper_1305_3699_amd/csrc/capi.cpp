@@ -156,20 +156,24 @@ int choose_engine(const BaseSet &bs, int requested, int group, int *engine) {
     const int K = bs.K;
     if (requested < 0 || requested > RNS_ENGINE_MATRIX) return fail(RNS_EINVAL, "bad engine");
     if (group != 0 && group != 16 && group != 32) return fail(RNS_EINVAL, "group must be 0, 16 or 32");
+    const bool channel_ok = channel_kernel(K, bs.W);
     if (requested == RNS_ENGINE_CHANNEL) {
+        if (!channel_ok) return fail(RNS_EUNSUPPORTED, "no channel-engine kernel for this k (matrix cores only)");
         *engine = RNS_ENGINE_CHANNEL;
         return RNS_OK;
     }
     MfmaShape sh;
     bool primes_ok = true;
-    for (uint32_t m : bs.Bp) primes_ok = primes_ok && m <= kMaxPrimeP;
+    for (uint32_t m : bs.B) primes_ok = primes_ok && mfma_prime_fits(m, K, false);
+    for (uint32_t m : bs.Bp) primes_ok = primes_ok && mfma_prime_fits(m, K, true);
     if (mfma_shape_for(K, sh, group) && primes_ok) {
         *engine = RNS_ENGINE_MATRIX;
         return RNS_OK;
     }
-    if (requested == RNS_ENGINE_MATRIX)
+    if (requested == RNS_ENGINE_MATRIX || !channel_ok)
         return fail(RNS_EUNSUPPORTED, primes_ok ? "no matrix-core kernel for this k"
-                                                : "matrix cores need every B' prime <= 2^32 - 2^18");
+                                                : "a channel prime is outside the matrix engine's one-step reduction "
+                                                  "bounds (B' primes <= 2^32 - 2^18, all primes large enough)");
     *engine = RNS_ENGINE_CHANNEL;
     return RNS_OK;
 }
@@ -440,6 +444,7 @@ int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint3
     if (!x || !y || !out) return fail(RNS_EINVAL, "null buffer");
     if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
     const BaseSet &bs = *ctx->plan.base;
+    if (!channel_kernel(bs.K, bs.W)) return fail(RNS_EUNSUPPORTED, "no single-product kernel for this k");
     MontMulLaunch a{ctx->d_base, ctx->d_mod, x, y, out, (int)batch};
     hipError_t e = launch_montmul(bs.K, bs.W, a, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "montmul launch");
@@ -478,15 +483,15 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
                 po.waves = 0;
                 rc = make_modplan(limbs_of(n, n_limbs), (int)n_limbs, po, mp, err);
             }
-            if (rc == RNS_ERANGE && all_crt) {
-                // no base covers the full modulus: a CRT-only key (decryption
-                // through the halves; encryption is unsupported)
-                rc = RNS_OK;
-            } else if (rc) {
-                return fail(rc, err);
+            // a CRT-only key when no base covers the full modulus or no kernel
+            // of the requested engine runs it: decryption through the halves,
+            // encryption unsupported
+            if (rc) {
+                if (!(rc == RNS_ERANGE && all_crt)) return fail(rc, err);
             } else if ((rc = ctx_from_plan(std::move(mp), window, engine, group, &key->n))) {
-                return rc;
+                if (!(rc == RNS_EUNSUPPORTED && all_crt)) return rc;   // message recorded by ctx_from_plan
             }
+            rc = RNS_OK;
         }
         key->h_e.assign(e, e + e_limbs);
         if (d) key->h_d.assign(d, d + n_limbs);
@@ -677,8 +682,9 @@ int rns_emul_modexp(const rns_plan *plan, const uint32_t *base, const uint32_t *
     if (exp_stride != 0 && exp_stride < exp_limbs) return fail(RNS_EINVAL, "exp_stride below exp_limbs");
     if (plan->engine == RNS_ENGINE_MATRIX) {
         std::vector<uint32_t> E = make_mfma_entry_table(plan->plan, plan->mt.shape, {plan->plan.R2}, plan->plan.L);
-        emul_modexp_mfma(plan->plan, plan->mt, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride, plan->window,
-                         out, batch);
+        if (!emul_modexp_mfma(plan->plan, plan->mt, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride,
+                              plan->window, out, batch))
+            return fail(RNS_EVERIFY, "a one-step reduction of the matrix-engine model left [0, m 2^32)");
         return ok();
     }
     std::vector<uint32_t> E = make_entry_table(plan->plan, {plan->plan.R2}, plan->plan.L);

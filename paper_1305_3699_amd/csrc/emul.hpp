@@ -17,7 +17,9 @@ void emul_modexp(const ModPlan &mp, const std::vector<uint32_t> &E, int in_limbs
                  size_t batch);
 
 // Host model of the matrix-core kernel (emul_mfma.cpp), same contract.
-void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
+// Returns false when a one-REDC step saw an input outside [0, m 2^32), where
+// the kernel's result would be wrong.
+bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
                       const uint32_t *base, const uint32_t *exp, int exp_limbs, size_t exp_stride, int window,
                       uint32_t *out, size_t batch);
 

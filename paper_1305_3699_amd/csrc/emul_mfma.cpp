@@ -62,8 +62,15 @@ struct MSt {
 
 uint32_t pack_digits(uint32_t v) { return v ^ kDigitBias; }
 
-uint32_t reduce_signed(int64_t S, uint32_t m, uint32_t u) {
-    const uint64_t x = (uint64_t)(S + ((int64_t)m << 17));
+// cleared when a REDC input of steps (iii)/(iv) leaves [0, m 2^32), where the
+// kernel's one-step reduction would be wrong
+thread_local bool t_in_range = true;
+
+// REDC of P + S + m 2^sh, the kernel's reduction of an extension output
+uint32_t reduce_offset(uint64_t P, int64_t S, uint32_t m, uint32_t u, int sh) {
+    const __int128 T = (__int128)P + S + ((__int128)m << sh);
+    if (T < 0 || T >= ((__int128)m << 32)) t_in_range = false;
+    const uint64_t x = (uint64_t)T;
     return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
 }
 
@@ -81,7 +88,8 @@ int64_t extension(const std::vector<int64_t> &V, size_t vrow, const std::vector<
 // (xi' digits) and returns nothing; with full == false skips the second extension.
 void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::vector<uint32_t> &dig2, bool full) {
     const MLayout &ly = c.ly;
-    const int SW = 4 * ly.MT, NM = ly.NM(), KK = 64 * ly.KSTEPS(), BROW = ly.BROW(), K = c.K;
+    const int SW = 4 * ly.MT, NM = ly.NM(), KK = 64 * ly.KSTEPS(), BROW = ly.BROW();
+    const int sh = mfma_offset_shift(c.K);
     const uint32_t Mpinv_r = c.T.base[ly.bscal()], Minv_r = c.T.base[ly.bscal() + 1], N_r = c.T.key[ly.kscal()];
     auto idx = [&](int w, int s, int e) { return ((size_t)w * SW + s) * NM + e; };
     for (int w = 0; w < ly.W; w++)
@@ -106,15 +114,13 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
             const uint32_t H = c.slot(ly.slotP(), 4, 2, w, s);
             for (int e = 0; e < NM; e++) {
                 const int64_t S = extension(c.V1, ((size_t)w * SW + s) * KK, dig1, e, KK, BROW);
-                // x' y' + S + m 2^17 < m 2^32 for m <= kMaxPrimeP: one REDC
-                const uint64_t T = (uint64_t)x.p[idx(w, s, e)] * y.p[idx(w, s, e)] + (uint64_t)(S + ((int64_t)m << 17));
-                const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, u);
+                // x' y' + S + m 2^sh in one REDC
+                const uint32_t r = reduce_offset((uint64_t)x.p[idx(w, s, e)] * y.p[idx(w, s, e)], S, m, u, sh);
                 x.p[idx(w, s, e)] = r;
                 if (c.real(w, s)) dig2[(size_t)e * BROW + c.channel(w, s)] = pack_digits(mulredc(r, H, m, u));
             }
         }
     for (int e = 0; e < NM; e++) x.r[e] = rr[e];
-    (void)K;
     if (!full) return;
     for (int w = 0; w < ly.W; w++) {
         std::vector<uint32_t> alpha(NM);
@@ -127,7 +133,7 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
             const uint32_t nu = c.slot(ly.slotB(), 3, 2, w, s);
             for (int e = 0; e < NM; e++) {
                 const int64_t S = extension(c.V2, ((size_t)w * SW + s) * KK, dig2, e, KK, BROW);
-                x.b[idx(w, s, e)] = reduce_signed(S + (int64_t)((uint64_t)alpha[e] * nu), m, u);
+                x.b[idx(w, s, e)] = reduce_offset((uint64_t)alpha[e] * nu, S, m, u, sh);
             }
         }
     }
@@ -143,9 +149,10 @@ uint32_t digit_of(const uint32_t *e, int nlimbs, int nd, int w, int di) {
 
 }  // namespace
 
-void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
+bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
                       const uint32_t *base, const uint32_t *exp, int exp_limbs, size_t exp_stride, int window,
                       uint32_t *out, size_t batch) {
+    t_in_range = true;
     const MCtx c(T);
     const MLayout &ly = c.ly;
     const int K = c.K, SW = 4 * ly.MT, NM = ly.NM(), BROW = ly.BROW(), L = mp.L;
@@ -320,6 +327,7 @@ void emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
             std::copy(acc.begin(), acc.begin() + L, out + (g0 + e) * (size_t)L);
         }
     }
+    return t_in_range;
 }
 
 }  // namespace rnsrsa

@@ -36,6 +36,7 @@ struct MShp {
     static constexpr int NM = LY.NM();
     static constexpr int SLOTS = LY.SLOTS();
     static constexpr int ECOLS = (int)LY.ecols();
+    static constexpr int OSH = mfma_offset_shift(K);   // REDC offset m 2^OSH of steps (iii) and (iv)
     // smallest b with 2^b > K+1: an exit value below (K+2)N has quotient < 2^b
     static constexpr int qbits() {
         int b = 0;
@@ -135,9 +136,10 @@ __device__ __forceinline__ uint32_t mfma_combine_lo(const mfma_v4i &d) {
     return t1 + (t2 << 16);
 }
 
-// acc + the signed value S of the four byte partials, mod 2^64.  |S| < 2^48:
-// at most 4*129+1 terms of |A byte value| <= 0x80808080 times |digit byte|
-// <= 128.  Callers add m 2^17 > 2^48 so that the REDC input is positive.  The factors
+// acc + the signed value S of the four byte partials, mod 2^64.  |S| is at
+// most mfma_sum_bound(K): 4K+1 terms of |A byte value| <= 0x80808080 times
+// |digit byte| <= 128.  Callers add m 2^OSH > |S| so that the REDC input is
+// positive (the host checks every channel prime).  The factors
 // k16 = 2^16 and k1 = 1 come from scalar registers the compiler cannot see
 // through, so each step is one signed 32x32+64 multiply-add instead of a
 // sign extension, a 64-bit shift and a 64-bit add.
@@ -263,9 +265,9 @@ __device__ __forceinline__ void mfma_mm(const MConstOf<K, W, MT, NT> &C, MState<
         for (int nt = 0; nt < NT; nt++) {
             const MSlotP sp = C.slotP(mt);
             const uint32_t m = sp.m;
-            // x' y' + S in one REDC (S + m 2^17 > 0; the sum stays below
-            // m 2^32 for every B' prime m <= kMaxPrimeP)
-            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)x.p[mt][nt] * y.p[mt][nt] + ((uint64_t)m << 17),
+            // x' y' + S in one REDC (S + m 2^OSH > 0; the sum stays below
+            // m 2^32 for every B' prime that mfma_prime_fits accepts)
+            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)x.p[mt][nt] * y.p[mt][nt] + ((uint64_t)m << S::OSH),
                                                C.k16, C.k1);
             const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, sp.u);
             x.p[mt][nt] = r;
@@ -291,9 +293,9 @@ __device__ __forceinline__ void mfma_mm(const MConstOf<K, W, MT, NT> &C, MState<
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            // S + alpha nu + m 2^17 (alpha nu < 2^40): positive, below m 2^32
+            // S + alpha nu + m 2^OSH (alpha nu < 2^42): positive, below m 2^32
             const MSlotB sb = C.slotB(mt);
-            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)alpha[nt] * sb.nu + ((uint64_t)sb.m << 17),
+            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)alpha[nt] * sb.nu + ((uint64_t)sb.m << S::OSH),
                                                C.k16, C.k1);
             x.b[mt][nt] = redc((uint32_t)T, (uint32_t)(T >> 32), sb.m, sb.u);
         }

@@ -21,9 +21,29 @@ constexpr uint32_t kDigitBias = 0x80808080u;
 // the range of four signed bytes.
 constexpr uint32_t kDigitSplit = 0x7F7F7F80u;
 // Largest B' prime the matrix engine accepts: step (iii) of a product reduces
-// x' y' + S + m 2^17 (|S| < 2^48) in one REDC, whose input must stay below
-// m 2^32; that holds for m <= 2^32 - 2^18.
+// x' y' + S + m 2^17 in one REDC, whose input must stay below m 2^32; with
+// |S| < 2^48 that holds for m <= 2^32 - 2^18.
 constexpr uint32_t kMaxPrimeP = 0xFFFC0000u;
+
+// Bound on |S|, the signed value of an extension output's four byte partials:
+// 4K digit terms, each a constant of magnitude <= 0x80808080 times a digit
+// byte of magnitude <= 128, plus the offset column (digit 1).
+constexpr uint64_t mfma_sum_bound(int K) { return (uint64_t)4 * K * 0x80808080ull * 128u + 0x80808080ull; }
+
+// Steps (iii) and (iv) add m 2^s to S so that the REDC input is positive:
+// s = 17 up to 256 + 1 channels (|S| about 2^48), 18 beyond (about 2^49).
+constexpr int mfma_offset_shift(int K) { return K > 257 ? 18 : 17; }
+
+// Whether channel prime m keeps the one-REDC steps exact: S + m 2^s > 0 for
+// a prime of B (step (iv) adds alpha nu < K m, far below m 2^32), and for a
+// prime of B' also x' y' + S + m 2^s < m 2^32 with x', y' < m, i.e.
+// m 2^s + |S| < m (2^32 - m) + 2m - 1 (every term below 2^63).
+constexpr bool mfma_prime_fits(uint32_t m, int K, bool in_bprime) {
+    const uint64_t off = (uint64_t)m << mfma_offset_shift(K), smax = mfma_sum_bound(K);
+    if (off <= smax) return false;
+    if (!in_bprime) return true;
+    return m <= kMaxPrimeP && off + smax < (uint64_t)m * ((1ull << 32) - m) + 2ull * m - 1;
+}
 
 struct MLayout {
     int K, W, MT, NT;

@@ -14,10 +14,20 @@ namespace rnsrsa {
 const std::vector<Shape> &supported_shapes() {
     static const std::vector<Shape> shapes = {
 #define RNSRSA_SHAPE(K, W) {K, W},
+#define RNSRSA_BASE_SHAPE(K, W) {K, W},
 #include "kernel_configs.inc"
+#undef RNSRSA_BASE_SHAPE
 #undef RNSRSA_SHAPE
     };
     return shapes;
+}
+
+bool channel_kernel(int K, int W) {
+#define RNSRSA_SHAPE(k, w) \
+    if (K == k && W == w) return true;
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+    return false;
 }
 
 int default_waves(int K) {

@@ -21,7 +21,8 @@ struct Shape {
 };
 const std::vector<Shape> &supported_shapes();
 int default_waves(int K);              // 0 if K unsupported
-bool shape_supported(int K, int W);
+bool shape_supported(int K, int W);    // a base of this shape can be planned
+bool channel_kernel(int K, int W);     // the channel-engine kernels exist for it
 
 enum PrimeRange { RANGE_HIGH = 0, RANGE_FULL = 1 };
 

@@ -260,6 +260,31 @@ def test_modexp_8192_bit(engine):
         assert np.array_equal(_run_modexp(ctx, bases[:17], e), oracle.modexp_batch(bases[:17], e, nl))
 
 
+def test_modexp_16384_bit():
+    """16384-bit moduli on bases of 512 + 1 channels (k = 513, the matrix
+    engine alone): 20 bases (a full 16-element tile and a ragged one)
+    including 0, 1, N - 1 and 2^16384 - 1 with a 64-bit exponent, and with
+    per-element 40-bit exponents; the channel engine and the single-product
+    kernel refuse this base."""
+    from paper_1305_3699_amd import ENGINE_CHANNEL, ENGINE_MATRIX, RnsError
+    rng = random.Random(16384)
+    N = rng.getrandbits(16384) | (1 << 16383) | 1
+    ctx = _ctx(N, 512)
+    assert ctx.info["k"] == 513 and ctx.info["engine"] == ENGINE_MATRIX and ctx.info["group"] == 16
+    bases = gen.to_limbs([rng.getrandbits(16384) for _ in range(16)] + [0, 1, N - 1, (1 << 16384) - 1], 512)
+    nl = gen.to_limbs(N, 512)[0]
+    e = gen.to_limbs(rng.getrandbits(64) | (1 << 63), 2)[0]
+    assert np.array_equal(_run_modexp(ctx, bases, e), oracle.modexp_batch(bases, e, nl))
+    ex = gen.to_limbs([rng.getrandbits(40) for _ in range(19)] + [0], 2)
+    assert np.array_equal(_run_modexp(ctx, bases, ex), oracle.modexp_batch(bases, ex, nl))
+    with pytest.raises(RnsError) as err:
+        _ctx(N, 512, engine=ENGINE_CHANNEL)
+    assert err.value.status == -8
+    with pytest.raises(RnsError) as err:
+        ctx.mont_mul(_dev(np.zeros((2 * 513 + 1, 1), np.uint32)), _dev(np.zeros((2 * 513 + 1, 1), np.uint32)))
+    assert err.value.status == -8
+
+
 def test_mont_mul_8192_bit():
     """The standalone product at 8192 bits (k = 257, channel kernels)."""
     rng = random.Random(257)
@@ -282,13 +307,14 @@ def test_mont_mul_8192_bit():
 
 
 def test_rsa16384_crt_only_key():
-    """RSA-16384 CRT decryption: 8192-bit halves on bases of 257 channels.  No
-    base covers the 16384-bit modulus, so the key loads CRT-only: decryption
+    """RSA-16384 CRT decryption: 8192-bit halves on bases of 257 channels.
+    With the channel engine requested, which has no kernel for the
+    513-channel base of the full modulus, the key loads CRT-only: decryption
     through the halves works, encryption is refused.  20 ciphertexts (a full
     16-element tile and a ragged one) against the oracle's CRT path, two of
     them also by m^e = c.  The key is the stored seeded fixture."""
-    from paper_1305_3699_amd import RnsError
-    rk, parts = _rsa16384_key()
+    from paper_1305_3699_amd import ENGINE_CHANNEL, RnsError
+    rk, parts = _rsa16384_key(engine=ENGINE_CHANNEL)
     n, e, p, q, dp, dq, qinv = (parts[k] for k in ("n", "e", "p", "q", "dp", "dq", "qinv"))
     assert n.bit_length() == 16384
     assert rk.info(1)["k"] == 257 and rk.info(2)["k"] == 257
@@ -308,14 +334,34 @@ def test_rsa16384_crt_only_key():
     assert err.value.status == -8
 
 
-def _rsa16384_key():
+def _rsa16384_key(**opts):
     from paper_1305_3699_amd import RsaKey
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rsa16384_key.json")) as fh:
         fx = json.load(fh)
     p, q, e = int(fx["p"], 16), int(fx["q"], 16), int(fx["e"])
     d = pow(e, -1, (p - 1) * (q - 1))
     parts = dict(n=p * q, e=e, d=d, p=p, q=q, dp=d % (p - 1), dq=d % (q - 1), qinv=pow(q, -1, p))
-    return RsaKey(**parts), parts
+    return RsaKey(**parts, **opts), parts
+
+
+def test_rsa16384_full_modulus():
+    """RSA-16384 with the full modulus on bases of 512 + 1 channels (k = 513,
+    matrix engine only): 20 encryptions (a full tile and a ragged one) against
+    the oracle; non-CRT decryption with the full-length d of 3 of them gives
+    the messages back and agrees with the CRT path (257-channel halves)."""
+    from paper_1305_3699_amd import ENGINE_MATRIX
+    rk, parts = _rsa16384_key()
+    n, e = parts["n"], parts["e"]
+    assert rk.info(0)["k"] == 513 and rk.info(0)["engine"] == ENGINE_MATRIX
+    assert rk.info(1)["k"] == 257
+    msgs = gen.uniform_below(n, 18, seed=gen.config_seed(8, 22)) + [0, n - 1]
+    ml = gen.to_limbs(msgs, 512)
+    c = _host(rk.encrypt(_dev(ml)))
+    assert np.array_equal(c, oracle.modexp_batch(ml, gen.to_limbs(e, 1)[0], gen.to_limbs(n, 512)[0]))
+    sel = c[[0, 1, 19]]
+    full = _host(rk.decrypt(_dev(sel), use_crt=False))
+    assert np.array_equal(full, ml[[0, 1, 19]])
+    assert np.array_equal(full, _host(rk.decrypt(_dev(sel), use_crt=True)))
 
 
 def test_batched_with_rsa16384_crt_only_key():
@@ -323,8 +369,8 @@ def test_batched_with_rsa16384_crt_only_key():
     a CRT-only key) with RSA-2048 encryptions and decryptions: every output
     equals the oracle's; an encryption with the CRT-only key is refused at
     creation."""
-    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RnsError, RsaBatch, RsaKey
-    big, bp = _rsa16384_key()
+    from paper_1305_3699_amd import ENGINE_CHANNEL, OP_DECRYPT, OP_ENCRYPT, RnsError, RsaBatch, RsaKey
+    big, bp = _rsa16384_key(engine=ENGINE_CHANNEL)
     k2 = gen.rsa_key(2048, seed=gen.config_seed(3, 12))
     small = RsaKey(k2.n, k2.e, k2.d, k2.p, k2.q, k2.dp, k2.dq, k2.qinv)
     c_big = gen.to_limbs(gen.uniform_below(bp["n"], 18, seed=gen.config_seed(8, 18)), 512)
@@ -696,11 +742,12 @@ def test_keygen_and_primality_edges():
 
 
 def test_served_refuses_encryption_with_crt_only_key():
-    """A served trace that asks a CRT-only key (RSA-16384) to encrypt is
-    refused before any work (RNS_EUNSUPPORTED); its CRT decryptions are
-    served and match the oracle."""
-    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RnsError, RsaServer
-    big, bp = _rsa16384_key()
+    """A served trace that asks a CRT-only key (RSA-16384 loaded for the
+    channel engine) to encrypt is refused before any work
+    (RNS_EUNSUPPORTED); its CRT decryptions are served and match the
+    oracle."""
+    from paper_1305_3699_amd import ENGINE_CHANNEL, OP_DECRYPT, OP_ENCRYPT, RnsError, RsaServer
+    big, bp = _rsa16384_key(engine=ENGINE_CHANNEL)
     srv = RsaServer([big], max_inflight=2)
     msgs = gen.to_limbs(gen.uniform_below(bp["n"], 4, seed=gen.config_seed(8, 21)), 512)
     kidx = np.zeros(4, np.int32)

@@ -251,6 +251,52 @@ def test_emul_8192_bit_modulus(engine):
     assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]
 
 
+def test_emul_16384_bit_modulus():
+    """512 + 1 channels per base (k = 513): a 16384-bit modulus, the base
+    doubled once more instead of 64-bit channels; the matrix engine alone
+    serves it (its REDC offset grows to m 2^18).  The host model checks that
+    every one-step reduction input stays in [0, m 2^32) (else RNS_EVERIFY)."""
+    rng = random.Random(16384)
+    N = rng.getrandbits(16384) | (1 << 16383) | 1
+    p = Plan(N, 512, window=2)
+    assert p.info["k"] == 513 and p.info["engine"] == rnsrsa.ENGINE_MATRIX
+    bases = [rng.getrandbits(16384) for _ in range(3)] + [0, 1, N - 1]
+    e = 65537
+    out = p.emul_modexp(gen.to_limbs(bases, 512), gen.to_limbs(e, 1)[0])
+    assert oracle.rows_to_ints(out) == [pow(b, e, N) for b in bases]
+    with pytest.raises(RnsError) as err:
+        Plan(N, 512, engine=rnsrsa.ENGINE_CHANNEL)      # no channel-engine kernel for k = 513
+    assert err.value.status == -8
+
+
+def test_matrix_engine_sum_bound():
+    """The one-REDC steps (iii)/(iv) add m 2^s to the extension's signed sum
+    S, |S| <= 4k 0x80808080 128 + 0x80808080, and need m 2^s > |S|: at
+    k = 257 (s = 17) every prime must exceed about 2^31.011, so bases drawn
+    from the full 32-bit range (with primes just above 2^31) take the channel
+    engine; requesting the matrix engine for them is refused.  The default
+    high-range bases of k = 257 and 513 satisfy the bound."""
+    def smax(k):
+        return 4 * k * 0x80808080 * 128 + 0x80808080
+
+    rng = random.Random(6000)
+    N = rng.getrandbits(6000) | (1 << 5999) | 1
+    full = Plan(N, 188, prime_range=rnsrsa.PRIMES_FULL, prime_seed=0)
+    assert full.info["k"] == 257 and full.info["engine"] == rnsrsa.ENGINE_CHANNEL
+    assert min(full.primes) << 17 <= smax(257)
+    with pytest.raises(RnsError) as err:
+        Plan(N, 188, prime_range=rnsrsa.PRIMES_FULL, prime_seed=0, engine=rnsrsa.ENGINE_MATRIX)
+    assert err.value.status == -8
+    for bits, k, s in ((6000, 257, 17), (16384, 513, 18)):
+        M = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+        pl = Plan(M, (bits + 31) // 32)
+        assert pl.info["k"] == k and pl.info["engine"] == rnsrsa.ENGINE_MATRIX
+        pr = pl.primes
+        assert all(m << s > smax(k) for m in pr)
+        # B' (second half): x'y' + S + m 2^s < m 2^32 with x', y' <= m - 1
+        assert all((m - 1) ** 2 + (m << s) + smax(k) < m << 32 for m in pr[k:])
+
+
 def test_keygen_argument_errors():
     """Argument checks of the primality entry points that fail before any
     device work (a nonzero count with null buffers, an even candidate, a

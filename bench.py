@@ -599,8 +599,10 @@ def run_configs(args) -> list:
     trip (64 encryptions, 64 plain decryptions, one launch each), RSA-2048
     CRT decryption of 16384 ciphertexts per fixed window width w = 1..6,
     exponents of 4096 / 8192 / 16128 bits on 1024 bases modulo a 2048-bit n,
-    and RSA-3072 / RSA-4096 CRT decryption of 4096 ciphertexts.  HIP-event
-    means over `--config-reps` launches after one untimed."""
+    RSA-3072 / RSA-4096 CRT decryption of 4096 ciphertexts, and RSA-16384
+    (encryption on the full modulus, CRT decryption, plain decryption with the
+    full-length d).  HIP-event means over `--config-reps` launches after one
+    untimed (one launch for the plain RSA-16384 decryption)."""
     import numpy as np
     import torch
 
@@ -670,6 +672,28 @@ def run_configs(args) -> list:
         row["ms"][str(bits)] = round(ms, 3)
         rk.close()
     lines.append(row)
+    # RSA-16384: the full modulus on 512 + 1 channels, the halves on 256 + 1
+    with open(os.path.join(ROOT, "tests", "golden", "rsa16384_key.json")) as fh:
+        fx = json.load(fh)
+    p, q, e = int(fx["p"], 16), int(fx["q"], 16), int(fx["e"])
+    n, d = p * q, pow(e, -1, (p - 1) * (q - 1))
+    rk = RsaKey(n, e, d, p, q, d % (p - 1), d % (q - 1), pow(q, -1, p))
+    msgs = dev(gen.to_limbs(gen.uniform_below(n, 4096, seed=gen.config_seed(8, 30)), 512))
+    c = rk.encrypt(msgs)
+    out = torch.empty_like(c)
+    enc_ms = timed(lambda: rk.encrypt(msgs, out=out), reps)
+    crt_ms = timed(lambda: rk.decrypt(c, use_crt=True, out=out), reps)
+    nd = 1024
+    full_ms = timed(lambda: rk.decrypt(c[:nd], use_crt=False, out=out[:nd]), 1)
+    ok = bool(torch.equal(out[:nd], msgs[:nd]))
+    lines.append({"config": "RSA-16384 (stored seeded key): encryption with e = 65537 of 4096 messages on the "
+                            "full modulus (k = %d), CRT decryption of the 4096 (k = %d halves), non-CRT "
+                            "decryption with the full-length d of %d" % (rk.info(0)["k"], rk.info(1)["k"], nd),
+                  "encrypts_per_s": round(4096 / enc_ms * 1e3, 1), "crt_decrypts_per_s": round(4096 / crt_ms * 1e3, 1),
+                  "plain_decrypts_per_s": round(nd / full_ms * 1e3, 1),
+                  "ms": {"encrypt": round(enc_ms, 3), "crt": round(crt_ms, 3), "plain": round(full_ms, 3)},
+                  "plain_round_trip_ok": ok})
+    rk.close()
     return lines
 
 

@@ -49,7 +49,8 @@ enum rns_status {
     RNS_EFACTOR = -3,       /* a channel prime of an explicit base divides N */
     RNS_ENOMEM = -4,        /* host or device allocation failed */
     RNS_EDEVICE = -5,       /* HIP runtime error */
-    RNS_EVERIFY = -6,       /* reserved: a result failed its self-check */
+    RNS_EVERIFY = -6,       /* a result failed its self-check (key generation's d e = 1 mod f;
+                               the host model's one-step reduction range check) */
     RNS_EBUSY = -7,         /* reserved: admission budget exhausted */
     RNS_EUNSUPPORTED = -8   /* no kernel is built for the requested shape */
 };
@@ -71,7 +72,9 @@ enum rns_prime_range {
  * Options for context / key creation.  Pass NULL for defaults; a zeroed struct
  * means defaults too.
  *   k           channels per RNS base (0 = the smallest built base size that
- *               meets the bounds below).
+ *               meets the bounds below).  Built sizes: 2, 3, 5, 9, 17, 33, 49,
+ *               65, 66, 97, 129, 257 (moduli up to 8192 bits) and 513 (up to
+ *               16384 bits; matrix-core engine only).
  *   window      exponent window width w in 1..6 (0 = 5).  The exponent loop
  *               precomputes 2^w table entries and does w squarings plus one
  *               multiplication per w-bit digit.
@@ -80,10 +83,18 @@ enum rns_prime_range {
  *   prime_range rns_prime_range; prime_seed seeds the deterministic draw.
  *   primes      optional explicit bases: n_primes = 2k distinct primes in
  *               (2^31, 2^32), B first then B'.  Overrides k and prime_range.
- *               The matrix-core engine needs every B' prime <= 2^32 - 2^18
- *               (else: channel engine, or RNS_EUNSUPPORTED if requested).
+ *               The matrix-core engine reduces each base-extension output
+ *               in one step, which needs every B' prime <= 2^32 - 2^18 and
+ *               every prime m with m 2^s > 4k*0x80808080*128 + 0x80808080
+ *               (s = 17 up to k = 257, 18 beyond; B' also below the REDC
+ *               limit, checked exactly per prime); a base that fails takes
+ *               the channel engine (or RNS_EUNSUPPORTED if the matrix engine
+ *               was requested or k = 513, which has no channel kernel).
+ *               Full-range draws at k = 257 usually fail it.
  *   engine      rns_engine (0 = auto).  rns_mont_mul_batch and the Garner
- *               step of CRT decryption always use the channel kernels.
+ *               step of CRT decryption always use the channel kernels;
+ *               k = 513 runs on the matrix engine only (the channel engine
+ *               returns RNS_EUNSUPPORTED there).
  *   group       matrix-core engine: preferred elements per workgroup, 16 or
  *               32, used by every launch (a k without a kernel of that size
  *               uses its default).  0: the default for k, except that a
@@ -171,6 +182,7 @@ int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, si
  *              0..k-1 are B, k..2k-1 are B', 2k is the redundant 2^32 channel.
  *              Each input must be the residue vector of one integer below
  *              (k+1)N; out may alias x or y.
+ * Runs the channel kernels: RNS_EUNSUPPORTED for k = 513.
  */
 int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint32_t *out,
                        size_t batch, void *hip_stream);
@@ -184,11 +196,14 @@ int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint3
  *   opts       host or NULL; applied to every context of the key, except that
  *              an explicit k too small for n (one sized for the CRT halves)
  *              leaves the full-modulus context sized automatically
- * A key with CRT parts whose modulus no base covers (above 8192 bits; the
- * halves of keys up to 16384 bits fit the 257-channel bases) loads as a
- * CRT-only key: CRT decryption works; encryption, decryption with use_crt = 0
- * and rsa_key_info(key, 0) return RNS_EUNSUPPORTED, as do batched operations
- * and served requests that need the full modulus.
+ * A key with CRT parts whose full modulus no base covers, or that no kernel
+ * of the requested engine runs (the channel engine on a 16384-bit modulus,
+ * k = 513), loads as a CRT-only key: CRT decryption works; encryption,
+ * decryption with use_crt = 0 and rsa_key_info(key, 0) return
+ * RNS_EUNSUPPORTED, as do batched operations and served requests that need
+ * the full modulus.  With default options keys up to 16384 bits get a
+ * full-modulus context (k = 513 above 8192 bits) and CRT halves on bases of
+ * up to 257 channels.
  * The private parts stay in library-owned memory (the paper keeps private keys
  * on the GPU, Sec. 4.3).  Release with rsa_key_free.
  */
@@ -413,7 +428,9 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
  *   n_out             host, 2 * half_limbs limbs
  * Synchronises hip_stream.  Errors: RNS_EINVAL (bad argument, a base out of
  * range), RNS_ERANGE (a stream holds no probable prime), RNS_EUNSUPPORTED
- * (e equal to a channel prime), RNS_EVERIFY, as rsa_key_load.
+ * (e equal to a channel prime; keys above 8192 bits, half_limbs > 128, whose
+ * (p-1)(q-1) needs a base without a channel kernel for Arazi's step),
+ * RNS_EVERIFY, as rsa_key_load.
  */
 int rsa_keygen(const uint32_t *cand_p, const uint32_t *bases_p, const uint32_t *cand_q, const uint32_t *bases_q,
                size_t count, int half_limbs, int rounds, uint32_t e, const rns_opts *opts, uint32_t *n_out,

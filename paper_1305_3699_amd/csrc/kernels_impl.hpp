@@ -207,31 +207,55 @@ __device__ __forceinline__ void rns_entry(const uint32_t *__restrict__ bc, const
     a.r = (uint32_t)zr;
 }
 
-// RNS -> binary for the value whose xi' (LDS) and alpha the last product left:
-//   A = sum_j xi'_j M'_j - alpha M'   (CRT with the redundant modulus, Sec. 3.1)
-// then the canonical representative A mod N (A < (K+1) N).  Result: L limbs
-// in acc[l*64 + lane] (acc has room for L+1 rows).  Wave-local (no barrier).
+// Limbs [l0, l1) of sum_j xi'_j M'_j into acc[l*64 + lane], carries
+// propagated inside the range; returns the carry out of limb l1 - 1.
 template <int K, int W>
-__device__ __forceinline__ void rns_exit(const uint32_t *__restrict__ bc, const uint32_t *__restrict__ mc,
-                                         uint32_t *acc, uint32_t *tmp, const uint32_t *xip, uint32_t alpha,
-                                         int L, int lane) {
+__device__ __forceinline__ uint64_t exit_columns(const uint32_t *__restrict__ bc, const uint32_t *xip, uint32_t *acc,
+                                                 int l0, int l1, int lane) {
     using S = Shp<K, W>;
     constexpr Layout LY{K, S::KP};
-    {
-        uint64_t carry = 0;
-        for (int l = 0; l <= L; l++) {
-            const uint32_t *__restrict__ col = bc + LY.MpL() + l;
-            Acc s;
-            s.lo = carry;
+    uint64_t carry = 0;
+    for (int l = l0; l < l1; l++) {
+        const uint32_t *__restrict__ col = bc + LY.MpL() + l;
+        Acc s;
+        s.lo = carry;
 #pragma unroll 8
-            for (int j = 0; j < K; j++) acc_mac(s, xip[j * 64 + lane], col[j * (K + 1)]);
-            uint64_t lo;
-            uint32_t top;
-            acc_value(s, lo, top);
-            acc[l * 64 + lane] = (uint32_t)lo;
-            carry = (lo >> 32) | ((uint64_t)top << 32);
+        for (int j = 0; j < K; j++) acc_mac(s, xip[j * 64 + lane], col[j * (K + 1)]);
+        uint64_t lo;
+        uint32_t top;
+        acc_value(s, lo, top);
+        acc[l * 64 + lane] = (uint32_t)lo;
+        carry = (lo >> 32) | ((uint64_t)top << 32);
+    }
+    return carry;
+}
+
+// The limbs of a sum computed as n consecutive ranges of C limbs each, range r
+// starting at limb r*C, whose carries out are cout[r*128 + lane] (low word)
+// and cout[r*128 + 64 + lane] (high word): adds each range's carry into the
+// limbs that follow it, in order (v[l*vs] is limb l; nl limbs in all).
+template <typename P>
+__device__ __forceinline__ void ripple_carries(P v, size_t vs, int nl, const uint32_t *cout, int n, int C, int lane) {
+    uint64_t c = 0;
+    for (int r = 1; r < n; r++) {
+        c += (uint64_t)cout[(r - 1) * 128 + lane] | ((uint64_t)cout[(r - 1) * 128 + 64 + lane] << 32);
+        const int end = (r + 1) * C < nl ? (r + 1) * C : nl;
+        for (int l = r * C; c != 0 && l < end; l++) {
+            const uint64_t t = (uint64_t)v[l * vs] + (uint32_t)c;
+            v[l * vs] = (uint32_t)t;
+            c = (c >> 32) + (t >> 32);
         }
     }
+}
+
+// Given acc = sum_j xi'_j M'_j (L+1 limbs): subtracts alpha M', then takes the
+// canonical representative mod N (the value is below (K+1) N) by conditional
+// subtractions of N 2^b, b = qbits-1 .. 0.  tmp: L+1 rows of scratch.
+template <int K, int W>
+__device__ __forceinline__ void exit_reduce(const uint32_t *__restrict__ bc, const uint32_t *__restrict__ mc,
+                                            uint32_t *acc, uint32_t *tmp, uint32_t alpha, int L, int lane) {
+    using S = Shp<K, W>;
+    constexpr Layout LY{K, S::KP};
     {
         uint64_t carry = 0;
         uint32_t borrow = 0;
@@ -258,6 +282,18 @@ __device__ __forceinline__ void rns_exit(const uint32_t *__restrict__ bc, const 
         if (!borrow)
             for (int l = 0; l <= L; l++) acc[l * 64 + lane] = tmp[l * 64 + lane];
     }
+}
+
+// RNS -> binary for the value whose xi' (LDS) and alpha the last product left:
+//   A = sum_j xi'_j M'_j - alpha M'   (CRT with the redundant modulus, Sec. 3.1)
+// then the canonical representative A mod N (A < (K+1) N).  Result: L limbs
+// in acc[l*64 + lane] (acc has room for L+1 rows).  Wave-local (no barrier).
+template <int K, int W>
+__device__ __forceinline__ void rns_exit(const uint32_t *__restrict__ bc, const uint32_t *__restrict__ mc,
+                                         uint32_t *acc, uint32_t *tmp, const uint32_t *xip, uint32_t alpha,
+                                         int L, int lane) {
+    exit_columns<K, W>(bc, xip, acc, 0, L + 1, lane);
+    exit_reduce<K, W>(bc, mc, acc, tmp, alpha, L, lane);
 }
 
 template <int KS>
@@ -419,7 +455,7 @@ __global__ __launch_bounds__(64 * W) void garner_kernel(
     int out_limbs, int out_stride, int batch) {
     using S = Shp<K, W>;
     constexpr int KS = S::KS, KP = S::KP;
-    __shared__ uint32_t lds[2 * KP * 64];
+    __shared__ uint32_t lds[2 * KP * 64 + 2 * W * 64];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int c0 = wave * KS;
@@ -427,17 +463,39 @@ __global__ __launch_bounds__(64 * W) void garner_kernel(
     const bool active = msg < batch;
     const size_t msafe = active ? (size_t)msg : 0;
     const uint32_t *src = in + msafe * (size_t)(2 * L);
+    uint32_t *cout = lds + 2 * KP * 64;   // [W][2][64] carries out of each wave's limb range
 
     Res<KS> a, y;
     rns_entry<K, W>(bc, E, src, 2 * L, active, a, c0);
     res_set_one<KS>(y);
     const uint32_t alpha = rns_mm<K, W>(bc, mc, a, y, lds, c0, lane, false);
     __syncthreads();
-    if (wave != 0) return;
+    // leaving the RNS: the L+1 limbs of sum_j xi'_j M'_j in W ranges, one per
+    // wave (the range sums are independent), then the carries between ranges,
+    // alpha M' and the reduction mod p on wave 0
     uint32_t *h = lds;
-    rns_exit<K, W>(bc, mc, h, h + (L + 1) * 64, lds + KP * 64, alpha, L, lane);
+    {
+        const int C = (L + 1 + W - 1) / W;
+        const int l0 = wave * C < L + 1 ? wave * C : L + 1;
+        const int l1 = l0 + C < L + 1 ? l0 + C : L + 1;
+        const uint64_t c = exit_columns<K, W>(bc, lds + KP * 64, h, l0, l1, lane);
+        cout[wave * 128 + lane] = (uint32_t)c;
+        cout[wave * 128 + 64 + lane] = (uint32_t)(c >> 32);
+        __syncthreads();
+        if (wave == 0) {
+            ripple_carries(h + lane, 64, L + 1, cout, W, C, lane);
+            exit_reduce<K, W>(bc, mc, h, h + (L + 1) * 64, alpha, L, lane);
+        }
+        __syncthreads();
+    }
+    // m = m_q + h q: each wave its range of output limbs, then wave 0 adds the
+    // carries between ranges (in the output buffer)
+    const int C = (out_limbs + W - 1) / W;
+    const int o0 = wave * C < out_limbs ? wave * C : out_limbs;
+    const int o1 = o0 + C < out_limbs ? o0 + C : out_limbs;
+    uint32_t *dst = out + msafe * (size_t)out_stride;
     uint64_t carry = 0;
-    for (int l = 0; l < out_limbs; l++) {
+    for (int l = o0; l < o1; l++) {
         const int i0 = l - L + 1 > 0 ? l - L + 1 : 0;
         const int i1 = l < L - 1 ? l : L - 1;
         Acc s;
@@ -446,9 +504,13 @@ __global__ __launch_bounds__(64 * W) void garner_kernel(
         uint64_t lo;
         uint32_t top;
         acc_value(s, lo, top);
-        if (active) out[(size_t)msg * out_stride + l] = (uint32_t)lo;
+        if (active) dst[l] = (uint32_t)lo;
         carry = (lo >> 32) | ((uint64_t)top << 32);
     }
+    cout[wave * 128 + lane] = (uint32_t)carry;
+    cout[wave * 128 + 64 + lane] = (uint32_t)(carry >> 32);
+    __syncthreads();
+    if (wave == 0 && active) ripple_carries(dst, 1, out_limbs, cout, W, C, lane);
 }
 
 // One RNS Montgomery product per element on channel-major residues.

@@ -741,6 +741,38 @@ def test_keygen_and_primality_edges():
     assert int(miller_rabin(gen.to_limbs([p], 4), np.stack([gen.to_limbs(bases, 4)]))[0]) == 1
 
 
+def test_batched_and_served_with_rsa16384_full_modulus():
+    """A batch and a served trace mixing RSA-16384 encryptions (full modulus,
+    513-channel group) and CRT decryptions (257-channel halves) with RSA-2048
+    work: every output equals the oracle's."""
+    from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RsaBatch, RsaKey, RsaServer
+    big, bp = _rsa16384_key()
+    k2 = gen.rsa_key(2048, seed=gen.config_seed(3, 12))
+    small = RsaKey(k2.n, k2.e, k2.d, k2.p, k2.q, k2.dp, k2.dq, k2.qinv)
+    n, e = bp["n"], bp["e"]
+    m_big = gen.to_limbs(gen.uniform_below(n, 21, seed=gen.config_seed(8, 23)), 512)
+    c_big = gen.to_limbs(gen.uniform_below(n, 5, seed=gen.config_seed(8, 24)), 512)
+    x2 = gen.to_limbs(gen.uniform_below(k2.n, 33, seed=gen.config_seed(8, 25)), 64)
+    ins = [_dev(m_big), _dev(c_big), _dev(x2)]
+    outs = [torch.zeros_like(t) for t in ins]
+    b = RsaBatch([(big, OP_ENCRYPT, ins[0], outs[0]), (big, OP_DECRYPT, ins[1], outs[1]),
+                  (small, OP_DECRYPT, ins[2], outs[2])])
+    b.run()
+    torch.cuda.synchronize()
+    nl = gen.to_limbs(n, 512)[0]
+    assert np.array_equal(_host(outs[0]), oracle.modexp_batch(m_big, gen.to_limbs(e, 1)[0], nl))
+    assert np.array_equal(_host(outs[1]), oracle.rsa_crt_batch(c_big, bp["p"], bp["q"], bp["dp"], bp["dq"], bp["qinv"]))
+    assert np.array_equal(_host(outs[2]), oracle.rsa_crt_batch(x2, k2.p, k2.q, k2.dp, k2.dq, k2.qinv))
+    b.close()
+    srv = RsaServer([big], max_inflight=2)
+    msgs = np.concatenate([m_big[:3], c_big[:3]])
+    ops = np.array([OP_ENCRYPT] * 3 + [OP_DECRYPT] * 3, np.int32)
+    got, lat, stats = srv.replay(np.zeros(6, np.int32), ops, np.linspace(0.0, 0.001, 6), msgs)
+    assert np.array_equal(got[:3], oracle.modexp_batch(m_big[:3], gen.to_limbs(e, 1)[0], nl))
+    assert np.array_equal(got[3:], oracle.rsa_crt_batch(c_big[:3], bp["p"], bp["q"], bp["dp"], bp["dq"], bp["qinv"]))
+    srv.close()
+
+
 def test_served_refuses_encryption_with_crt_only_key():
     """A served trace that asks a CRT-only key (RSA-16384 loaded for the
     channel engine) to encrypt is refused before any work

@@ -173,6 +173,38 @@ int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, si
                      size_t exp_stride, uint32_t *out, size_t batch, void *hip_stream);
 
 /*
+ * rns_modexp_jobs -- several exponentiation batches, each on its own context
+ * (modulus), in as few launches as possible: the paper runs a batch of
+ * independent exponentiations side by side (Sec. 3.3), and Miller-Rabin
+ * takes one modulus per candidate (Sec. 3.2).  Jobs on matrix-core contexts
+ * of one kernel shape (and requested tile) share one grouped launch whatever
+ * their moduli; jobs on channel-engine contexts take one launch each.
+ *   jobs[i].ctx        context of job i (modulus, window, engine, tile)
+ *   jobs[i].base, exp, exp_limbs, exp_stride, out, count
+ *                      as the arguments of rns_modexp_batch on that context
+ *                      (device buffers; L = the context's mod_limbs); a job
+ *                      of count 0 is skipped
+ * A job's out may alias its own base; it must not overlap another job's
+ * base or out (the jobs of a launch run concurrently).  Every context must
+ * belong to the current device.  Every job is validated before anything is
+ * enqueued (RNS_EINVAL names the job); RNS_ENOMEM or RNS_EDEVICE after that
+ * may leave earlier launches enqueued.  Asynchronous on hip_stream; the
+ * library's host copy of a launch's job table is released by the stream
+ * once copied.  Scratch as rns_modexp_batch, per launch.
+ */
+typedef struct rns_job {
+    const rns_ctx *ctx;
+    const uint32_t *base;
+    const uint32_t *exp;
+    size_t exp_limbs;
+    size_t exp_stride;
+    uint32_t *out;
+    size_t count;
+} rns_job;
+
+int rns_modexp_jobs(const rns_job *jobs, size_t njobs, void *hip_stream);
+
+/*
  * rns_mont_mul_batch -- one RNS Montgomery product per element in the residue
  * domain (Sec. 3.1, the operation the paper times in its Fig. 1):
  *   r = (X*Y + q^*N) / M,   q^ = sum_i |x_i y_i (-N^-1) M_i^-1|_{m_i} M_i,

@@ -5,4 +5,4 @@ all the arithmetic; ``rnsrsa`` is its ctypes binding.
 """
 from .rnsrsa import (ENGINE_AUTO, ENGINE_CHANNEL, ENGINE_MATRIX, OP_DECRYPT, OP_ENCRYPT, PRIMES_FULL,  # noqa: F401
                      PRIMES_HIGH, Plan, RnsContext, RnsError, RsaBatch, RsaKey, RsaServer, int_to_limbs, lib,
-                     keygen, miller_rabin, nlimbs, trial_division)
+                     keygen, miller_rabin, modexp_jobs, nlimbs, trial_division)

@@ -11,6 +11,7 @@
 
 #include "capi_internal.hpp"
 #include "emul.hpp"
+#include "jobs.hpp"
 #include "rnsrsa_host.h"
 
 using namespace rnsrsa;
@@ -435,6 +436,104 @@ int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, si
     int rc = run_modexp(ctx, nullptr, entry_of(ctx), nullptr, base, ctx->plan.L, exp, nullptr, (int)exp_limbs, (int)exp_stride,
                         out, nullptr, ctx->plan.L, batch, (hipStream_t)hip_stream);
     return rc ? rc : ok();
+}
+
+int rns_modexp_jobs(const rns_job *jobs, size_t njobs, void *hip_stream) {
+    using namespace rnsrsa::api;
+    if (njobs == 0) return ok();
+    if (!jobs) return fail(RNS_EINVAL, "null job array");
+    if (njobs > (1u << 20)) return fail(RNS_EINVAL, "more than 2^20 jobs");
+    for (size_t i = 0; i < njobs; i++) {
+        const rns_job &j = jobs[i];
+        const std::string at = "job " + std::to_string(i) + ": ";
+        if (!j.ctx) return fail(RNS_EINVAL, at + "null context");
+        if (j.count == 0) continue;
+        if (!j.base || !j.exp || !j.out || j.exp_limbs == 0)
+            return fail(RNS_EINVAL, at + "null buffer or zero exponent limbs");
+        if (j.exp_stride != 0 && j.exp_stride < j.exp_limbs) return fail(RNS_EINVAL, at + "exp_stride below exp_limbs");
+        if (j.count > (size_t)INT32_MAX - 64 || j.exp_limbs > 1u << 20 || j.exp_stride > 1u << 24)
+            return fail(RNS_EINVAL, at + "count or exponent too large");
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (size_t i = 0; i < njobs; i++)
+        if (jobs[i].count && jobs[i].ctx->device != dev)
+            return fail(RNS_EINVAL, "job " + std::to_string(i) + ": context belongs to another device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    try {
+        // matrix-core jobs of one kernel shape (and requested tile) share a launch
+        std::map<std::tuple<int, int, int, int>, JobGroup> groups;
+        for (size_t i = 0; i < njobs; i++) {
+            const rns_job &j = jobs[i];
+            const rns_ctx *c = j.ctx;
+            if (j.count == 0) continue;
+            const int L = c->plan.L;
+            if (c->engine != RNS_ENGINE_MATRIX) {
+                int rc = run_modexp(c, nullptr, entry_of(c), nullptr, j.base, L, j.exp, nullptr, (int)j.exp_limbs,
+                                    (int)j.exp_stride, j.out, nullptr, L, j.count, s);
+                if (rc) return rc;
+                continue;
+            }
+            const MfmaShape &sh = c->mshape;
+            JobGroup &g = groups[std::make_tuple(sh.K, sh.W, sh.MT, c->group_req)];
+            if (g.jobs.empty()) {
+                g.shape = sh;
+                g.device = dev;
+                g.auto_tile = c->group_req == 0;
+            }
+            PlannedJob J{};
+            J.j.mb = c->d_mbase;
+            J.j.mk = c->d_mkey;
+            J.j.E = entry_of(c);
+            J.j.exp = j.exp;
+            J.j.in = j.base;
+            J.j.out = j.out;
+            J.j.batch = (int)j.count;
+            J.j.in_limbs = L;
+            J.j.in_stride = L;
+            J.j.L = L;
+            J.j.out_stride = L;
+            J.j.exp_limbs = (int)j.exp_limbs;
+            J.j.exp_stride = (int)j.exp_stride;
+            J.j.window = c->window;
+            J.cost = 32 * j.exp_limbs;   // the exponents stay on the device: their length orders the tiles
+            g.jobs.push_back(J);
+        }
+        for (auto &kv : groups) {
+            JobGroup &g = kv.second;
+            finish_group(g);
+            if (g.auto_tile) {
+                const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, dev);
+                if (t.NT != g.shape.NT) {
+                    g.shape = t;
+                    finish_group(g);
+                }
+            }
+            // the job table's host copy is released by the stream once copied
+            std::unique_ptr<std::vector<MJob>> host(new std::vector<MJob>());
+            for (const PlannedJob &J : g.jobs) host->push_back(J.j);
+            const size_t bytes = host->size() * sizeof(MJob);
+            Scratch jt, tb;
+            int rc = scratch_alloc(jt, bytes, s);
+            if (!rc) rc = scratch_alloc(tb, g.table_words() * sizeof(uint32_t), s);
+            if (rc) return rc;
+            if ((e = hipMemcpyAsync(jt.p, host->data(), bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync");
+            std::vector<MJob> *h = host.get();
+            if (hipLaunchHostFunc(s, [](void *p) { delete (std::vector<MJob> *)p; }, h) == hipSuccess) {
+                host.release();
+            } else if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+                host.release();   // the copy may still read it: leaked rather than freed early
+                return hip_fail(e, "hipStreamSynchronize");
+            }
+            if ((e = launch_group(g, (const MJob *)jt.p, (uint32_t *)tb.p, s)) != hipSuccess)
+                return hip_fail(e, "grouped modexp launch");
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
+    }
+    return ok();
 }
 
 int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch,

@@ -91,6 +91,7 @@ _SIGNATURES = {
     "rns_get_info": ([_P, _P], _I),
     "rns_get_primes": ([_P, _P, _S], _I),
     "rns_modexp_batch": ([_P, _P, _P, _S, _S, _P, _S, _P], _I),
+    "rns_modexp_jobs": ([_P, _S, _P], _I),
     "rns_mont_mul_batch": ([_P, _P, _P, _P, _S, _P], _I),
     "rsa_key_load": ([_P, _S, _P, _S, _P, _P, _P, _P, _P, _P, _S, _P, _P], _I),
     "rsa_key_free": ([_P], None),
@@ -255,14 +256,7 @@ class RnsContext:
         B = base.shape[0] if base.dim() == 2 else 0
         if base.dim() != 2 or base.shape[1] != self.L:
             raise ValueError("base must be [B, %d]" % self.L)
-        if exp.dim() == 1:
-            E, stride = exp.shape[0], 0
-            xp = _dev_ptr(exp, 1, E, "exp")
-        elif exp.dim() == 2 and exp.shape[0] == B:
-            E, stride = exp.shape[1], exp.shape[1]
-            xp = _dev_ptr(exp, B, E, "exp")
-        else:
-            raise ValueError("exp must be [E] or [B, E]")
+        xp, E, stride = _exp_args(exp, B)
         if out is None:
             out = torch.empty_like(base)
         _check(lib().rns_modexp_batch(self._h, _dev_ptr(base, B, self.L, "base"), xp, E, stride,
@@ -281,6 +275,43 @@ class RnsContext:
         _check(lib().rns_mont_mul_batch(self._h, _dev_ptr(x, 2 * k + 1, B, "x"), _dev_ptr(y, 2 * k + 1, B, "y"),
                                         _dev_ptr(out, 2 * k + 1, B, "out"), B, _stream_handle(stream)))
         return out
+
+
+def _exp_args(exp, B):
+    """(device pointer, limbs, stride) of a shared [E] or per-element [B, E] exponent tensor."""
+    if exp.dim() == 1:
+        return _dev_ptr(exp, 1, exp.shape[0], "exp"), exp.shape[0], 0
+    if exp.dim() == 2 and exp.shape[0] == B:
+        return _dev_ptr(exp, B, exp.shape[1], "exp"), exp.shape[1], exp.shape[1]
+    raise ValueError("exp must be [E] or [B, E]")
+
+
+class RnsJob(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("base", ctypes.c_void_p), ("exp", ctypes.c_void_p),
+                ("exp_limbs", ctypes.c_size_t), ("exp_stride", ctypes.c_size_t), ("out", ctypes.c_void_p),
+                ("count", ctypes.c_size_t)]
+
+
+def modexp_jobs(jobs, stream=None):
+    """rns_modexp_jobs: jobs is a sequence of (ctx, base, exp) or (ctx, base,
+    exp, out) with the tensors of RnsContext.modexp on each job's context;
+    jobs of one matrix-core kernel shape share a launch.  Returns the outputs."""
+    import torch
+    arr = (RnsJob * len(jobs))()
+    outs = []
+    for i, job in enumerate(jobs):
+        ctx, base, exp = job[:3]
+        out = job[3] if len(job) > 3 and job[3] is not None else None
+        if base.dim() != 2 or base.shape[1] != ctx.L:
+            raise ValueError("job %d: base must be [B, %d]" % (i, ctx.L))
+        B = base.shape[0]
+        xp, E, stride = _exp_args(exp, B)
+        if out is None:
+            out = torch.empty_like(base)
+        arr[i] = RnsJob(ctx._h, _dev_ptr(base, B, ctx.L, "base"), xp, E, stride, _dev_ptr(out, B, ctx.L, "out"), B)
+        outs.append(out)
+    _check(lib().rns_modexp_jobs(arr, len(jobs), _stream_handle(stream)))
+    return outs
 
 
 class RsaKey:

@@ -285,6 +285,40 @@ def test_modexp_16384_bit():
     assert err.value.status == -8
 
 
+def test_modexp_jobs_mixed_moduli():
+    """rns_modexp_jobs: three 1024-bit moduli (one grouped launch), a 2048-bit
+    one with per-element exponents, a channel-engine context, a job of
+    count 0 and a job whose out aliases its base, in one call; every output
+    equals the oracle's and the job's own rns_modexp_batch."""
+    from paper_1305_3699_amd import ENGINE_CHANNEL, modexp_jobs
+    rng = random.Random(77)
+    specs = [(1024, {}), (1024, {}), (1024, {"window": 3}), (2048, {}), (1536, {"engine": ENGINE_CHANNEL})]
+    jobs, want = [], []
+    for i, (bits, opts) in enumerate(specs):
+        N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+        L = bits // 32
+        ctx = _ctx(N, L, **opts)
+        B = [17, 40, 3, 33, 20][i]
+        bases = gen.to_limbs([rng.getrandbits(bits) for _ in range(B - 2)] + [0, N - 1], L)
+        if i == 3:
+            e = gen.to_limbs([rng.getrandbits(200) for _ in range(B)], 7)
+        else:
+            e = gen.to_limbs(rng.getrandbits(bits) | 1, L)[0]
+        jobs.append((ctx, _dev(bases), _dev(e)))
+        want.append(oracle.modexp_batch(bases, e, gen.to_limbs(N, L)[0]))
+    alias = jobs[1][1].clone()
+    jobs.append((jobs[1][0], alias, jobs[1][2], alias))
+    want.append(want[1])
+    empty = torch.zeros((0, 32), dtype=torch.int32, device="cuda")
+    jobs.append((jobs[0][0], empty, jobs[0][2]))
+    outs = modexp_jobs(jobs)
+    torch.cuda.synchronize()
+    for i, w in enumerate(want):
+        assert np.array_equal(_host(outs[i]), w), i
+        assert np.array_equal(_host(jobs[i][0].modexp(jobs[i][1] if i != 5 else jobs[1][1], jobs[i][2])), w), i
+    assert outs[6].shape == (0, 32)
+
+
 def test_mont_mul_8192_bit():
     """The standalone product at 8192 bits (k = 257, channel kernels)."""
     rng = random.Random(257)

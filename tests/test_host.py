@@ -297,6 +297,19 @@ def test_matrix_engine_sum_bound():
         assert all((m - 1) ** 2 + (m << s) + smax(k) < m << 32 for m in pr[k:])
 
 
+def test_modexp_jobs_argument_errors():
+    """rns_modexp_jobs validates every job before touching the device: no
+    jobs is a no-op, a null job array or a job without a context is
+    RNS_EINVAL and names the job."""
+    lib = rnsrsa.lib()
+    assert lib.rns_modexp_jobs(None, 0, None) == 0
+    assert lib.rns_modexp_jobs(None, 1, None) == -1
+    arr = (rnsrsa.RnsJob * 2)()
+    arr[1] = rnsrsa.RnsJob(None, None, None, 1, 0, None, 4)
+    assert lib.rns_modexp_jobs(arr, 2, None) == -1
+    assert b"job 0" in lib.rns_last_error()
+
+
 def test_keygen_argument_errors():
     """Argument checks of the primality entry points that fail before any
     device work (a nonzero count with null buffers, an even candidate, a

@@ -277,6 +277,23 @@ int rsa_crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t 
 int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, void *hip_stream);
 
 /*
+ * rsa_crt_verify -- check of CRT decryption results against fault attacks
+ * (a fault in one half of a CRT decryption gives an m whose gcd with n
+ * reveals a factor; the paper keeps the private key on the GPU, Sec. 4.3):
+ * m[i]^e mod n is recomputed on the full-modulus context and compared with
+ * c[i]; every m[i] that fails is overwritten with zeros.
+ *   c      device, batch x n_limbs: the ciphertexts (< n), not aliasing m
+ *   m      device, batch x n_limbs: the results of rsa_decrypt (CRT)
+ *   n_bad  host or NULL: number of failing elements
+ * Synchronises hip_stream.  RNS_OK if every element passes, RNS_EVERIFY if
+ * any fails (outputs zeroed, count in n_bad); RNS_EINVAL (null buffers,
+ * c == m), RNS_EUNSUPPORTED for a CRT-only key.  Cost: one exponentiation by
+ * e per element on the full modulus (17 products for e = 65537).
+ */
+int rsa_crt_verify(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch, size_t *n_bad,
+                   void *hip_stream);
+
+/*
  * Batched form: many RSA operations over keys of different sizes in a fixed
  * set of launches (Sec. 3.3 operations, batched as in Sec. 4.3's throughput
  * use of many messages).  rsa_batch_create plans a list of operations once;

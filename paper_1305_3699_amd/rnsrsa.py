@@ -92,6 +92,7 @@ _SIGNATURES = {
     "rns_get_primes": ([_P, _P, _S], _I),
     "rns_modexp_batch": ([_P, _P, _P, _S, _S, _P, _S, _P], _I),
     "rns_modexp_jobs": ([_P, _S, _P], _I),
+    "rsa_crt_verify": ([_P, _P, _P, _S, _P, _P], _I),
     "rns_mont_mul_batch": ([_P, _P, _P, _P, _S, _P], _I),
     "rsa_key_load": ([_P, _S, _P, _S, _P, _P, _P, _P, _P, _P, _S, _P, _P], _I),
     "rsa_key_free": ([_P], None),
@@ -382,6 +383,18 @@ class RsaKey:
                                  1 if use_crt else 0, _stream_handle(stream)))
         return out
 
+
+    def verify_crt(self, c, m, stream=None) -> int:
+        """rsa_crt_verify: recomputes m^e mod n for every row and compares it
+        with c; failing rows of m are zeroed.  Returns their number (0: all
+        pass).  Synchronises the stream."""
+        B = c.shape[0]
+        nb = ctypes.c_size_t(0)
+        rc = lib().rsa_crt_verify(self._h, _dev_ptr(c, B, self.L, "c"), _dev_ptr(m, B, self.L, "m"), B,
+                                  ctypes.byref(nb), _stream_handle(stream))
+        if rc not in (0, -6):
+            _check(rc)
+        return int(nb.value)
 
     @property
     def half_limbs(self) -> int:

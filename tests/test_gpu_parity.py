@@ -319,6 +319,33 @@ def test_modexp_jobs_mixed_moduli():
     assert outs[6].shape == (0, 32)
 
 
+def test_crt_verify_detects_faulty_half():
+    """rsa_crt_verify, the check against faults in CRT decryption: 40
+    RSA-2048 ciphertexts through rsa_crt_halves and rsa_crt_combine all pass;
+    with a bit of m_p flipped in row 5 and a bit of m_q in row 17 between the
+    two launches (faults planted in the data from the host), exactly those
+    two rows fail and are zeroed, and the others equal the oracle's."""
+    from paper_1305_3699_amd import RsaKey
+    k = gen.rsa_key(2048, seed=gen.config_seed(3, 12))
+    rk = RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv)
+    c = gen.to_limbs(gen.uniform_below(k.n, 40, seed=gen.config_seed(8, 26)), 64)
+    want = oracle.rsa_crt_batch(c, k.p, k.q, k.dp, k.dq, k.qinv)
+    dc = _dev(c)
+    mpq = rk.crt_halves(dc)
+    m = rk.crt_combine(mpq)
+    assert rk.verify_crt(dc, m) == 0
+    assert np.array_equal(_host(m), want)
+    bad = mpq.clone()
+    bad[5, 3] ^= 1 << 9
+    bad[17, rk.half_limbs + 7] ^= 1
+    m2 = rk.crt_combine(bad)
+    assert rk.verify_crt(dc, m2) == 2
+    got = _host(m2)
+    assert not got[[5, 17]].any()
+    keep = [i for i in range(40) if i not in (5, 17)]
+    assert np.array_equal(got[keep], want[keep])
+
+
 def test_mont_mul_8192_bit():
     """The standalone product at 8192 bits (k = 257, channel kernels)."""
     rng = random.Random(257)

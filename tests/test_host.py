@@ -310,6 +310,15 @@ def test_modexp_jobs_argument_errors():
     assert b"job 0" in lib.rns_last_error()
 
 
+def test_crt_verify_argument_errors():
+    """rsa_crt_verify refuses a null key or buffer before any device work and
+    reports no failing element."""
+    lib = rnsrsa.lib()
+    nb = ctypes.c_size_t(7)
+    assert lib.rsa_crt_verify(None, None, None, 1, ctypes.byref(nb), None) == -1
+    assert nb.value == 0
+
+
 def test_keygen_argument_errors():
     """Argument checks of the primality entry points that fail before any
     device work (a nonzero count with null buffers, an even candidate, a

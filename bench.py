@@ -23,8 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "RSA-2048 CRT decrypts/sec on 1 MI355X (batched vs plain), p50/p99 latency"
-# MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz; v_mad_u64_u32 (32x32->64
-# multiply-add) issues at the full per-lane rate on gfx950.
+# MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz, the full per-lane VALU issue
+# rate.  The rate of v_mad_u64_u32 (32x32->64 multiply-add) itself is
+# measured on the device (rns_probe_alu) and reported beside it.
 PEAK_MUL_PER_S = 256 * 64 * 2.4e9
 # MI355X dense int8 matrix-core peak (v_mfma_i32_16x16x64_i8): 5.0 POP/s.
 PEAK_I8_OPS_PER_S = 5.0e15
@@ -97,6 +98,16 @@ def kernel_shape(info: dict) -> tuple:
         if k == info["k"] and w == info["waves"] and 16 * nt == info["group"]:
             return (k, w, mt, nt)
     return (info["k"], info["waves"])
+
+
+def probe_alu_rate(op: int):
+    """Measured lane-ops/s of a wide multiply form (0: v_mad_u64_u32, 1:
+    v_mad_i64_i32) on the current GPU, or None if the probe fails."""
+    import ctypes
+
+    from paper_1305_3699_amd import rnsrsa
+    v = ctypes.c_double(0.0)
+    return v.value if rnsrsa.lib().rns_probe_alu(op, ctypes.byref(v), None) == 0 else None
 
 
 def i8_macs_per_mm(k: int) -> int:
@@ -240,6 +251,11 @@ def run(args) -> dict:
         "frac": round(achieved / PEAK_MUL_PER_S, 4),
         "work_per_launch": muls_per_launch,
     }
+    mad = probe_alu_rate(0)
+    if mad:
+        valu["peak_measured"] = round(mad / 1e12, 4)
+        valu["frac_measured"] = round(achieved / mad, 4)
+        valu["measured"] = "v_mad_u64_u32 lane-ops/s on this GPU (rns_probe_alu)"
     if info["engine"] == 2:
         ops = 2 * B * mms * i8_macs_per_mm(k)
         roofline = {"bound": "mfma", "kernel": kname,

@@ -277,6 +277,21 @@ int rsa_crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t 
 int rsa_crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, void *hip_stream);
 
 /*
+ * rns_probe_alu -- measured throughput of one vector-ALU wide multiply form
+ * on the current device: the denominator of the roofline of the per-channel
+ * steps of an RNS product (32 x 32 -> 64-bit multiply-adds).  Each lane runs
+ * 8 independent chains of 4096 dependent instructions; 32 workgroups of 256
+ * lanes per compute unit; the second of two launches is timed with HIP
+ * events on hip_stream (synchronised).  *lane_ops_per_s = instructions x
+ * lanes per second.  RNS_EINVAL for an unknown op or a null output.
+ */
+enum rns_probe_op {
+    RNS_PROBE_MAD_U64_U32 = 0,   /* v_mad_u64_u32: the REDC and residue products */
+    RNS_PROBE_MAD_I64_I32 = 1    /* v_mad_i64_i32: recombination of the matrix cores' byte partials */
+};
+int rns_probe_alu(int op, double *lane_ops_per_s, void *hip_stream);
+
+/*
  * rsa_crt_verify -- check of CRT decryption results against fault attacks
  * (a fault in one half of a CRT decryption gives an m whose gcd with n
  * reveals a factor; the paper keeps the private key on the GPU, Sec. 4.3):

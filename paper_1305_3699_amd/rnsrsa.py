@@ -93,6 +93,7 @@ _SIGNATURES = {
     "rns_modexp_batch": ([_P, _P, _P, _S, _S, _P, _S, _P], _I),
     "rns_modexp_jobs": ([_P, _S, _P], _I),
     "rsa_crt_verify": ([_P, _P, _P, _S, _P, _P], _I),
+    "rns_probe_alu": ([_I, _P, _P], _I),
     "rns_mont_mul_batch": ([_P, _P, _P, _P, _S, _P], _I),
     "rsa_key_load": ([_P, _S, _P, _S, _P, _P, _P, _P, _P, _P, _S, _P, _P], _I),
     "rsa_key_free": ([_P], None),

@@ -346,6 +346,18 @@ def test_crt_verify_detects_faulty_half():
     assert np.array_equal(got[keep], want[keep])
 
 
+def test_probe_alu_rates():
+    """rns_probe_alu measures both wide multiply forms at a plausible rate:
+    above a quarter of the full per-lane issue rate (256 CUs x 64 lanes x
+    2.4 GHz = 39.3 T lane-ops/s) and not above it."""
+    import ctypes
+    from paper_1305_3699_amd import rnsrsa
+    for op in (0, 1):
+        v = ctypes.c_double(0.0)
+        assert rnsrsa.lib().rns_probe_alu(op, ctypes.byref(v), None) == 0
+        assert 0.25 * 39.3e12 < v.value <= 1.02 * 39.3e12, (op, v.value)
+
+
 def test_mont_mul_8192_bit():
     """The standalone product at 8192 bits (k = 257, channel kernels)."""
     rng = random.Random(257)

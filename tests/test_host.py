@@ -319,6 +319,16 @@ def test_crt_verify_argument_errors():
     assert nb.value == 0
 
 
+def test_probe_alu_argument_errors():
+    """rns_probe_alu refuses an unknown instruction form or a null output
+    before any device work."""
+    lib = rnsrsa.lib()
+    v = ctypes.c_double(1.0)
+    assert lib.rns_probe_alu(7, ctypes.byref(v), None) == -1
+    assert v.value == 0.0
+    assert lib.rns_probe_alu(0, None, None) == -1
+
+
 def test_keygen_argument_errors():
     """Argument checks of the primality entry points that fail before any
     device work (a nonzero count with null buffers, an even candidate, a

@@ -421,7 +421,8 @@ def test_rsa16384_full_modulus():
     """RSA-16384 with the full modulus on bases of 512 + 1 channels (k = 513,
     matrix engine only): 20 encryptions (a full tile and a ragged one) against
     the oracle; non-CRT decryption with the full-length d of 3 of them gives
-    the messages back and agrees with the CRT path (257-channel halves)."""
+    the messages back and agrees with the CRT path (257-channel halves),
+    whose results pass the re-encryption check."""
     from paper_1305_3699_amd import ENGINE_MATRIX
     rk, parts = _rsa16384_key()
     n, e = parts["n"], parts["e"]
@@ -434,7 +435,10 @@ def test_rsa16384_full_modulus():
     sel = c[[0, 1, 19]]
     full = _host(rk.decrypt(_dev(sel), use_crt=False))
     assert np.array_equal(full, ml[[0, 1, 19]])
-    assert np.array_equal(full, _host(rk.decrypt(_dev(sel), use_crt=True)))
+    dsel = _dev(sel)
+    crt = rk.decrypt(dsel, use_crt=True)
+    assert np.array_equal(full, _host(crt))
+    assert rk.verify_crt(dsel, crt) == 0          # re-encryption on the 513-channel base
 
 
 def test_batched_with_rsa16384_crt_only_key():

@@ -439,7 +439,6 @@ int rns_modexp_batch(rns_ctx *ctx, const uint32_t *base, const uint32_t *exp, si
 }
 
 int rns_modexp_jobs(const rns_job *jobs, size_t njobs, void *hip_stream) {
-    using namespace rnsrsa::api;
     if (njobs == 0) return ok();
     if (!jobs) return fail(RNS_EINVAL, "null job array");
     if (njobs > (1u << 20)) return fail(RNS_EINVAL, "more than 2^20 jobs");

@@ -321,6 +321,17 @@ def run(args) -> dict:
                       % (ns, B, t3 - t2),
             "matches_gpu": bool(np.array_equal(ref, got)),
         }
+        # the correctness definition itself, c^d mod n, on a bounded sample
+        npl = min(max(ns // 16, 1), B)
+        t4 = time.perf_counter()
+        refp = oracle.modexp_batch(c_np[:npl], np.array(gen.to_limbs(key.d, 64)[0]), np.array(gen.to_limbs(key.n, 64)[0]),
+                                   nthreads=threads)
+        t5 = time.perf_counter()
+        out["cpu_baseline"]["plain"] = {
+            "value": round(npl / (t5 - t4), 2), "unit": "decrypts/s",
+            "sample": "first %d ciphertexts, the oracle's c^d mod n (schoolbook, no CRT), %.1f s wall" % (npl, t5 - t4),
+            "matches_gpu": bool(np.array_equal(refp, got[:npl])),
+        }
     return out
 
 

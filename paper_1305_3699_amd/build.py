@@ -52,6 +52,7 @@ def _shape_source(k: int, w: int) -> str:
         f"template hipError_t launch_modexp_t<{k}, {w}>(const ModexpLaunch &, hipStream_t);\n"
         f"template hipError_t launch_garner_t<{k}, {w}>(const GarnerLaunch &, hipStream_t);\n"
         f"template hipError_t launch_montmul_t<{k}, {w}>(const MontMulLaunch &, hipStream_t);\n"
+        f"template hipError_t launch_garner_jobs_t<{k}, {w}>(const GJob *, int, int, hipStream_t);\n"
         "}\n"
     )
 

@@ -25,6 +25,8 @@ struct rsa_batch {
     std::vector<uint32_t *> d_tables;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> done;
+    std::vector<GarnerGroup> ggroups;   // Garner steps, one grouped launch per base shape
+    std::vector<GJob *> d_gjobs;
     uint32_t *d_mpq = nullptr;
     hipEvent_t fork = nullptr;
     hipStream_t capture = nullptr;
@@ -38,6 +40,8 @@ struct rsa_batch {
         for (MJob *p : d_jobs)
             if (p) hipFree(p);
         for (uint32_t *p : d_tables)
+            if (p) hipFree(p);
+        for (GJob *p : d_gjobs)
             if (p) hipFree(p);
         for (hipEvent_t e : done)
             if (e) hipEventDestroy(e);
@@ -74,7 +78,10 @@ int enqueue(rsa_batch *b, hipStream_t s) {
     if (rc) return rc;
     for (hipEvent_t d : b->done)
         if ((e = hipStreamWaitEvent(s, d, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-    return launch_plain_and_garner(b->plan, s, false, true);
+    for (size_t i = 0; i < b->ggroups.size(); i++)
+        if ((e = launch_garner_group(b->ggroups[i], b->d_gjobs[i], s)) != hipSuccess)
+            return hip_fail(e, "grouped Garner launch");
+    return RNS_OK;
 }
 
 // Times each candidate tile of a group's shape class on copies of its most
@@ -220,10 +227,20 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
             b->done.push_back(ge);
             if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         }
+        // Garner steps: one grouped launch per base shape, job tables on the device
+        b->ggroups = garner_groups(b->plan);
+        for (const GarnerGroup &g : b->ggroups) {
+            GJob *dj = nullptr;
+            rc = dmalloc((void **)&dj, g.jobs.size() * sizeof(GJob), &b->info.workspace_bytes);
+            b->d_gjobs.push_back(dj);
+            if (rc) return rc;
+            hipError_t e = hipMemcpy(dj, g.jobs.data(), g.jobs.size() * sizeof(GJob), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        }
         hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         b->info.launches = (int)(b->plan.groups.size() + b->plan.plain.size());
-        b->info.garner_launches = (int)b->plan.garners.size();
+        b->info.garner_launches = (int)b->ggroups.size();
         b->info.jobs = (int)b->plan.jobs;
         b->info.modmuls = b->plan.modmuls;
 

@@ -337,8 +337,7 @@ int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batc
 }
 
 // Garner recombination over the p-modulus tables.
-int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s) {
-    const BaseSet &bs = *key->p->plan.base;
+GarnerLaunch garner_launch_of(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch) {
     GarnerLaunch g{};
     g.bc = key->p->d_base;
     g.mc = key->p->d_mod;
@@ -350,7 +349,12 @@ int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t bat
     g.out_limbs = (int)key->n_limbs;
     g.out_stride = (int)key->n_limbs;
     g.batch = (int)batch;
-    hipError_t e = launch_garner(bs.K, bs.W, g, s);
+    return g;
+}
+
+int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s) {
+    const BaseSet &bs = *key->p->plan.base;
+    hipError_t e = launch_garner(bs.K, bs.W, garner_launch_of(key, mpq, m, batch), s);
     if (e != hipSuccess) return hip_fail(e, "garner launch");
     return RNS_OK;
 }

@@ -94,6 +94,8 @@ namespace api {
 const uint32_t *entry_of(const rns_ctx *c);
 // Garner recombination of [m_p | m_q] rows into m (n_limbs limbs).
 int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s);
+// The Garner launch arguments of that recombination.
+GarnerLaunch garner_launch_of(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch);
 // Tile of one matrix-core launch of `tiles` workgroups of shape sh on device
 // dev: the 16-element tile of the same (K, W, MT) instead of the 32-element one
 // when the latter would leave fewer than 1.5 resident waves per SIMD.  Below

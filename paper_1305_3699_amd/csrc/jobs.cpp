@@ -178,6 +178,29 @@ hipError_t launch_group(const JobGroup &g, const MJob *d_jobs, uint32_t *table, 
     return launch_modexp_mfma(g.shape, a, s);
 }
 
+std::vector<GarnerGroup> garner_groups(const JobPlan &p) {
+    std::map<std::pair<int, int>, GarnerGroup> m;
+    for (const GarnerJob &gj : p.garners) {
+        if (gj.count == 0) continue;
+        const BaseSet &bs = *gj.key->p->plan.base;
+        GarnerGroup &g = m[std::make_pair(bs.K, bs.W)];
+        g.K = bs.K;
+        g.W = bs.W;
+        GJob J{};
+        J.g = garner_launch_of(gj.key, gj.mpq, gj.out, gj.count);
+        J.tile0 = g.tiles;
+        g.tiles += (int)((gj.count + 63) / 64);
+        g.jobs.push_back(J);
+    }
+    std::vector<GarnerGroup> out;
+    for (auto &kv : m) out.push_back(std::move(kv.second));
+    return out;
+}
+
+hipError_t launch_garner_group(const GarnerGroup &g, const GJob *d_jobs, hipStream_t s) {
+    return launch_garner_jobs(g.K, g.W, d_jobs, (int)g.jobs.size(), g.tiles, s);
+}
+
 int launch_plain_and_garner(const JobPlan &p, hipStream_t s, bool plain, bool garner) {
     if (plain)
         for (const PlainJob &j : p.plain) {

@@ -93,5 +93,18 @@ hipError_t launch_group(const JobGroup &g, const MJob *d_jobs, uint32_t *table, 
 // Enqueue the channel-engine jobs and the Garner steps of a plan on s.
 int launch_plain_and_garner(const JobPlan &p, hipStream_t s, bool plain, bool garner);
 
+// Garner steps of one base shape (K, W): one grouped launch whose
+// workgroups serve every key's step of that shape at once.
+struct GarnerGroup {
+    int K = 0, W = 0;
+    std::vector<GJob> jobs;
+    int tiles = 0;
+};
+// The plan's Garner steps grouped by base shape, with the buffer pointers
+// they hold in p.garners (so rebase those first).
+std::vector<GarnerGroup> garner_groups(const JobPlan &p);
+// Enqueue one grouped Garner launch with device job table d_jobs.
+hipError_t launch_garner_group(const GarnerGroup &g, const GJob *d_jobs, hipStream_t s);
+
 }  // namespace api
 }  // namespace rnsrsa

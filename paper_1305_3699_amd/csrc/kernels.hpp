@@ -53,6 +53,14 @@ struct GarnerLaunch {
     int batch;
 };
 
+// One Garner step of a grouped launch (several keys of one base shape):
+// the fields of GarnerLaunch plus the job's first workgroup (64 elements
+// each) in the launch.  Jobs are ordered by tile0.
+struct GJob {
+    GarnerLaunch g;
+    int tile0;
+};
+
 struct MontMulLaunch {
     const uint32_t *bc;
     const uint32_t *mc;
@@ -93,6 +101,8 @@ int mfma_blocks_per_cu(const MLayout &shape);
 hipError_t launch_modexp_mfma(const MLayout &shape, const ModexpMfmaLaunch &a, hipStream_t s);
 hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s);
 hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s);
+// Grouped Garner steps: `tiles` workgroups over njobs jobs (device table).
+hipError_t launch_garner_jobs(int K, int W, const GJob *jobs, int njobs, int tiles, hipStream_t s);
 hipError_t launch_montmul(int K, int W, const MontMulLaunch &a, hipStream_t s);
 
 }  // namespace rnsrsa

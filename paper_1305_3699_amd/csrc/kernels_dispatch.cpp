@@ -11,11 +11,14 @@ template <int K, int W>
 hipError_t launch_garner_t(const GarnerLaunch &a, hipStream_t s);
 template <int K, int W>
 hipError_t launch_montmul_t(const MontMulLaunch &a, hipStream_t s);
+template <int K, int W>
+hipError_t launch_garner_jobs_t(const GJob *jobs, int njobs, int tiles, hipStream_t s);
 
 #define RNSRSA_SHAPE(k, w)                                                          \
     extern template hipError_t launch_modexp_t<k, w>(const ModexpLaunch &, hipStream_t); \
     extern template hipError_t launch_garner_t<k, w>(const GarnerLaunch &, hipStream_t); \
-    extern template hipError_t launch_montmul_t<k, w>(const MontMulLaunch &, hipStream_t);
+    extern template hipError_t launch_montmul_t<k, w>(const MontMulLaunch &, hipStream_t); \
+    extern template hipError_t launch_garner_jobs_t<k, w>(const GJob *, int, int, hipStream_t);
 #include "kernel_configs.inc"
 #undef RNSRSA_SHAPE
 
@@ -75,6 +78,14 @@ hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s) {
 hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s) {
 #define RNSRSA_SHAPE(k, w) \
     if (K == k && W == w) return launch_garner_t<k, w>(a, s);
+#include "kernel_configs.inc"
+#undef RNSRSA_SHAPE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_garner_jobs(int K, int W, const GJob *jobs, int njobs, int tiles, hipStream_t s) {
+#define RNSRSA_SHAPE(k, w) \
+    if (K == k && W == w) return launch_garner_jobs_t<k, w>(jobs, njobs, tiles, s);
 #include "kernel_configs.inc"
 #undef RNSRSA_SHAPE
     return hipErrorInvalidValue;

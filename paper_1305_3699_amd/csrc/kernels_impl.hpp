@@ -449,17 +449,26 @@ __global__ __launch_bounds__(64 * W) void modexp_kernel(
 //   h = ((m_p - m_q) qinv) mod p as one RNS Montgomery product of the entry
 //   value Z = m_p A + m_q (p - A), A = qinv M mod p, then m = m_q + h q.
 template <int K, int W>
-__global__ __launch_bounds__(64 * W) void garner_kernel(
-    const uint32_t *__restrict__ bc, const uint32_t *__restrict__ mc, const uint32_t *__restrict__ E,
-    const uint32_t *__restrict__ ql, const uint32_t *__restrict__ in, uint32_t *__restrict__ out, int L,
-    int out_limbs, int out_stride, int batch) {
+struct GarnerLds {
+    static constexpr int WORDS = 2 * Shp<K, W>::KP * 64 + 2 * W * 64;
+};
+
+// Elements [e0, e0 + 64) of one Garner step (lds: GarnerLds<K, W>::WORDS).
+template <int K, int W>
+__device__ __forceinline__ void garner_tile(const GarnerLaunch &G, int e0, uint32_t *lds) {
     using S = Shp<K, W>;
     constexpr int KS = S::KS, KP = S::KP;
-    __shared__ uint32_t lds[2 * KP * 64 + 2 * W * 64];
+    const uint32_t *__restrict__ bc = G.bc;
+    const uint32_t *__restrict__ mc = G.mc;
+    const uint32_t *__restrict__ E = G.E;
+    const uint32_t *__restrict__ ql = G.qlimbs;
+    const uint32_t *__restrict__ in = G.in;
+    uint32_t *__restrict__ out = G.out;
+    const int L = G.L, out_limbs = G.out_limbs, out_stride = G.out_stride, batch = G.batch;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int c0 = wave * KS;
-    const int msg = blockIdx.x * 64 + lane;
+    const int msg = e0 + lane;
     const bool active = msg < batch;
     const size_t msafe = active ? (size_t)msg : 0;
     const uint32_t *src = in + msafe * (size_t)(2 * L);
@@ -511,6 +520,27 @@ __global__ __launch_bounds__(64 * W) void garner_kernel(
     cout[wave * 128 + 64 + lane] = (uint32_t)(carry >> 32);
     __syncthreads();
     if (wave == 0 && active) ripple_carries(dst, 1, out_limbs, cout, W, C, lane);
+}
+
+template <int K, int W>
+__global__ __launch_bounds__(64 * W) void garner_kernel(GarnerLaunch G) {
+    __shared__ uint32_t lds[GarnerLds<K, W>::WORDS];
+    garner_tile<K, W>(G, blockIdx.x * 64, lds);
+}
+
+// Grouped Garner steps: workgroup t serves the job j with
+// jobs[j].tile0 <= t < jobs[j+1].tile0 (binary search; jobs sorted).
+template <int K, int W>
+__global__ __launch_bounds__(64 * W) void garner_jobs_kernel(const GJob *__restrict__ jobs, int njobs) {
+    __shared__ uint32_t lds[GarnerLds<K, W>::WORDS];
+    const int t = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    const GJob J = jobs[lo];
+    garner_tile<K, W>(J.g, (t - J.tile0) * 64, lds);
 }
 
 // One RNS Montgomery product per element on channel-major residues.
@@ -565,8 +595,14 @@ hipError_t launch_modexp_t(const ModexpLaunch &a, hipStream_t s) {
 template <int K, int W>
 hipError_t launch_garner_t(const GarnerLaunch &a, hipStream_t s) {
     const unsigned gx = (unsigned)((a.batch + 63) / 64);
-    hipLaunchKernelGGL((garner_kernel<K, W>), dim3(gx), dim3(64 * W), 0, s, a.bc, a.mc, a.E, a.qlimbs, a.in,
-                       a.out, a.L, a.out_limbs, a.out_stride, a.batch);
+    hipLaunchKernelGGL((garner_kernel<K, W>), dim3(gx), dim3(64 * W), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int K, int W>
+hipError_t launch_garner_jobs_t(const GJob *jobs, int njobs, int tiles, hipStream_t s) {
+    if (tiles <= 0 || njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL((garner_jobs_kernel<K, W>), dim3((unsigned)tiles), dim3(64 * W), 0, s, jobs, njobs);
     return hipGetLastError();
 }
 

@@ -69,9 +69,10 @@ size_t op_bytes(const rsa_key *k, int kind, size_t count) {
         if (!c || c->engine != RNS_ENGINE_MATRIX) continue;
         words += modexp_mfma_table_words(c->mshape, 6, (size_t)mfma_tiles(c->mshape, count));
     }
-    // job descriptors, plus the alignment of the arena's regions (inputs,
-    // outputs, CRT scratch, one table per group, job tables: at most 6 per op)
-    return words * sizeof(uint32_t) + 2 * sizeof(MJob) + 6 * kAlign;
+    // job descriptors (two exponentiations and a Garner step at most), plus
+    // the alignment of the arena's regions (inputs, outputs, CRT scratch, one
+    // table per group, job tables, Garner job tables: at most 7 per op)
+    return words * sizeof(uint32_t) + 2 * sizeof(MJob) + sizeof(GJob) + 7 * kAlign;
 }
 
 // Kernel-shape class of a request: the context its exponentiations run on
@@ -126,7 +127,7 @@ int dispatch(rsa_server *srv, Slot &sl, const rsa_request *reqs, const std::vect
         }
         ops[it->second].reqs.push_back(id);
     }
-    // device layout: [inputs | outputs | CRT scratch | window tables | job tables]
+    // device layout: [inputs | outputs | CRT scratch | window tables | job tables | Garner job tables]
     size_t in_words = 0, out_words = 0, mpq_words = 0;
     for (const Op &o : ops) {
         const rsa_key *k = srv->keys[o.key];
@@ -164,10 +165,14 @@ int dispatch(rsa_server *srv, Slot &sl, const rsa_request *reqs, const std::vect
         g_jobs.push_back(jobs_off + njobs * sizeof(MJob));
         njobs += g.jobs.size();
     }
-    const size_t total = jobs_off + align_up(njobs * sizeof(MJob));
+    // at most one Garner job per planned Garner step
+    const size_t mjob_bytes = align_up(njobs * sizeof(MJob)), ngj = plan.garners.size();
+    const size_t gj_off = jobs_off + mjob_bytes;
+    const size_t total = gj_off + align_up(ngj * sizeof(GJob));
 
-    // pinned staging: inputs then job tables (one copy), outputs
-    if ((rc = ensure_pinned(&sl.h_in, &sl.h_in_bytes, align_up(in_words * 4) + njobs * sizeof(MJob)))) return rc;
+    // pinned staging: inputs then job tables and Garner job tables (one copy), outputs
+    if ((rc = ensure_pinned(&sl.h_in, &sl.h_in_bytes, align_up(in_words * 4) + mjob_bytes + ngj * sizeof(GJob))))
+        return rc;
     if ((rc = ensure_pinned(&sl.h_out, &sl.h_out_bytes, out_words * 4))) return rc;
     hipError_t e = hipMallocAsync(&sl.d_arena, total, sl.stream);
     if (e != hipSuccess) {
@@ -209,6 +214,15 @@ int dispatch(rsa_server *srv, Slot &sl, const rsa_request *reqs, const std::vect
         gj.mpq = rebase(gj.mpq);
         gj.out = rebase(gj.out);
     }
+    // Garner steps grouped by base shape (real pointers), after the job tables
+    const std::vector<GarnerGroup> gg = garner_groups(plan);
+    GJob *hg = (GJob *)((char *)hj + mjob_bytes);
+    std::vector<size_t> g_gj;
+    size_t gn = 0;
+    for (const GarnerGroup &g : gg) {
+        g_gj.push_back(gj_off + gn * sizeof(GJob));
+        for (const GJob &J : g.jobs) hg[gn++] = J;
+    }
     // enqueue (on failure the arena is released on the slot's stream)
     struct ArenaGuard {
         Slot &sl;
@@ -219,14 +233,17 @@ int dispatch(rsa_server *srv, Slot &sl, const rsa_request *reqs, const std::vect
     } guard{sl};
     if ((e = hipMemcpyAsync(base + in_off, sl.h_in, in_words * 4, hipMemcpyHostToDevice, sl.stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
-    if (njobs && (e = hipMemcpyAsync(base + jobs_off, hj, njobs * sizeof(MJob), hipMemcpyHostToDevice, sl.stream)) !=
-                     hipSuccess)
+    if ((njobs || gn) && (e = hipMemcpyAsync(base + jobs_off, hj, mjob_bytes + gn * sizeof(GJob),
+                                             hipMemcpyHostToDevice, sl.stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     for (size_t i = 0; i < plan.groups.size(); i++)
         if ((e = launch_group(plan.groups[i], (const MJob *)(base + g_jobs[i]), (uint32_t *)(base + g_tbl[i]),
                               sl.stream)) != hipSuccess)
             return hip_fail(e, "grouped modexp launch");
-    if ((rc = launch_plain_and_garner(plan, sl.stream, true, true))) return rc;
+    if ((rc = launch_plain_and_garner(plan, sl.stream, true, false))) return rc;
+    for (size_t i = 0; i < gg.size(); i++)
+        if ((e = launch_garner_group(gg[i], (const GJob *)(base + g_gj[i]), sl.stream)) != hipSuccess)
+            return hip_fail(e, "grouped Garner launch");
     if ((e = hipMemcpyAsync(sl.h_out, base + out_off, out_words * 4, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     e = hipFreeAsync(sl.d_arena, sl.stream);

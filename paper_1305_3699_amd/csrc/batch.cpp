@@ -27,6 +27,7 @@ struct rsa_batch {
     std::vector<hipEvent_t> done;
     std::vector<GarnerGroup> ggroups;   // Garner steps, one grouped launch per base shape
     std::vector<GJob *> d_gjobs;
+    std::vector<int> gdep;              // the one exponentiation group a Garner group waits for, or -1
     uint32_t *d_mpq = nullptr;
     hipEvent_t fork = nullptr;
     hipStream_t capture = nullptr;
@@ -68,18 +69,23 @@ int dmalloc(void **p, size_t bytes, size_t *total) {
 int enqueue(rsa_batch *b, hipStream_t s) {
     hipError_t e = hipEventRecord(b->fork, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    // each exponentiation group on its stream, followed there by the Garner
+    // groups that need only its results; the others follow the join on s
     for (size_t i = 0; i < b->plan.groups.size(); i++) {
         if ((e = hipStreamWaitEvent(b->streams[i], b->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         if ((e = launch_group(b->plan.groups[i], b->d_jobs[i], b->d_tables[i], b->streams[i])) != hipSuccess)
             return hip_fail(e, "grouped modexp launch");
+        for (size_t j = 0; j < b->ggroups.size(); j++)
+            if (b->gdep[j] == (int)i && (e = launch_garner_group(b->ggroups[j], b->d_gjobs[j], b->streams[i])) != hipSuccess)
+                return hip_fail(e, "grouped Garner launch");
         if ((e = hipEventRecord(b->done[i], b->streams[i])) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
     int rc = launch_plain_and_garner(b->plan, s, true, false);
     if (rc) return rc;
     for (hipEvent_t d : b->done)
         if ((e = hipStreamWaitEvent(s, d, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-    for (size_t i = 0; i < b->ggroups.size(); i++)
-        if ((e = launch_garner_group(b->ggroups[i], b->d_gjobs[i], s)) != hipSuccess)
+    for (size_t j = 0; j < b->ggroups.size(); j++)
+        if (b->gdep[j] < 0 && (e = launch_garner_group(b->ggroups[j], b->d_gjobs[j], s)) != hipSuccess)
             return hip_fail(e, "grouped Garner launch");
     return RNS_OK;
 }
@@ -227,8 +233,22 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
             b->done.push_back(ge);
             if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         }
-        // Garner steps: one grouped launch per base shape, job tables on the device
+        // Garner steps: one grouped launch per base shape, job tables on the
+        // device; a group whose halves all come from one matrix-core
+        // exponentiation group (same k, no channel-engine jobs of that k)
+        // runs right after it on its stream
         b->ggroups = garner_groups(b->plan);
+        for (const GarnerGroup &g : b->ggroups) {
+            int dep = -1, n = 0;
+            for (size_t i = 0; i < b->plan.groups.size(); i++)
+                if (b->plan.groups[i].shape.K == g.K) {
+                    dep = (int)i;
+                    n++;
+                }
+            for (const PlainJob &pj : b->plan.plain)
+                if (pj.c0->plan.base->K == g.K) n = 2;
+            b->gdep.push_back(n == 1 ? dep : -1);
+        }
         for (const GarnerGroup &g : b->ggroups) {
             GJob *dj = nullptr;
             rc = dmalloc((void **)&dj, g.jobs.size() * sizeof(GJob), &b->info.workspace_bytes);

@@ -316,8 +316,11 @@ int rsa_crt_verify(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t ba
  * half- or full-size k share a matrix-core kernel shape run in ONE launch per
  * shape (one workgroup per tile of 16 or 32 elements, longest jobs first),
  * the launches of different shapes run concurrently on internal streams, and
- * the Garner steps of CRT decryptions follow.  With use_graph the whole set
- * is captured once into a hipGraph and each run is one graph launch.
+ * the Garner steps of CRT decryptions follow, grouped the same way: one
+ * launch per base shape of the halves (on the stream of the exponentiation
+ * group that produced the halves when that group alone did).  With
+ * use_graph the whole set is captured once into a hipGraph and each run is
+ * one graph launch.
  *
  *   rsa_op.kind  RSA_OP_ENCRYPT: out = in^e mod n;
  *                RSA_OP_DECRYPT: out = in^d mod n, by CRT when the key has
@@ -360,7 +363,7 @@ typedef struct rsa_batch_opts {
 typedef struct rsa_batch_info {
     int launches;            /* exponentiation launches per run */
     int jobs;                /* exponentiation jobs (a CRT decryption is 2) */
-    int garner_launches;
+    int garner_launches;     /* grouped Garner launches per run (one per base shape of CRT halves) */
     size_t workspace_bytes;  /* device memory held by the batch */
     size_t modmuls;          /* RNS Montgomery products per element, summed over elements */
 } rsa_batch_info;

@@ -436,35 +436,37 @@ def run_served(args) -> dict:
         for i in range(n):
             L = limbs[kidx[i]]
             msgs[i, :L] = gen.to_limbs(gen.uniform_below_fast(keys[kidx[i]].n, int(seeds[i])), L)[0]
-        srv = RsaServer(rks, hbm_budget=64 << 30, max_inflight=args.served_inflight)
-        res, lat, st = srv.replay(kidx, kind, arrival, msgs)
-        srv.close()
-        sel = arrival >= args.served_warmup
-        lw = np.sort(lat[sel])
-        done_t = arrival + lat
-        in_window = (done_t >= args.served_warmup) & (done_t < total)
-        ok = True
-        for i in random.Random(int(rate)).sample(range(n), min(64, n)):
-            k = keys[kidx[i]]
-            L = limbs[kidx[i]]
-            x = np.ascontiguousarray(msgs[i:i + 1, :L])
-            want = (oracle.modexp_batch(x, gen.to_limbs(k.e, 1)[0], gen.to_limbs(k.n, L)[0]) if kind[i] == 0
-                    else oracle.rsa_crt_batch(x, k.p, k.q, k.dp, k.dq, k.qinv))
-            ok = ok and bool(np.array_equal(res[i:i + 1, :L], want))
-        out["runs"].append({
-            "offered_req_per_s": rate,
-            "requests": int(sel.sum()),
-            "completed_per_s": round(float(in_window.sum()) / args.served_duration, 1),
-            "latency_ms": {"p50": round(float(lw[(lw.size - 1) // 2]) * 1e3, 3),
-                           "p99": round(float(lw[min(lw.size - 1, int(0.99 * (lw.size - 1) + 0.5))]) * 1e3, 3),
-                           "max": round(float(lw[-1]) * 1e3, 3)},
-            "dispatches": st["dispatches"],
-            "mean_dispatch_requests": round(st["mean_dispatch_ops"], 1),
-            "peak_inflight": st["peak_inflight"],
-            "peak_inflight_mb": round(st["peak_inflight_bytes"] / 2 ** 20, 1),
-            "sample_matches_oracle": ok,
-        })
-        print("served rate %g: %s" % (rate, json.dumps(out["runs"][-1])), file=sys.stderr, flush=True)
+        for cap in args.served_max_ops:
+            srv = RsaServer(rks, hbm_budget=64 << 30, max_inflight=args.served_inflight, max_dispatch_ops=cap)
+            res, lat, st = srv.replay(kidx, kind, arrival, msgs)
+            srv.close()
+            sel = arrival >= args.served_warmup
+            lw = np.sort(lat[sel])
+            done_t = arrival + lat
+            in_window = (done_t >= args.served_warmup) & (done_t < total)
+            ok = True
+            for i in random.Random(int(rate)).sample(range(n), min(64, n)):
+                k = keys[kidx[i]]
+                L = limbs[kidx[i]]
+                x = np.ascontiguousarray(msgs[i:i + 1, :L])
+                want = (oracle.modexp_batch(x, gen.to_limbs(k.e, 1)[0], gen.to_limbs(k.n, L)[0]) if kind[i] == 0
+                        else oracle.rsa_crt_batch(x, k.p, k.q, k.dp, k.dq, k.qinv))
+                ok = ok and bool(np.array_equal(res[i:i + 1, :L], want))
+            out["runs"].append({
+                "offered_req_per_s": rate,
+                "max_dispatch_ops": cap or 16384,
+                "requests": int(sel.sum()),
+                "completed_per_s": round(float(in_window.sum()) / args.served_duration, 1),
+                "latency_ms": {"p50": round(float(lw[(lw.size - 1) // 2]) * 1e3, 3),
+                               "p99": round(float(lw[min(lw.size - 1, int(0.99 * (lw.size - 1) + 0.5))]) * 1e3, 3),
+                               "max": round(float(lw[-1]) * 1e3, 3)},
+                "dispatches": st["dispatches"],
+                "mean_dispatch_requests": round(st["mean_dispatch_ops"], 1),
+                "peak_inflight": st["peak_inflight"],
+                "peak_inflight_mb": round(st["peak_inflight_bytes"] / 2 ** 20, 1),
+                "sample_matches_oracle": ok,
+            })
+            print("served rate %g: %s" % (rate, json.dumps(out["runs"][-1])), file=sys.stderr, flush=True)
     return out
 
 
@@ -801,6 +803,8 @@ def main(argv=None) -> int:
     ap.add_argument("--served-duration", type=float, default=10.0)
     ap.add_argument("--served-warmup", type=float, default=1.0)
     ap.add_argument("--served-inflight", type=int, default=8)
+    ap.add_argument("--served-max-ops", type=int, nargs="+", default=[0],
+                    help="operations per dispatch at most (0: the server's default, 16384); one run per value")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one elementwise copy of N MiB before the benchmark (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

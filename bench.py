@@ -814,8 +814,8 @@ def main(argv=None) -> int:
         print(json.dumps(ingest_counters(*args.ingest_counters, calib_mb=args.calib_copy_mb or 256), indent=1))
         return 0
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
-              "(multi-GPU sharding is a design note, not a measured configuration)", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures the hot path on a single device "
+              "(sharding over several GPUs is described, not measured)", file=sys.stderr)
         return 2
     if args.modmul_sweep:
         for line in run_modmul_sweep(args):

@@ -112,4 +112,25 @@ struct Layout {
     constexpr int ecols() const { return 2 * KP + 1; }
 };
 
+#ifdef __HIPCC__
+// The limbs of a sum computed as n consecutive ranges of C limbs each, range r
+// starting at limb r*C, whose carries out are cout[2*cs*r] (low word) and
+// cout[2*cs*r + cs] (high word): adds each range's carry into the limbs that
+// follow it, in order (v[l*vs] is limb l; nl limbs in all; a carry past limb
+// nl-1 is dropped, the sum being taken mod 2^(32 nl)).
+template <typename P>
+__device__ __forceinline__ void ripple_carries(P v, size_t vs, int nl, const uint32_t *cout, int cs, int n, int C) {
+    uint64_t c = 0;
+    for (int r = 1; r < n; r++) {
+        c += (uint64_t)cout[2 * cs * (r - 1)] | ((uint64_t)cout[2 * cs * (r - 1) + cs] << 32);
+        const int end = (r + 1) * C < nl ? (r + 1) * C : nl;
+        for (int l = r * C; c != 0 && l < end; l++) {
+            const uint64_t t = (uint64_t)v[l * vs] + (uint32_t)c;
+            v[l * vs] = (uint32_t)t;
+            c = (c >> 32) + (t >> 32);
+        }
+    }
+}
+#endif
+
 }  // namespace rnsrsa

@@ -230,24 +230,6 @@ __device__ __forceinline__ uint64_t exit_columns(const uint32_t *__restrict__ bc
     return carry;
 }
 
-// The limbs of a sum computed as n consecutive ranges of C limbs each, range r
-// starting at limb r*C, whose carries out are cout[r*128 + lane] (low word)
-// and cout[r*128 + 64 + lane] (high word): adds each range's carry into the
-// limbs that follow it, in order (v[l*vs] is limb l; nl limbs in all).
-template <typename P>
-__device__ __forceinline__ void ripple_carries(P v, size_t vs, int nl, const uint32_t *cout, int n, int C, int lane) {
-    uint64_t c = 0;
-    for (int r = 1; r < n; r++) {
-        c += (uint64_t)cout[(r - 1) * 128 + lane] | ((uint64_t)cout[(r - 1) * 128 + 64 + lane] << 32);
-        const int end = (r + 1) * C < nl ? (r + 1) * C : nl;
-        for (int l = r * C; c != 0 && l < end; l++) {
-            const uint64_t t = (uint64_t)v[l * vs] + (uint32_t)c;
-            v[l * vs] = (uint32_t)t;
-            c = (c >> 32) + (t >> 32);
-        }
-    }
-}
-
 // Given acc = sum_j xi'_j M'_j (L+1 limbs): subtracts alpha M', then takes the
 // canonical representative mod N (the value is below (K+1) N) by conditional
 // subtractions of N 2^b, b = qbits-1 .. 0.  tmp: L+1 rows of scratch.
@@ -492,7 +474,7 @@ __device__ __forceinline__ void garner_tile(const GarnerLaunch &G, int e0, uint3
         cout[wave * 128 + 64 + lane] = (uint32_t)(c >> 32);
         __syncthreads();
         if (wave == 0) {
-            ripple_carries(h + lane, 64, L + 1, cout, W, C, lane);
+            ripple_carries(h + lane, 64, L + 1, cout + lane, 64, W, C);
             exit_reduce<K, W>(bc, mc, h, h + (L + 1) * 64, alpha, L, lane);
         }
         __syncthreads();
@@ -519,7 +501,7 @@ __device__ __forceinline__ void garner_tile(const GarnerLaunch &G, int e0, uint3
     cout[wave * 128 + lane] = (uint32_t)carry;
     cout[wave * 128 + 64 + lane] = (uint32_t)(carry >> 32);
     __syncthreads();
-    if (wave == 0 && active) ripple_carries(dst, 1, out_limbs, cout, W, C, lane);
+    if (wave == 0 && active) ripple_carries(dst, 1, out_limbs, cout + lane, 64, W, C);
 }
 
 template <int K, int W>

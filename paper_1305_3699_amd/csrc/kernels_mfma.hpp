@@ -43,7 +43,14 @@ struct MShp {
         while ((1 << b) <= K + 1) b++;
         return b;
     }
-    static constexpr int EXIT_WORDS = (K + 2 * (K + 1)) * NM;
+    // Exit: [K][NM] digits and 2 x [K+1][NM] limbs; with the split exit (from
+    // 49 channels on, where it pays for itself) also the carries out of the
+    // limb ranges that the 64 W / NM workers per element sum, [workers][2][NM].
+    // Below that one lane per element sums all limbs, and the main loop keeps
+    // its register allocation (the split exit measured 7% slower at k = 33).
+    static constexpr bool SPLIT_EXIT = K >= 49;
+    static constexpr int EXIT_CORE = (K + 2 * (K + 1)) * NM;
+    static constexpr int EXIT_WORDS = EXIT_CORE + (SPLIT_EXIT ? 128 * W : 0);
     static constexpr int BUF_WORDS = 2 * NM * BROW;
     static constexpr int WORK_WORDS = EXIT_WORDS > BUF_WORDS ? EXIT_WORDS : BUF_WORDS;
     // Where the second extension's constant tiles (the same for every key of
@@ -388,6 +395,46 @@ __device__ __forceinline__ uint32_t mexp_digit(const gu32 *__restrict__ e, int n
     return (uint32_t)(v >> sh) & ((1u << w) - 1u);
 }
 
+// End of the exit on wave 0, lane n (element n of the tile, message msg):
+// acc holds the L+1 limbs of sum_j xi'_j M'_j; subtracts alpha M', takes the
+// canonical representative mod N by conditional subtractions of N 2^b, and
+// stores the L limbs.
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ void mfma_exit_tail(const gu32 *__restrict__ mb, const gu32 *__restrict__ mk, uint32_t *acc,
+                                               uint32_t *tmp, uint32_t alpha, int L, int n, int msg, const MJob &J,
+                                               gu32 *__restrict__ out) {
+    using S = MShp<K, W, MT, NT>;
+    constexpr int NM = S::NM;
+    {
+        uint64_t carry = 0;
+        uint32_t borrow = 0;
+        for (int l = 0; l <= L; l++) {
+            const uint64_t p = (uint64_t)alpha * mb[S::LY.MpF() + l] + carry;
+            carry = p >> 32;
+            const uint32_t v = acc[l * NM + n], pl = (uint32_t)p;
+            const uint32_t d = v - pl, d2 = d - borrow;
+            borrow = (v < pl) | (d < borrow);
+            acc[l * NM + n] = d2;
+        }
+    }
+    for (int b = S::qbits() - 1; b >= 0; b--) {
+        uint32_t borrow = 0;
+        for (int l = 0; l <= L; l++) {
+            const uint32_t nlo = l < L ? mk[S::LY.Nl() + l] : 0u;
+            const uint32_t nhi = (b && l > 0) ? (mk[S::LY.Nl() + l - 1] >> (32 - b)) : 0u;
+            const uint32_t nl = (nlo << b) | nhi;
+            const uint32_t v = acc[l * NM + n];
+            const uint32_t d = v - nl, d2 = d - borrow;
+            borrow = (v < nl) | (d < borrow);
+            tmp[l * NM + n] = d2;
+        }
+        if (!borrow)
+            for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
+    }
+    if (msg < J.batch)
+        for (int l = 0; l < L; l++) out[(size_t)msg * J.out_stride + l] = acc[l * NM + n];
+}
+
 // One tile (16*NT elements) of exponentiation job J, elements
 // [e0, e0 + 16*NT) of the job, with window table slot `slot` of the launch.
 template <int K, int W, int MT, int NT>
@@ -664,67 +711,123 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         }
     }
 
-    // leave the RNS: wave 0, lane n < NM handles element n of the workgroup
-    __syncthreads();
-    if (wave != 0 || lane >= S::NM) return;
-    const int n = lane;
-    const int msg = e0 + n;
-    uint32_t rr = a.r[0];
+    // leave the RNS
+    if constexpr (!S::SPLIT_EXIT) {
+        // wave 0, lane n < NM handles element n of the workgroup alone
+        __syncthreads();
+        if (wave != 0 || lane >= S::NM) return;
+        const int n = lane;
+        const int msg = e0 + n;
+        uint32_t rr = a.r[0];
 #pragma unroll
-    for (int nt = 1; nt < NT; nt++) rr = (n >> 4) == nt ? a.r[nt] : rr;   // lane n holds element n's r in slot n/16
-    const int L = J.L;
-    constexpr int NM = S::NM;
-    uint32_t *X = lds;                               // [K][NM] xi'_j of the exit product
-    uint32_t *acc = lds + K * NM;                    // [L+1][NM]
-    uint32_t *tmp = acc + (L + 1) * NM;              // [L+1][NM]
-    uint32_t s2 = 0;
-    for (int jj = 0; jj < K; jj++) {
-        const uint32_t v = buf2[n * S::BROW + jj] ^ kDigitBias;       // xi'_j in [0, m'_j)
-        X[jj * NM + n] = v;
-        s2 += v * mb[S::LY.mplo() + jj];
-    }
-    const uint32_t alpha = (s2 - rr) * C.Mpinv_r;                    // in [0, K)
-    {
-        uint64_t carry = 0;
-        for (int l = 0; l <= L; l++) {
-            Acc sum;
-            sum.lo = carry;
-            for (int jj = 0; jj < K; jj++) acc_mac(sum, X[jj * NM + n], mb[S::LY.MpL() + (size_t)jj * (K + 1) + l]);
-            uint64_t lo;
-            uint32_t top;
-            acc_value(sum, lo, top);
-            acc[l * NM + n] = (uint32_t)lo;
-            carry = (lo >> 32) | ((uint64_t)top << 32);
+        for (int nt = 1; nt < NT; nt++) rr = (n >> 4) == nt ? a.r[nt] : rr;   // lane n holds element n's r in slot n/16
+        const int L = J.L;
+        constexpr int NM = S::NM;
+        uint32_t *X = lds;                               // [K][NM] xi'_j of the exit product
+        uint32_t *acc = lds + K * NM;                    // [L+1][NM]
+        uint32_t *tmp = acc + (L + 1) * NM;              // [L+1][NM]
+        uint32_t s2 = 0;
+        for (int jj = 0; jj < K; jj++) {
+            const uint32_t v = buf2[n * S::BROW + jj] ^ kDigitBias;       // xi'_j in [0, m'_j)
+            X[jj * NM + n] = v;
+            s2 += v * mb[S::LY.mplo() + jj];
         }
-    }
-    {
-        uint64_t carry = 0;
-        uint32_t borrow = 0;
-        for (int l = 0; l <= L; l++) {
-            const uint64_t p = (uint64_t)alpha * mb[S::LY.MpF() + l] + carry;
-            carry = p >> 32;
-            const uint32_t v = acc[l * NM + n], pl = (uint32_t)p;
-            const uint32_t d = v - pl, d2 = d - borrow;
-            borrow = (v < pl) | (d < borrow);
-            acc[l * NM + n] = d2;
+        const uint32_t alpha = (s2 - rr) * C.Mpinv_r;                    // in [0, K)
+        {
+            uint64_t carry = 0;
+            for (int l = 0; l <= L; l++) {
+                Acc sum;
+                sum.lo = carry;
+                for (int jj = 0; jj < K; jj++) acc_mac(sum, X[jj * NM + n], mb[S::LY.MpL() + (size_t)jj * (K + 1) + l]);
+                uint64_t lo;
+                uint32_t top;
+                acc_value(sum, lo, top);
+                acc[l * NM + n] = (uint32_t)lo;
+                carry = (lo >> 32) | ((uint64_t)top << 32);
+            }
         }
-    }
-    for (int b = S::qbits() - 1; b >= 0; b--) {
-        uint32_t borrow = 0;
-        for (int l = 0; l <= L; l++) {
-            const uint32_t nlo = l < L ? mk[S::LY.Nl() + l] : 0u;
-            const uint32_t nhi = (b && l > 0) ? (mk[S::LY.Nl() + l - 1] >> (32 - b)) : 0u;
-            const uint32_t nl = (nlo << b) | nhi;
-            const uint32_t v = acc[l * NM + n];
-            const uint32_t d = v - nl, d2 = d - borrow;
-            borrow = (v < nl) | (d < borrow);
-            tmp[l * NM + n] = d2;
+        {
+            uint64_t carry = 0;
+            uint32_t borrow = 0;
+            for (int l = 0; l <= L; l++) {
+                const uint64_t p = (uint64_t)alpha * mb[S::LY.MpF() + l] + carry;
+                carry = p >> 32;
+                const uint32_t v = acc[l * NM + n], pl = (uint32_t)p;
+                const uint32_t d = v - pl, d2 = d - borrow;
+                borrow = (v < pl) | (d < borrow);
+                acc[l * NM + n] = d2;
+            }
         }
-        if (!borrow)
-            for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
+        for (int b = S::qbits() - 1; b >= 0; b--) {
+            uint32_t borrow = 0;
+            for (int l = 0; l <= L; l++) {
+                const uint32_t nlo = l < L ? mk[S::LY.Nl() + l] : 0u;
+                const uint32_t nhi = (b && l > 0) ? (mk[S::LY.Nl() + l - 1] >> (32 - b)) : 0u;
+                const uint32_t nl = (nlo << b) | nhi;
+                const uint32_t v = acc[l * NM + n];
+                const uint32_t d = v - nl, d2 = d - borrow;
+                borrow = (v < nl) | (d < borrow);
+                tmp[l * NM + n] = d2;
+            }
+            if (!borrow)
+                for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
+        }
+        if (msg < J.batch)
+            for (int l = 0; l < L; l++) out[(size_t)msg * J.out_stride + l] = acc[l * NM + n];
+    } else {
+        __syncthreads();
+        const int L = J.L;
+        constexpr int NM = S::NM;
+        uint32_t *X = lds;                           // [K][NM] xi'_j of the exit product
+        uint32_t *acc = lds + K * NM;                // [L+1][NM]
+        uint32_t *tmp = acc + (L + 1) * NM;          // [L+1][NM]
+        // wave 0 (lane n < NM: element n) gathers xi'_j and alpha; then every
+        // wave and lane group sums a contiguous range of the limbs of
+        // sum_j xi'_j M'_j (the range sums are independent); wave 0 adds the
+        // carries between the ranges and finishes
+        uint32_t *cout = lds + S::EXIT_CORE;         // [workers][2][NM]
+        uint32_t alpha = 0;
+        if (wave == 0 && lane < NM) {
+            const int n = lane;
+            uint32_t rr = a.r[0];
+#pragma unroll
+            for (int nt = 1; nt < NT; nt++) rr = (n >> 4) == nt ? a.r[nt] : rr;
+            uint32_t s2 = 0;
+            for (int jj = 0; jj < K; jj++) {
+                const uint32_t v = buf2[n * S::BROW + jj] ^ kDigitBias;
+                X[jj * NM + n] = v;
+                s2 += v * mb[S::LY.mplo() + jj];
+            }
+            alpha = (s2 - rr) * C.Mpinv_r;
+        }
+        __syncthreads();
+        constexpr int NW = W * (64 / NM);            // workers per element
+        const int CW = (L + 1 + NW - 1) / NW;        // limbs per worker
+        {
+            const int n = lane % NM, wid = wave * (64 / NM) + lane / NM;
+            const int l0 = wid * CW < L + 1 ? wid * CW : L + 1;
+            const int l1 = l0 + CW < L + 1 ? l0 + CW : L + 1;
+            uint64_t carry = 0;
+            for (int l = l0; l < l1; l++) {
+                Acc sum;
+                sum.lo = carry;
+                for (int jj = 0; jj < K; jj++)
+                    acc_mac(sum, X[jj * NM + n], mb[S::LY.MpL() + (size_t)jj * (K + 1) + l]);
+                uint64_t lo;
+                uint32_t top;
+                acc_value(sum, lo, top);
+                acc[l * NM + n] = (uint32_t)lo;
+                carry = (lo >> 32) | ((uint64_t)top << 32);
+            }
+            cout[2 * NM * wid + n] = (uint32_t)carry;
+            cout[2 * NM * wid + NM + n] = (uint32_t)(carry >> 32);
+        }
+        __syncthreads();
+        if (wave != 0 || lane >= NM) return;
+        const int n = lane;
+        ripple_carries(acc + n, NM, L + 1, cout + n, NM, NW, CW);
+        mfma_exit_tail<K, W, MT, NT>(mb, mk, acc, tmp, alpha, L, n, e0 + n, J, out);
     }
-    if (msg < J.batch)
-        for (int l = 0; l < L; l++) out[(size_t)msg * J.out_stride + l] = acc[l * NM + n];
 }
 
 // Exponentiation kernel, matrix-core variant: workgroup t runs tile t of the

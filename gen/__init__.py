@@ -14,8 +14,11 @@ little-endian uint32.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 import random
+import sys
 from dataclasses import dataclass
 from functools import lru_cache
 
@@ -104,8 +107,16 @@ class RsaKey:
         return self.n.bit_length()
 
 
-def rsa_key(bits: int, seed: int, e: int = 65537) -> RsaKey:
-    """Seeded RSA key with an exactly ``bits``-bit modulus n = p*q."""
+def _key_from_primes(p: int, q: int, e: int) -> RsaKey:
+    n = p * q
+    phi = (p - 1) * (q - 1)
+    d = pow(e, -1, phi)
+    return RsaKey(n=n, e=e, d=d, p=p, q=q, dp=d % (p - 1), dq=d % (q - 1),
+                  qinv=pow(q, -1, p))
+
+
+def _generate_key(bits: int, seed: int, e: int = 65537) -> RsaKey:
+    """The seeded draw itself: p from the first half of the stream, then q."""
     rng = random.Random(seed)
     half = bits // 2
     p = random_prime(half, rng, e)
@@ -113,11 +124,32 @@ def rsa_key(bits: int, seed: int, e: int = 65537) -> RsaKey:
         q = random_prime(bits - half, rng, e)
         if q != p:
             break
-    n = p * q
-    phi = (p - 1) * (q - 1)
-    d = pow(e, -1, phi)
-    return RsaKey(n=n, e=e, d=d, p=p, q=q, dp=d % (p - 1), dq=d % (q - 1),
-                  qinv=pow(q, -1, p))
+    return _key_from_primes(p, q, e)
+
+
+# Keys of the mixed-size and served workloads, drawn once by _generate_key
+# (gen/make_keys.py): "bits:seed" -> [p, q] in hex.
+KEY_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "keys.json")
+
+
+@lru_cache(maxsize=1)
+def _key_cache() -> dict:
+    if not os.path.exists(KEY_CACHE):
+        return {}
+    with open(KEY_CACHE) as fh:
+        return json.load(fh).get("keys", {})
+
+
+def rsa_key(bits: int, seed: int, e: int = 65537) -> RsaKey:
+    """Seeded RSA key with an exactly ``bits``-bit modulus n = p*q (from the
+    stored draw when gen/keys.json holds it, with e = 65537)."""
+    hit = _key_cache().get("%d:%d" % (bits, seed)) if e == 65537 else None
+    if hit is not None:
+        k = _key_from_primes(int(hit[0], 16), int(hit[1], 16), e)
+        if k.n.bit_length() != bits:
+            raise ValueError("gen/keys.json entry %d:%d does not have %d bits" % (bits, seed, bits))
+        return k
+    return _generate_key(bits, seed, e)
 
 
 def uniform_below(n: int, count: int, seed: int) -> list:
@@ -235,18 +267,36 @@ def mixed_batch_spec(n_keys: int = 64, sizes=(1024, 2048, 3072, 4096), median: f
 
 def _key_job(args):
     bits, seed = args
-    return rsa_key(bits, seed)
+    return _generate_key(bits, seed)
+
+
+def _gpu_in_use() -> bool:
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:
+        return False
 
 
 def rsa_keys(specs, processes: int = 1) -> list:
-    """rsa_key for each (bits, seed) in specs, optionally in a process pool
-    (key generation is pure Python: seconds per 4096-bit key)."""
+    """rsa_key for each (bits, seed) in specs.  Keys stored in gen/keys.json
+    are read from it; the others are drawn, optionally in a process pool
+    (pure Python: seconds per 4096-bit key).  A pool forks this process,
+    which must not have touched the GPU yet (a forked copy of an initialised
+    HIP runtime is not usable, and its exit can crash): that case raises."""
     specs = list(specs)
-    if processes <= 1 or len(specs) < 2:
+    cache = _key_cache()
+    missing = [s for s in specs if "%d:%d" % s not in cache]
+    if processes <= 1 or len(missing) < 2:
         return [rsa_key(b, s) for b, s in specs]
+    if _gpu_in_use():
+        raise RuntimeError("rsa_keys: %d keys are not in gen/keys.json and a process pool would fork a process "
+                           "that already uses the GPU; draw them before the first GPU call or use processes=1"
+                           % len(missing))
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(min(processes, len(specs))) as pool:
-        return pool.map(_key_job, specs)
+    with mp.get_context("fork").Pool(min(processes, len(missing))) as pool:
+        drawn = dict(zip(missing, pool.map(_key_job, missing)))
+    return [drawn[s] if s in drawn else rsa_key(*s) for s in specs]
 
 
 # ---------------------------------------------------------------------------

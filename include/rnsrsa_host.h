@@ -37,6 +37,32 @@ int rns_emul_modexp(const rns_plan *plan, const uint32_t *base, const uint32_t *
 /* Host model of rns_mont_mul_batch (same layout, host memory). */
 int rns_emul_mont_mul(const rns_plan *plan, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch);
 
+/*
+ * Host model of one base extension of the matrix-core kernel (which = 1: the
+ * first, q^ into B' and 2^32; which = 2: the second, into B), on raw digits
+ * xi ([batch][k], any 32-bit words; the kernel's digits are residues below
+ * their channel prime).  *rows receives the number of slot rows (waves * 4 *
+ * tiles of the plan's shape); with partials and value both NULL nothing else
+ * is done.  partials: [batch][rows][4] the exact byte partials P_b of every
+ * slot row, in the kernel's slot order: the int32 sums the matrix cores
+ * accumulate; value: [batch][rows] S = sum_b 2^(8b) P_b formed as the kernel
+ * forms it.  Returns RNS_EVERIFY when a partial leaves int32 or the kernel's
+ * way of combining them would wrap (every output is still written),
+ * RNS_EUNSUPPORTED for a plan on the channel engine.
+ */
+int rns_emul_mfma_extension(const rns_plan *plan, int which, const uint32_t *xi, size_t batch, size_t *rows,
+                            int64_t *partials, int64_t *value);
+
+/*
+ * The constant matrix of one extension of the matrix-core kernel (which as
+ * above), read back from the plan's tables through the matrix cores' operand
+ * layout: A[rows][4][kdim] signed bytes, byte b of slot row r at K index
+ * kappa (4 per input channel digit, then the offset column, then zero
+ * padding).  *rows and *kdim receive the sizes; with A NULL nothing else is
+ * done.  RNS_EUNSUPPORTED for a plan on the channel engine.
+ */
+int rns_emul_mfma_matrix(const rns_plan *plan, int which, size_t *rows, size_t *kdim, int8_t *A);
+
 #ifdef __cplusplus
 }
 #endif

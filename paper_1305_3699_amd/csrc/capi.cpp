@@ -794,6 +794,31 @@ int rns_emul_modexp(const rns_plan *plan, const uint32_t *base, const uint32_t *
     return ok();
 }
 
+int rns_emul_mfma_extension(const rns_plan *plan, int which, const uint32_t *xi, size_t batch, size_t *rows,
+                            int64_t *partials, int64_t *value) {
+    if (!plan || !rows) return fail(RNS_EINVAL, "null plan or rows");
+    if (plan->engine != RNS_ENGINE_MATRIX) return fail(RNS_EUNSUPPORTED, "the plan does not use the matrix engine");
+    if (which != 1 && which != 2) return fail(RNS_EINVAL, "which must be 1 or 2");
+    const MfmaShape &sh = plan->mt.shape;
+    *rows = (size_t)sh.W * 4 * sh.MT;
+    if (batch == 0 || (!partials && !value)) return ok();
+    if (!xi || !partials || !value) return fail(RNS_EINVAL, "null buffer");
+    if (!emul_mfma_extension(plan->mt, which, xi, batch, partials, value))
+        return fail(RNS_EVERIFY, "a byte partial or the kernel's combination of them left its integer range");
+    return ok();
+}
+
+int rns_emul_mfma_matrix(const rns_plan *plan, int which, size_t *rows, size_t *kdim, int8_t *A) {
+    if (!plan || !rows || !kdim) return fail(RNS_EINVAL, "null argument");
+    if (plan->engine != RNS_ENGINE_MATRIX) return fail(RNS_EUNSUPPORTED, "the plan does not use the matrix engine");
+    if (which != 1 && which != 2) return fail(RNS_EINVAL, "which must be 1 or 2");
+    const MfmaShape &sh = plan->mt.shape;
+    *rows = (size_t)sh.W * 4 * sh.MT;
+    *kdim = (size_t)64 * MLayout{sh.K, sh.W, sh.MT, sh.NT}.KSTEPS();
+    if (A) emul_mfma_matrix(plan->mt, which, A);
+    return ok();
+}
+
 int rns_emul_mont_mul(const rns_plan *plan, const uint32_t *x, const uint32_t *y, uint32_t *out, size_t batch) {
     if (!plan) return fail(RNS_EINVAL, "null plan");
     if (batch == 0) return ok();

@@ -6,6 +6,8 @@
 // and K indices 16*(l/16) + byte), independently of how the tables were
 // packed, so a packing mistake shows up here before any GPU run.
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 
 #include "emul.hpp"
 #include "plan_mfma.hpp"
@@ -18,28 +20,30 @@ struct MCtx {
     const MfmaTables &T;
     const MLayout ly;
     int K;
-    std::vector<int64_t> V1, V2;  // [W][4MT][64*KSTEPS] extension constants
+    // [W][4MT][4 bytes][64*KSTEPS]: the A-row byte b of each slot, per K index
+    std::vector<int16_t> A1, A2;
 
     MCtx(const MfmaTables &t) : T(t), ly(t.shape), K(t.shape.K) {
         const int SW = 4 * ly.MT, KK = 64 * ly.KSTEPS();
-        V1.assign((size_t)ly.W * SW * KK, 0);
-        V2.assign((size_t)ly.W * SW * KK, 0);
+        A1.assign((size_t)ly.W * SW * 4 * KK, 0);
+        A2.assign((size_t)ly.W * SW * 4 * KK, 0);
         for (int w = 0; w < ly.W; w++)
             for (int s = 0; s < SW; s++)
-                for (int kap = 0; kap < KK; kap++) {
-                    V1[((size_t)w * SW + s) * KK + kap] = tile_value(T.key.data() + ly.a1(), w, s, kap);
-                    V2[((size_t)w * SW + s) * KK + kap] = tile_value(T.base.data() + ly.a2(), w, s, kap);
-                }
+                for (int b = 0; b < 4; b++)
+                    for (int kap = 0; kap < KK; kap++) {
+                        const size_t at = (((size_t)w * SW + s) * 4 + b) * KK + kap;
+                        A1[at] = tile_byte(T.key.data() + ly.a1(), w, s, b, kap);
+                        A2[at] = tile_byte(T.base.data() + ly.a2(), w, s, b, kap);
+                    }
     }
-    int64_t tile_value(const uint32_t *tiles, int w, int s, int kap) const {
+    // byte b of slot s's constant at K index kap, read through the hardware
+    // operand layout: A row 4g+b of tile mt lives in lane (row + 16 lg), K
+    // index 16 lg + j of the k-step in byte j of that lane's 16 bytes
+    int16_t tile_byte(const uint32_t *tiles, int w, int s, int b, int kap) const {
         const int mt = s / 4, g = s % 4, ks = kap / 64, k = kap % 64, lg = k / 16, j = k % 16;
-        int64_t v = 0;
-        for (int b = 0; b < 4; b++) {
-            const int lane = 16 * lg + 4 * g + b;  // A row 4g+b lives in lane (row + 16*lg)
-            const uint32_t word = tiles[((((size_t)w * ly.MT + mt) * ly.KSTEPS() + ks) * 64 + lane) * 4 + j / 4];
-            v += (int64_t)(int8_t)(word >> (8 * (j % 4))) * ((int64_t)1 << (8 * b));
-        }
-        return v;
+        const int lane = 16 * lg + 4 * g + b;
+        const uint32_t word = tiles[((((size_t)w * ly.MT + mt) * ly.KSTEPS() + ks) * 64 + lane) * 4 + j / 4];
+        return (int16_t)(int8_t)(word >> (8 * (j % 4)));
     }
     // per-lane constant of slot s in wave w: any lane of group s%4
     uint32_t slot(size_t off, size_t fields, int field, int w, int s) const {
@@ -74,14 +78,40 @@ uint32_t reduce_offset(uint64_t P, int64_t S, uint32_t m, uint32_t u, int sh) {
     return redc((uint32_t)x, (uint32_t)(x >> 32), m, u);
 }
 
-// sum over K indices of V * digit, digits from the packed rows of element e
-int64_t extension(const std::vector<int64_t> &V, size_t vrow, const std::vector<uint32_t> &dig, int e, int KK, int BROW) {
-    int64_t s = 0;
-    for (int kap = 0; kap < KK; kap++) {
-        const uint32_t word = dig[(size_t)e * BROW + kap / 4];
-        s += V[vrow + kap] * (int64_t)(int8_t)(word >> (8 * (kap % 4)));
+// The four byte partials P_b of slot row `row` ([W][4MT] index) for element
+// e: exact sums over K indices of A byte times digit byte, the int32 values
+// the matrix core accumulates (the host checks they fit).
+void partials(const std::vector<int16_t> &A, size_t row, const std::vector<uint32_t> &dig, int e, int KK, int BROW,
+              int64_t P[4]) {
+    for (int b = 0; b < 4; b++) {
+        const int16_t *a = A.data() + (row * 4 + b) * KK;
+        int64_t s = 0;
+        for (int kap = 0; kap < KK; kap++) {
+            const uint32_t word = dig[(size_t)e * BROW + kap / 4];
+            s += (int64_t)a[kap] * (int8_t)(word >> (8 * (kap % 4)));
+        }
+        if (s < INT32_MIN || s > INT32_MAX) t_in_range = false;
+        P[b] = s;
     }
-    return s;
+}
+
+// S = sum_b 2^(8b) P_b as the kernel forms it: up to 127 channels the pairs
+// P_0 + 2^8 P_1 and P_2 + 2^8 P_3 in int32 (a wrap there would change S by a
+// multiple of 2^32 and is flagged), wider bases every partial in 64 bits.
+int64_t combine(const int64_t P[4], int K) {
+    if (mfma_pair_fits_i32(K)) {
+        const int64_t t1 = P[0] + 256 * P[1], t2 = P[2] + 256 * P[3];
+        if (t1 < INT32_MIN || t1 > INT32_MAX || t2 < INT32_MIN || t2 > INT32_MAX) t_in_range = false;
+        return (int64_t)(int32_t)(uint32_t)t1 + (int64_t)(int32_t)(uint32_t)t2 * 65536;
+    }
+    return P[0] + 256 * P[1] + 65536 * P[2] + 16777216 * P[3];
+}
+
+int64_t extension(const std::vector<int16_t> &A, size_t row, const std::vector<uint32_t> &dig, int e, int KK, int BROW,
+                  int K) {
+    int64_t P[4];
+    partials(A, row, dig, e, KK, BROW, P);
+    return combine(P, K);
 }
 
 // One product x <- x*y*M^-1 for the NM elements of one workgroup; fills dig2
@@ -105,7 +135,7 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
     std::vector<uint32_t> rr(NM);
     for (int e = 0; e < NM; e++) {
         // every wave carries the same redundant row; take wave 0's
-        const int64_t S = extension(c.V1, ((size_t)0 * SW + SW - 1) * KK, dig1, e, KK, BROW);
+        const int64_t S = extension(c.A1, (size_t)0 * SW + SW - 1, dig1, e, KK, BROW, c.K);
         rr[e] = (x.r[e] * y.r[e] + (uint32_t)S * N_r) * Minv_r;
     }
     for (int w = 0; w < ly.W; w++)
@@ -113,7 +143,7 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
             const uint32_t m = c.slot(ly.slotP(), 4, 0, w, s), u = c.slot(ly.slotP(), 4, 1, w, s);
             const uint32_t H = c.slot(ly.slotP(), 4, 2, w, s);
             for (int e = 0; e < NM; e++) {
-                const int64_t S = extension(c.V1, ((size_t)w * SW + s) * KK, dig1, e, KK, BROW);
+                const int64_t S = extension(c.A1, (size_t)w * SW + s, dig1, e, KK, BROW, c.K);
                 // x' y' + S + m 2^sh in one REDC
                 const uint32_t r = reduce_offset((uint64_t)x.p[idx(w, s, e)] * y.p[idx(w, s, e)], S, m, u, sh);
                 x.p[idx(w, s, e)] = r;
@@ -125,14 +155,14 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
     for (int w = 0; w < ly.W; w++) {
         std::vector<uint32_t> alpha(NM);
         for (int e = 0; e < NM; e++) {
-            const int64_t S = extension(c.V2, ((size_t)w * SW + SW - 1) * KK, dig2, e, KK, BROW);
+            const int64_t S = extension(c.A2, (size_t)w * SW + SW - 1, dig2, e, KK, BROW, c.K);
             alpha[e] = ((uint32_t)S - rr[e]) * Mpinv_r;
         }
         for (int s = 0; s < SW; s++) {
             const uint32_t m = c.slot(ly.slotB(), 3, 0, w, s), u = c.slot(ly.slotB(), 3, 1, w, s);
             const uint32_t nu = c.slot(ly.slotB(), 3, 2, w, s);
             for (int e = 0; e < NM; e++) {
-                const int64_t S = extension(c.V2, ((size_t)w * SW + s) * KK, dig2, e, KK, BROW);
+                const int64_t S = extension(c.A2, (size_t)w * SW + s, dig2, e, KK, BROW, c.K);
                 x.b[idx(w, s, e)] = reduce_offset((uint64_t)alpha[e] * nu, S, m, u, sh);
             }
         }
@@ -328,6 +358,32 @@ bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
         }
     }
     return t_in_range;
+}
+
+bool emul_mfma_extension(const MfmaTables &T, int which, const uint32_t *xi, size_t batch, int64_t *parts,
+                         int64_t *value) {
+    t_in_range = true;
+    const MCtx c(T);
+    const MLayout &ly = c.ly;
+    const int K = c.K, SW = 4 * ly.MT, BROW = ly.BROW(), KK = 64 * ly.KSTEPS(), rows = ly.W * SW;
+    std::vector<uint32_t> dig((size_t)BROW, 0);
+    dig[K] = 1;
+    for (size_t e = 0; e < batch; e++) {
+        for (int i = 0; i < K; i++) dig[i] = pack_digits(xi[e * K + i]);
+        for (int r = 0; r < rows; r++) {
+            int64_t P[4];
+            partials(which == 1 ? c.A1 : c.A2, (size_t)r, dig, 0, KK, BROW, P);
+            for (int b = 0; b < 4; b++) parts[(e * rows + r) * 4 + b] = P[b];
+            value[e * rows + r] = combine(P, K);
+        }
+    }
+    return t_in_range;
+}
+
+void emul_mfma_matrix(const MfmaTables &T, int which, int8_t *A) {
+    const MCtx c(T);
+    const std::vector<int16_t> &src = which == 1 ? c.A1 : c.A2;
+    for (size_t i = 0; i < src.size(); i++) A[i] = (int8_t)src[i];
 }
 
 }  // namespace rnsrsa

@@ -37,6 +37,7 @@ struct MShp {
     static constexpr int SLOTS = LY.SLOTS();
     static constexpr int ECOLS = (int)LY.ecols();
     static constexpr int OSH = mfma_offset_shift(K);   // REDC offset m 2^OSH of steps (iii) and (iv)
+    static constexpr bool PAIR_I32 = mfma_pair_fits_i32(K);   // byte partials paired in int32 (K <= 127)
     // smallest b with 2^b > K+1: an exit value below (K+2)N has quotient < 2^b
     static constexpr int qbits() {
         int b = 0;
@@ -111,7 +112,7 @@ struct MConst {
     uint32_t mP[MT], uP[MT], HP[MT];
     const uint32_t *cl;      // CL: this lane group's constants in LDS, tile mt at cl + 32 mt
     uint32_t Mpinv_r, Minv_r, N_r;
-    int32_t k16, k1;         // 2^16 and 1, opaque to the compiler (see mfma_accumulate)
+    int32_t kf[4];           // 1, 2^8, 2^16, 2^24, opaque to the compiler (see mfma_accumulate)
 
     __device__ __forceinline__ MSlotB slotB(int mt) const {
         if (CL) {
@@ -143,18 +144,27 @@ __device__ __forceinline__ uint32_t mfma_combine_lo(const mfma_v4i &d) {
     return t1 + (t2 << 16);
 }
 
-// acc + the signed value S of the four byte partials, mod 2^64.  |S| is at
-// most mfma_sum_bound(K): 4K+1 terms of |A byte value| <= 0x80808080 times
-// |digit byte| <= 128.  Callers add m 2^OSH > |S| so that the REDC input is
-// positive (the host checks every channel prime).  The factors
-// k16 = 2^16 and k1 = 1 come from scalar registers the compiler cannot see
-// through, so each step is one signed 32x32+64 multiply-add instead of a
-// sign extension, a 64-bit shift and a 64-bit add.
-__device__ __forceinline__ uint64_t mfma_accumulate(const mfma_v4i &d, uint64_t acc, int32_t k16, int32_t k1) {
-    const int32_t t1 = d[0] + (d[1] << 8);
-    const int32_t t2 = d[2] + (d[3] << 8);
-    acc += (uint64_t)((int64_t)t2 * k16);
-    acc += (uint64_t)((int64_t)t1 * k1);
+// acc + the signed value S = sum_b 2^(8b) P_b of the four byte partials, mod
+// 2^64.  |S| is at most mfma_sum_bound(K): 4K+1 terms of |A byte value| <=
+// 0x80808080 times |digit byte| <= 128.  Callers add m 2^OSH > |S| so that
+// the REDC input is positive (the host checks every channel prime).  The
+// factors (1, 2^8, 2^16, 2^24) come from scalar registers the compiler cannot
+// see through, so each step is one signed 32x32+64 multiply-add instead of a
+// sign extension, a 64-bit shift and a 64-bit add.  Up to 127 channels the
+// pairs P_0 + 2^8 P_1 and P_2 + 2^8 P_3 are formed in int32 first (exact:
+// mfma_pair_fits_i32); wider bases could overflow there and take each
+// partial into the 64-bit sum on its own.
+template <bool PAIR_I32>
+__device__ __forceinline__ uint64_t mfma_accumulate(const mfma_v4i &d, uint64_t acc, const int32_t (&kf)[4]) {
+    if constexpr (PAIR_I32) {
+        const int32_t t1 = d[0] + (d[1] << 8);
+        const int32_t t2 = d[2] + (d[3] << 8);
+        acc += (uint64_t)((int64_t)t2 * kf[2]);
+        acc += (uint64_t)((int64_t)t1 * kf[0]);
+    } else {
+#pragma unroll
+        for (int b = 3; b >= 0; b--) acc += (uint64_t)((int64_t)d[b] * kf[b]);
+    }
     return acc;
 }
 
@@ -274,8 +284,8 @@ __device__ __forceinline__ void mfma_mm(const MConstOf<K, W, MT, NT> &C, MState<
             const uint32_t m = sp.m;
             // x' y' + S in one REDC (S + m 2^OSH > 0; the sum stays below
             // m 2^32 for every B' prime that mfma_prime_fits accepts)
-            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)x.p[mt][nt] * y.p[mt][nt] + ((uint64_t)m << S::OSH),
-                                               C.k16, C.k1);
+            const uint64_t T = mfma_accumulate<S::PAIR_I32>(
+                D[mt][nt], (uint64_t)x.p[mt][nt] * y.p[mt][nt] + ((uint64_t)m << S::OSH), C.kf);
             const uint32_t r = redc((uint32_t)T, (uint32_t)(T >> 32), m, sp.u);
             x.p[mt][nt] = r;
             const uint32_t xip = mulredc(r, sp.H, m, sp.u);                            // r (M'_t)^-1
@@ -302,8 +312,8 @@ __device__ __forceinline__ void mfma_mm(const MConstOf<K, W, MT, NT> &C, MState<
         for (int nt = 0; nt < NT; nt++) {
             // S + alpha nu + m 2^OSH (alpha nu < 2^42): positive, below m 2^32
             const MSlotB sb = C.slotB(mt);
-            const uint64_t T = mfma_accumulate(D[mt][nt], (uint64_t)alpha[nt] * sb.nu + ((uint64_t)sb.m << S::OSH),
-                                               C.k16, C.k1);
+            const uint64_t T = mfma_accumulate<S::PAIR_I32>(
+                D[mt][nt], (uint64_t)alpha[nt] * sb.nu + ((uint64_t)sb.m << S::OSH), C.kf);
             x.b[mt][nt] = redc((uint32_t)T, (uint32_t)(T >> 32), sb.m, sb.u);
         }
 }
@@ -514,9 +524,11 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     C.Mpinv_r = mb[S::LY.bscal() + 0];
     C.Minv_r = mb[S::LY.bscal() + 1];
     C.N_r = mk[S::LY.kscal() + 0];
-    C.k16 = 1 << 16;
-    C.k1 = 1;
-    asm volatile("" : "+s"(C.k16), "+s"(C.k1));
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        C.kf[b] = 1 << (8 * b);
+        asm volatile("" : "+s"(C.kf[b]));
+    }
 
     // entry: residues of Z = sum_h X_h Y_h in the kept representation
     MState<MT, NT> a;

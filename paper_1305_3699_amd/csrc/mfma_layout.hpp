@@ -30,6 +30,16 @@ constexpr uint32_t kMaxPrimeP = 0xFFFC0000u;
 // byte of magnitude <= 128, plus the offset column (digit 1).
 constexpr uint64_t mfma_sum_bound(int K) { return (uint64_t)4 * K * 0x80808080ull * 128u + 0x80808080ull; }
 
+// Bound on one byte partial P_b of an extension output (the int32 the matrix
+// core returns): 4K digit bytes times constant bytes, each of magnitude <= 128,
+// plus the offset column (constant byte times digit 1).
+constexpr int64_t mfma_partial_bound(int K) { return (int64_t)4 * K * 128 * 128 + 128; }
+
+// Whether the pairwise combination P_0 + 2^8 P_1 (and P_2 + 2^8 P_3) of the
+// four byte partials stays inside int32 for every input: 257 times the
+// partial bound below 2^31, i.e. K <= 127.  Wider bases combine in 64 bits.
+constexpr bool mfma_pair_fits_i32(int K) { return 257 * mfma_partial_bound(K) < ((int64_t)1 << 31); }
+
 // Steps (iii) and (iv) add m 2^s to S so that the REDC input is positive:
 // s = 17 up to 256 + 1 channels (|S| about 2^48), 18 beyond (about 2^49).
 constexpr int mfma_offset_shift(int K) { return K > 257 ? 18 : 17; }

@@ -118,6 +118,8 @@ _SIGNATURES = {
     "rns_plan_primes": ([_P, _P, _S], _I),
     "rns_emul_modexp": ([_P, _P, _P, _S, _S, _P, _S], _I),
     "rns_emul_mont_mul": ([_P, _P, _P, _P, _S], _I),
+    "rns_emul_mfma_extension": ([_P, _I, _P, _S, _P, _P, _P], _I),
+    "rns_emul_mfma_matrix": ([_P, _I, _P, _P, _P], _I),
 }
 
 _lib_handle = None
@@ -464,6 +466,31 @@ class Plan:
         out = np.zeros((B, self.L), dtype=np.uint32)
         _check(lib().rns_emul_modexp(self._h, _host_ptr(base), _host_ptr(exp), E, stride, _host_ptr(out), B))
         return out
+
+    def emul_mfma_extension(self, which: int, xi: np.ndarray):
+        """rns_emul_mfma_extension on raw digits xi [B, k]: returns (status,
+        partials [B, rows, 4] int64, value [B, rows] int64)."""
+        xi = np.ascontiguousarray(xi, dtype=np.uint32)
+        if xi.ndim != 2 or xi.shape[1] != self.info["k"]:
+            raise ValueError("xi must be [B, %d]" % self.info["k"])
+        B = xi.shape[0]
+        rows = ctypes.c_size_t(0)
+        _check(lib().rns_emul_mfma_extension(self._h, int(which), None, 0, ctypes.byref(rows), None, None))
+        parts = np.zeros((B, rows.value, 4), dtype=np.int64)
+        value = np.zeros((B, rows.value), dtype=np.int64)
+        rc = lib().rns_emul_mfma_extension(self._h, int(which), _host_ptr(xi), B, ctypes.byref(rows),
+                                           _host_ptr(parts), _host_ptr(value))
+        if rc not in (0, -6):
+            _check(rc)
+        return rc, parts, value
+
+    def emul_mfma_matrix(self, which: int) -> np.ndarray:
+        """rns_emul_mfma_matrix: int8 [rows, 4, kdim] constant bytes."""
+        rows, kd = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(lib().rns_emul_mfma_matrix(self._h, int(which), ctypes.byref(rows), ctypes.byref(kd), None))
+        A = np.zeros((rows.value, 4, kd.value), dtype=np.int8)
+        _check(lib().rns_emul_mfma_matrix(self._h, int(which), ctypes.byref(rows), ctypes.byref(kd), _host_ptr(A)))
+        return A
 
     def emul_mont_mul(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.uint32)

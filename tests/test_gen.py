@@ -65,3 +65,33 @@ def test_mixed_batch_spec():
     total = sum(o.count for o in ops)
     assert 0.4 < n_dec / total < 0.6
     assert gen.mixed_batch_spec() == (keys, ops)           # deterministic
+
+
+def test_stored_keys_are_the_seeded_draws():
+    """gen/keys.json holds the draws of gen/make_keys.py: a sample of its
+    entries (all sizes of the mixed and served workloads) equals a fresh draw
+    from the seeded generator, and every entry is an RSA key of its size."""
+    import random
+
+    cache = gen._key_cache()
+    specs = [tuple(map(int, s.split(":"))) for s in cache]
+    from gen.make_keys import standard_specs
+    assert sorted(specs) == standard_specs()
+    for bits, seed in random.Random(1).sample(sorted(s for s in specs if s[0] <= 2048), 6):
+        assert gen.rsa_key(bits, seed) == gen._generate_key(bits, seed)
+    for bits, seed in specs:
+        k = gen.rsa_key(bits, seed)
+        assert k.n.bit_length() == bits and k.p.bit_length() == k.q.bit_length() == bits // 2
+        assert pow(3, k.p - 1, k.p) == 1 and pow(3, k.q - 1, k.q) == 1
+
+
+def test_rsa_keys_refuses_to_fork_a_gpu_process(monkeypatch):
+    """A process pool would fork the calling process: refused once the GPU is
+    in use (keys missing from gen/keys.json); stored keys need no pool."""
+    import pytest
+
+    monkeypatch.setattr(gen, "_gpu_in_use", lambda: True)
+    with pytest.raises(RuntimeError):
+        gen.rsa_keys([(512, 11), (512, 12)], processes=4)
+    specs, _ = gen.mixed_batch_spec()
+    assert len(gen.rsa_keys(specs[:4], processes=4)) == 4

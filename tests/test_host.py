@@ -297,6 +297,51 @@ def test_matrix_engine_sum_bound():
         assert all((m - 1) ** 2 + (m << s) + smax(k) < m << 32 for m in pr[k:])
 
 
+def _aligned_digits(a_row: np.ndarray) -> np.ndarray:
+    """Digit words whose signed digit bytes take the sign of a_row (one A
+    row's bytes over the 4k digit positions): +127 where the constant byte is
+    positive, -128 elsewhere, the largest |sum| any digits reach."""
+    d = np.where(a_row > 0, 127, -128).astype(np.int64)
+    by = ((d & 0xFF) ^ 0x80).astype(np.uint32).reshape(-1, 4)
+    return by[:, 0] | (by[:, 1] << 8) | (by[:, 2] << 16) | (by[:, 3] << 24)
+
+
+@pytest.mark.parametrize("bits", [2048, 4096, 8192, 16384])
+def test_matrix_extension_extreme_digits(bits):
+    """Byte partials of the matrix cores' extensions under digits aligned to
+    the signs of a constant row (the largest sums any digits give).  Each
+    partial P_b is an int32 sum; the kernel pairs P_0 + 2^8 P_1 in int32 only
+    up to 127 channels, where the extreme still fits, and combines every
+    partial in 64 bits for the wider bases (k = 129, 257, 513), where the
+    pairing would wrap.  S as the model forms it must equal the exact
+    sum_b 2^(8b) P_b computed here from the constant bytes."""
+    rng = random.Random(bits + 7)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    pl = Plan(N, bits // 32)
+    k = pl.info["k"]
+    assert pl.info["engine"] == rnsrsa.ENGINE_MATRIX
+    for which in (1, 2):
+        A = pl.emul_mfma_matrix(which).astype(np.int64)        # [rows, 4, kdim]
+        rows = A.shape[0]
+        # the row with the largest possible pair P_0 + 2^8 P_1
+        r = int(np.argmax(np.abs(A[:, 0, :4 * k]).sum(1) + 256 * np.abs(A[:, 1, :4 * k]).sum(1)))
+        dig = _aligned_digits(A[r, 1, :4 * k])[None, :]          # aligned to byte 1, the pair's heavy term
+        rc, parts, value = pl.emul_mfma_extension(which, dig)
+        db = ((np.frombuffer(dig.astype("<u4").tobytes(), dtype=np.uint8).astype(np.int64) ^ 0x80) + 128) % 256 - 128
+        dvec = np.concatenate([db, [1], np.zeros(A.shape[2] - 4 * k - 1, np.int64)])
+        exact_p = A @ dvec                                       # [rows, 4]
+        assert np.array_equal(parts[0], exact_p)
+        assert np.all(np.abs(exact_p) < 2 ** 31)
+        exact_s = exact_p @ np.array([1, 1 << 8, 1 << 16, 1 << 24], np.int64)
+        assert rc == 0 and np.array_equal(value[0], exact_s)
+        pair = exact_p[r, 0] + 256 * exact_p[r, 1]
+        if k <= 127:
+            assert abs(pair) < 2 ** 31
+        elif k >= 257:
+            assert abs(pair) >= 2 ** 31, "the crafted digits reach the int32 limit of the pairing"
+        assert rows == pl.info["waves"] * 4 * ((rows // pl.info["waves"]) // 4)
+
+
 def test_modexp_jobs_argument_errors():
     """rns_modexp_jobs validates every job before touching the device: no
     jobs is a no-op, a null job array or a job without a context is

@@ -176,7 +176,23 @@ def ingest_counters(fetch_csv: str, write_csv: str, calib_mb: int) -> dict:
     return out
 
 
-def run(args) -> dict:
+def draw_keys(args) -> dict:
+    """Every key of the run, drawn before the first GPU call (the mixed and
+    served workloads' keys come from gen/keys.json; a process that has used
+    the GPU must not fork a key-generation pool)."""
+    import gen
+    keys = {"c2": gen.rsa_key(2048, seed=gen.config_seed(2, 1))}
+    if args.mixed_steps > 0:
+        specs, ops = gen.mixed_batch_spec()
+        keys["c4"] = (gen.rsa_keys(specs), ops)
+    if args.served_default or args.served:
+        keys["c5"] = gen.rsa_keys(gen.served_keys(per_size=64))
+    return keys
+
+
+def run(args, key, ref=None) -> dict:
+    """The timed step on the C2 workload.  ref: the oracle's outputs for the
+    batch, if already computed (then compared with, not timed again)."""
     import numpy as np
     import torch
 
@@ -186,7 +202,6 @@ def run(args) -> dict:
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs the GPU")
     torch.cuda.set_device(0)
-    key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
     opts = {"window": args.window, "engine": args.engine, "group": args.group}
     if args.waves:
         opts.update(k=33, waves=args.waves)
@@ -303,15 +318,18 @@ def run(args) -> dict:
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    got_all = m.cpu().numpy().view(np.uint32)
+    if ref is not None:
+        out["matches_oracle"] = bool(np.array_equal(ref, got_all))
     if args.cpu_sample > 0:
         import oracle
         ns = min(args.cpu_sample, B)
         threads = cpu_threads()
         sample = c_np[:ns]
         t2 = time.perf_counter()
-        ref = oracle.rsa_crt_batch(sample, key.p, key.q, key.dp, key.dq, key.qinv, nthreads=threads)
+        ref_s = oracle.rsa_crt_batch(sample, key.p, key.q, key.dp, key.dq, key.qinv, nthreads=threads)
         t3 = time.perf_counter()
-        got = m.cpu().numpy().view(np.uint32)[:ns]
+        got = got_all[:ns]
         out["cpu_baseline"] = {
             "value": round(ns / (t3 - t2), 2),
             "unit": "decrypts/s",
@@ -319,8 +337,10 @@ def run(args) -> dict:
             "kind": "oracle",
             "sample": "first %d of the %d ciphertexts, the oracle's schoolbook CRT/Garner path, %.1f s wall"
                       % (ns, B, t3 - t2),
-            "matches_gpu": bool(np.array_equal(ref, got)),
+            "matches_gpu": bool(np.array_equal(ref_s, got)),
         }
+        if ns == B:
+            ref = ref_s
         # the correctness definition itself, c^d mod n, on a bounded sample
         npl = min(max(ns // 16, 1), B)
         t4 = time.perf_counter()
@@ -332,34 +352,36 @@ def run(args) -> dict:
             "sample": "first %d ciphertexts, the oracle's c^d mod n (schoolbook, no CRT), %.1f s wall" % (npl, t5 - t4),
             "matches_gpu": bool(np.array_equal(refp, got[:npl])),
         }
-    return out
+    return out, ref
 
 
-def run_mixed(args) -> dict:
+def run_mixed(args, keys, ops) -> dict:
     """Batched vs plain on the mixed-size workload: 64 seeded keys over
     1024/2048/3072/4096 bits, lognormal per-key counts (median 128), half
     encryptions and half CRT decryptions.  plain = one rsa_encrypt /
     rsa_decrypt call per (key, op) in sequence on one stream; batched = one
-    RsaBatch run (one grouped launch per kernel shape, hipGraph)."""
+    RsaBatch run (one grouped launch per kernel shape, hipGraph).  After the
+    timed runs every batched output is compared with the oracle (all host
+    threads, outside the timed region)."""
     import numpy as np
     import torch
 
     import gen
+    import oracle
     from paper_1305_3699_amd import OP_DECRYPT, OP_ENCRYPT, RsaBatch, RsaKey
 
-    specs, ops = gen.mixed_batch_spec()
-    keys = gen.rsa_keys(specs, processes=cpu_threads())
     rks = [RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv) for k in keys]
     items = []
     for o in ops:
         k = keys[o.key_index]
         vals = gen.uniform_below(k.n, o.count, seed=o.msg_seed)
-        inp = torch.from_numpy(gen.to_limbs(vals, o.bits // 32).view(np.int32)).cuda()
-        items.append((o, rks[o.key_index], inp, torch.empty_like(inp), torch.empty_like(inp)))
+        xl = gen.to_limbs(vals, o.bits // 32)
+        inp = torch.from_numpy(xl.view(np.int32)).cuda()
+        items.append((o, rks[o.key_index], inp, torch.empty_like(inp), torch.empty_like(inp), xl))
     n_ops = sum(o.count for o in ops)
 
     def plain_run():
-        for o, rk, inp, out_p, _ in items:
+        for o, rk, inp, out_p, _, _ in items:
             if o.kind == "encrypt":
                 rk.encrypt(inp, out=out_p)
             else:
@@ -367,7 +389,7 @@ def run_mixed(args) -> dict:
 
     t0 = time.perf_counter()
     batch = RsaBatch([(rk, OP_ENCRYPT if o.kind == "encrypt" else OP_DECRYPT, inp, out_b)
-                      for o, rk, inp, _, out_b in items], autotune=True, use_graph=True)
+                      for o, rk, inp, _, out_b, _ in items], autotune=True, use_graph=True)
     create_s = time.perf_counter() - t0
     res = {}
     for name, fn in (("plain", plain_run), ("batched", batch.run)):
@@ -385,9 +407,22 @@ def run_mixed(args) -> dict:
         ms.sort()
         res[name] = {"ops_per_s": round(n_ops / (statistics.mean(ms) / 1e3), 1),
                      "ms_p50": round(statistics.median(ms), 3), "ms_p99": round(ms[-1], 3)}
-    same = all(torch.equal(out_p, out_b) for _, _, _, out_p, out_b in items)
+    same = all(torch.equal(out_p, out_b) for _, _, _, out_p, out_b, _ in items)
     info = batch.info
     batch.close()
+    threads = cpu_threads()
+    t0 = time.perf_counter()
+    matches = True
+    for o, rk, inp, _, out_b, xl in items:
+        k = keys[o.key_index]
+        got = out_b.cpu().numpy().view(np.uint32)
+        if o.kind == "encrypt":
+            want = oracle.modexp_batch(xl, gen.to_limbs(k.e, 1)[0], gen.to_limbs(k.n, o.bits // 32)[0],
+                                       nthreads=threads)
+        else:
+            want = oracle.rsa_crt_batch(xl, k.p, k.q, k.dp, k.dq, k.qinv, nthreads=threads)
+        matches = matches and bool(np.array_equal(got, want))
+    oracle_s = time.perf_counter() - t0
     return {
         "workload": "64 keys (16 each of 1024/2048/3072/4096 bits), per-key counts lognormal(median 128, "
                     "sigma 1, cap 8192), each message encrypt or CRT-decrypt with p = 0.5",
@@ -397,6 +432,8 @@ def run_mixed(args) -> dict:
         "batched": res["batched"],
         "speedup": round(res["batched"]["ops_per_s"] / res["plain"]["ops_per_s"], 2),
         "batched_matches_plain": bool(same),
+        "matches_oracle": matches,
+        "oracle_check": "every output of the batched run vs the oracle (%d host threads, %.1f s)" % (threads, oracle_s),
         "launches_per_run": {"batched": info["launches"] + info["garner_launches"],
                              "plain": len(items) + sum(1 for o in ops if o.kind == "decrypt")},
         "graph": True,
@@ -405,7 +442,7 @@ def run_mixed(args) -> dict:
     }
 
 
-def run_served(args) -> dict:
+def run_served(args, keys) -> dict:
     """Served form: 256 resident keys (64 each of 2048/1024/3072/4096 bits),
     open-loop Poisson arrivals at each rate for warm-up + duration seconds,
     key size 40/30/20/10%, 70% CRT decryptions, 64 GiB admission budget.
@@ -419,13 +456,9 @@ def run_served(args) -> dict:
     from paper_1305_3699_amd import RsaKey, RsaServer
 
     per = 64
-    specs = gen.served_keys(per_size=per)
-    t0 = time.perf_counter()
-    keys = gen.rsa_keys(specs, processes=cpu_threads())
-    keygen_s = time.perf_counter() - t0
     rks = [RsaKey(k.n, k.e, k.d, k.p, k.q, k.dp, k.dq, k.qinv) for k in keys]
     limbs = [k.n.bit_length() // 32 for k in keys]
-    out = {"keys": len(keys), "keygen_s": round(keygen_s, 1), "budget_gib": 64,
+    out = {"keys": len(keys), "budget_gib": 64,
            "max_inflight": args.served_inflight, "warmup_s": args.served_warmup,
            "duration_s": args.served_duration, "runs": []}
     for rate in args.served_rates:
@@ -782,7 +815,10 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-sample", type=int, default=16384, help="ciphertexts for the oracle baseline (0: skip)")
     ap.add_argument("--sweep-window", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=5, help="timed runs of the batched-vs-plain mix (0: skip)")
-    ap.add_argument("--served", action="store_true", help="also run the served workload (about 2 minutes)")
+    ap.add_argument("--served", action="store_true",
+                    help="also run the full served sweep (5k/20k/80k req/s, 10 s each; about 2 minutes)")
+    ap.add_argument("--no-served-leg", action="store_true",
+                    help="skip the short served leg of the default run (80k req/s for 2 s)")
     ap.add_argument("--modmul-sweep", action="store_true",
                     help="only the 3072-bit modular multiplication sweep (one JSON line per base size)")
     ap.add_argument("--modmul-batches", type=int, nargs="+",
@@ -832,17 +868,41 @@ def main(argv=None) -> int:
         for line in run_tile_sweep(args):
             print(json.dumps(line), flush=True)
         return 0
+    args.served_default = not args.no_served_leg and not args.sweep_window
     if args.sweep_window:
+        args.mixed_steps = 0
+    keys = draw_keys(args)
+    if args.sweep_window:
+        # the oracle runs once on the whole batch; every window's outputs are
+        # compared with it
+        ref = None
         for w in range(1, 7):
             args.window = w
-            r = run(argparse.Namespace(**{**vars(args), "cpu_sample": 0, "mixed_steps": 0}))
+            r, got_ref = run(argparse.Namespace(**{**vars(args), "cpu_sample": 0 if ref is not None else args.batch,
+                                                   "mixed_steps": 0}), keys["c2"], ref)
+            if ref is None:
+                ref = got_ref
+                r["matches_oracle"] = bool(r["cpu_baseline"] and r["cpu_baseline"]["matches_gpu"])
             print(json.dumps(r), flush=True)
         return 0
-    out = run(args)
+    out, _ = run(args, keys["c2"])
     if args.mixed_steps > 0:
-        out["batched_vs_plain"] = run_mixed(args)
+        out["batched_vs_plain"] = run_mixed(args, *keys["c4"])
+    if args.served_default:
+        leg = argparse.Namespace(**{**vars(args), "served_rates": [80000.0], "served_duration": 2.0,
+                                    "served_warmup": 0.5, "served_max_ops": [0]})
+        sv = run_served(leg, keys["c5"])
+        r = sv["runs"][0]
+        out["served"] = {"what": "request loop over 256 resident keys (64 each of 2048/1024/3072/4096 bits), "
+                                 "Poisson arrivals, 40/30/20/10%% key sizes, 70%% CRT decryptions, 64 GiB "
+                                 "budget, %d slots; latency = completion - arrival (host clock), requests of "
+                                 "the 0.5 s warm-up excluded" % args.served_inflight,
+                         "offered_req_per_s": r["offered_req_per_s"], "duration_s": 2.0,
+                         "completed_per_s": r["completed_per_s"], "latency_ms": r["latency_ms"],
+                         "requests": r["requests"], "dispatches": r["dispatches"],
+                         "sample_matches_oracle": r["sample_matches_oracle"]}
     if args.served:
-        out["served"] = run_served(args)
+        out["served_sweep"] = run_served(args, keys["c5"])
     print(json.dumps(out), flush=True)
     return 0
 

@@ -45,13 +45,15 @@ extern "C" {
 enum rns_status {
     RNS_OK = 0,
     RNS_EINVAL = -1,        /* bad argument (null pointer, bad size, bad option) */
-    RNS_ERANGE = -2,        /* modulus < 2, or too large for any supported base */
+    RNS_ERANGE = -2,        /* modulus < 2, or too large for any supported base; an RSA input not
+                               below n (rsa_key_status, rsa_server_replay) */
     RNS_EFACTOR = -3,       /* a channel prime of an explicit base divides N */
     RNS_ENOMEM = -4,        /* host or device allocation failed */
     RNS_EDEVICE = -5,       /* HIP runtime error */
     RNS_EVERIFY = -6,       /* a result failed its self-check (key generation's d e = 1 mod f;
                                the host model's one-step reduction range check) */
-    RNS_EBUSY = -7,         /* reserved: admission budget exhausted */
+    RNS_EBUSY = -7,         /* the request server's admission limits refuse a request (device-memory
+                               budget below one request, or the pending queue full) */
     RNS_EUNSUPPORTED = -8   /* no kernel is built for the requested shape */
 };
 
@@ -136,7 +138,7 @@ typedef struct rsa_key rsa_key;
  * is valid until the next library call on this thread. */
 const char *rns_last_error(void);
 
-/* ABI version of this header (currently 3). */
+/* ABI version of this header (currently 4). */
 int rns_abi_version(void);
 
 /*
@@ -247,8 +249,11 @@ void rsa_key_free(rsa_key *key);
 int rsa_key_info(const rsa_key *key, int which /* 0 n, 1 p, 2 q */, rns_info *info);
 
 /*
- * rsa_encrypt -- c[i] = m[i]^e mod n (Sec. 3.3).  m, c: device, batch x n_limbs;
- * inputs should be below n (raw RSA on integers; larger values are reduced).
+ * rsa_encrypt -- c[i] = m[i]^e mod n (Sec. 3.3).  m, c: device, batch x n_limbs.
+ * Raw RSA works on integers below n: an input >= n is still reduced mod n and
+ * exponentiated, and it is counted on the device in the key's status word
+ * (rsa_key_status reports RNS_ERANGE).  The same holds for the inputs of
+ * rsa_decrypt, rsa_crt_halves and the batched form.
  */
 int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch, void *hip_stream);
 
@@ -261,6 +266,17 @@ int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch
  */
 int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch, int use_crt,
                 void *hip_stream);
+
+/*
+ * rsa_key_status -- the input range status of a key (Sec. 3.3: raw RSA on
+ * integers below n).  Synchronises hip_stream, then reads and clears the
+ * key's device count of inputs >= n enqueued by rsa_encrypt, rsa_decrypt,
+ * rsa_crt_halves and rsa_batch_run on this key since the last read (work on
+ * other streams is counted once it has run).  *n_out_of_range (optional,
+ * host) receives that count.  Returns RNS_OK when it is zero, RNS_ERANGE
+ * otherwise; RNS_EINVAL for a null key, RNS_EDEVICE.
+ */
+int rsa_key_status(const rsa_key *key, size_t *n_out_of_range, void *hip_stream);
 
 /*
  * The two launches of a CRT decryption, exposed separately (rsa_decrypt with
@@ -388,7 +404,9 @@ void rsa_batch_free(rsa_batch *b);
  *   rsa_server_opts  hbm_budget: device bytes in-flight dispatches may hold
  *                    (0 = 64 GiB); max_inflight: concurrent dispatches
  *                    (0 = 8); max_dispatch_ops: requests per dispatch
- *                    (0 = 16384).
+ *                    (0 = 16384); max_pending: requests waiting for
+ *                    admission at most (0 = no limit): a request arriving
+ *                    while that many wait is refused (load shedding).
  * A dispatch holds requests of one kernel-shape class (the base size k of
  * their exponentiations), so short requests never wait for long ones in the
  * same dispatch; a free slot goes to the class whose oldest pending request
@@ -401,15 +419,19 @@ void rsa_batch_free(rsa_batch *b);
  * than its arrival time on the host's monotonic clock (arrivals must be
  * non-decreasing); it returns when all have completed.  latency (optional,
  * n entries) receives completion - arrival in seconds; the completion time is
- * when the host sees the dispatch's results copied back.
- * Errors: RNS_EINVAL (bad key index or kind, null buffer, decreasing
- * arrivals, a request that alone exceeds the budget), RNS_ENOMEM,
- * RNS_EDEVICE.  The keys must outlive the server.
+ * when the host sees the dispatch's results copied back.  A refused request
+ * keeps its output untouched, gets latency -1 and is counted in
+ * stats.rejected; the others complete, and the call then returns RNS_EBUSY.
+ * Errors, before anything runs: RNS_EINVAL (bad key index or kind, null
+ * buffer, decreasing arrivals), RNS_ERANGE (an input not below its key's n),
+ * RNS_EBUSY (a request that alone exceeds the device-memory budget); while
+ * running: RNS_ENOMEM, RNS_EDEVICE.  The keys must outlive the server.
  */
 typedef struct rsa_server_opts {
     size_t hbm_budget;
     int max_inflight;
     size_t max_dispatch_ops;
+    size_t max_pending;
 } rsa_server_opts;
 
 typedef struct rsa_request {
@@ -422,6 +444,7 @@ typedef struct rsa_request {
 
 typedef struct rsa_server_stats {
     size_t completed;
+    size_t rejected;             /* refused by the pending-queue limit */
     size_t dispatches;
     double elapsed;              /* first arrival to last completion, seconds */
     double p50_latency, p99_latency, max_latency;   /* seconds */

@@ -23,18 +23,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bn_oracle.c")
-_LIBS = {32: os.path.join(_HERE, "liboracle.so"), 8: os.path.join(_HERE, "liboracle8.so")}
+# RNSRSA_SANITIZED=1 loads the AddressSanitizer + UndefinedBehaviorSanitizer
+# builds (build(sanitize=True), clang with the shared sanitizer runtime)
+_SANITIZED = os.environ.get("RNSRSA_SANITIZED") == "1"
+_SUFFIX = "_san" if _SANITIZED else ""
+_LIBS = {32: os.path.join(_HERE, "liboracle%s.so" % _SUFFIX), 8: os.path.join(_HERE, "liboracle8%s.so" % _SUFFIX)}
 _loaded = {}
 
 
-def build(force: bool = False) -> None:
-    """Compile the oracle with gcc (32-bit limbs, plus the 8-bit test build)."""
-    for bits, path in _LIBS.items():
+def build(force: bool = False, sanitize: bool = None) -> None:
+    """Compile the oracle with gcc (32-bit limbs, plus the 8-bit test build);
+    sanitize: with clang, -fsanitize=address,undefined (the *_san.so files)."""
+    sanitize = _SANITIZED if sanitize is None else sanitize
+    for bits in (32, 8):
+        path = os.path.join(_HERE, "liboracle%s%s.so" % ("" if bits == 32 else "8", "_san" if sanitize else ""))
         if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(_SRC):
             continue
         tmp = path + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-DORACLE_LIMB_BITS=%d" % bits, "-o", tmp, _SRC]
+        if sanitize:
+            cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                   "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                   "-shared-libsan", "-DORACLE_LIMB_BITS=%d" % bits, "-o", tmp, _SRC]
+        else:
+            cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                   "-DORACLE_LIMB_BITS=%d" % bits, "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, path)
 

@@ -2,11 +2,22 @@
 
 The kernels are instantiated one (K, W) shape per translation unit so the
 compile runs in parallel; host sources are compiled with the same compiler.
-Usage: python -m paper_1305_3699_amd.build [-j N] [-v]
+Usage: python -m paper_1305_3699_amd.build [-j N] [-v] [--sanitize]
+
+--sanitize builds paper_1305_3699_amd/_lib/librnsrsa_san.so instead, its host
+code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer (device
+code is built as usual).  The CPU tests run against it with
+
+  LD_PRELOAD=$(python -m paper_1305_3699_amd.build --print-asan-runtime) \
+  ASAN_OPTIONS=detect_leaks=0 RNSRSA_SANITIZED=1 python -m pytest tests -m "not gpu"
+
+(RNSRSA_SANITIZED=1 makes the binding and the oracle load their sanitized
+builds; the oracle's is built by oracle.build(sanitize=True)).
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import os
 import re
 import shutil
@@ -21,6 +32,12 @@ INC = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "librnsrsa.so")
+LIB_SAN = os.path.join(LIBDIR, "librnsrsa_san.so")
+BUILD_SAN = os.path.join(HERE, "_build_san")
+# host-side instrumentation only: each flag after -Xarch_host
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_LINK = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -31,7 +48,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-command-line-argument", "-I", INC, "-I", CSRC]
 HOST_SOURCES = ["capi.cpp", "batch.cpp", "jobs.cpp", "server.cpp", "keygen.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp",
-                "emul_mfma.cpp", "kernels_dispatch.cpp", "verify.cpp", "probe.cpp"]
+                "emul_mfma.cpp", "kernels_dispatch.cpp", "verify.cpp", "probe.cpp", "range.cpp"]
 
 
 def shapes() -> list:
@@ -66,20 +83,34 @@ def _run(cmd, verbose):
     return r.stdout
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def asan_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (for LD_PRELOAD)."""
+    root = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cands = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                          "libclang_rt.asan-x86_64.so")))
+    cands += sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not cands:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found")
+    return cands[-1]
+
+
+def build(jobs: int | None = None, verbose: bool = False, sanitize: bool = False) -> str:
     """Compile every source and link the shared library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+    build_dir = BUILD_SAN if sanitize else BUILD
+    lib = LIB_SAN if sanitize else LIB
+    extra = SAN_FLAGS if sanitize else []
+    os.makedirs(build_dir, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     units = []
     for k, w in shapes():
-        src = os.path.join(BUILD, "shape_%d_%d.hip" % (k, w))
+        src = os.path.join(build_dir, "shape_%d_%d.hip" % (k, w))
         text = _shape_source(k, w)
         if not os.path.exists(src) or open(src).read() != text:
             with open(src, "w") as f:
                 f.write(text)
-        units.append((src, os.path.join(BUILD, "shape_%d_%d.o" % (k, w))))
+        units.append((src, os.path.join(build_dir, "shape_%d_%d.o" % (k, w))))
     for k, w, mt, nt in mfma_shapes():
-        src = os.path.join(BUILD, "mshape_%d_%d_%d_%d.hip" % (k, w, mt, nt))
+        src = os.path.join(build_dir, "mshape_%d_%d_%d_%d.hip" % (k, w, mt, nt))
         text = ('#include "kernels_mfma.hpp"\nnamespace rnsrsa {\n'
                 "template hipError_t launch_modexp_mfma_t<%d, %d, %d, %d>(const ModexpMfmaLaunch &, hipStream_t);\n"
                 "template int mfma_blocks_per_cu_t<%d, %d, %d, %d>();\n"
@@ -87,28 +118,34 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         if not os.path.exists(src) or open(src).read() != text:
             with open(src, "w") as f:
                 f.write(text)
-        units.append((src, os.path.join(BUILD, "mshape_%d_%d_%d_%d.o" % (k, w, mt, nt))))
+        units.append((src, os.path.join(build_dir, "mshape_%d_%d_%d_%d.o" % (k, w, mt, nt))))
     for name in HOST_SOURCES:
-        units.append((os.path.join(CSRC, name), os.path.join(BUILD, name.replace(".cpp", ".o"))))
+        units.append((os.path.join(CSRC, name), os.path.join(build_dir, name.replace(".cpp", ".o"))))
     # longest compiles first
     units.sort(key=lambda u: -int(re.search(r"shape_(\d+)", u[0]).group(1)) if "shape_" in u[0] else 0)
     jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(_run, [HIPCC] + COMMON + ["-c", src, "-o", obj], verbose) for src, obj in units]
+        futs = [ex.submit(_run, [HIPCC] + COMMON + extra + ["-c", src, "-o", obj], verbose) for src, obj in units]
         for f in futs:
             f.result()
-    tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [o for _, o in units], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + (SAN_LINK if sanitize else []) + ["-o", tmp]
+         + [o for _, o in units], verbose)
+    os.replace(tmp, lib)
+    return lib
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--sanitize", action="store_true", help="host code with ASan + UBSan (librnsrsa_san.so)")
+    ap.add_argument("--print-asan-runtime", action="store_true")
     a = ap.parse_args(argv)
-    print(build(a.j, a.v))
+    if a.print_asan_runtime:
+        print(asan_runtime())
+        return 0
+    print(build(a.j, a.v, a.sanitize))
     return 0
 
 

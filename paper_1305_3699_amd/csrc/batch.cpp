@@ -10,11 +10,13 @@
 // streams; the Garner steps follow them.  With use_graph the whole sequence
 // is captured into a hipGraph at creation.
 #include <algorithm>
+#include <climits>
 #include <memory>
 #include <new>
 #include <vector>
 
 #include "jobs.hpp"
+#include "range.hpp"
 
 using namespace rnsrsa;
 using namespace rnsrsa::api;
@@ -29,6 +31,8 @@ struct rsa_batch {
     std::vector<GJob *> d_gjobs;
     std::vector<int> gdep;              // the one exponentiation group a Garner group waits for, or -1
     uint32_t *d_mpq = nullptr;
+    RangeLaunch range{};                // input check of every operation: one launch
+    RangeJob *d_rjobs = nullptr;
     hipEvent_t fork = nullptr;
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
@@ -49,6 +53,7 @@ struct rsa_batch {
         for (hipStream_t s : streams)
             if (s) hipStreamDestroy(s);
         if (d_mpq) hipFree(d_mpq);
+        if (d_rjobs) hipFree(d_rjobs);
         if (fork) hipEventDestroy(fork);
         if (capture) hipStreamDestroy(capture);
     }
@@ -80,6 +85,7 @@ int enqueue(rsa_batch *b, hipStream_t s) {
                 return hip_fail(e, "grouped Garner launch");
         if ((e = hipEventRecord(b->done[i], b->streams[i])) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
+    if ((e = launch_range_check(b->range, s)) != hipSuccess) return hip_fail(e, "range check launch");
     int rc = launch_plain_and_garner(b->plan, s, true, false);
     if (rc) return rc;
     for (hipEvent_t d : b->done)
@@ -256,6 +262,26 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
             if (rc) return rc;
             hipError_t e = hipMemcpy(dj, g.jobs.data(), g.jobs.size() * sizeof(GJob), hipMemcpyHostToDevice);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        }
+        // input range check: one job per operation
+        std::vector<RangeJob> rj;
+        int elems = 0;
+        for (size_t i = 0; i < n_ops; i++) {
+            if (!ops[i].count) continue;
+            if (ops[i].count > (size_t)(INT32_MAX - 256 - elems)) return fail(RNS_EINVAL, "more than 2^31 elements");
+            RangeJob j = range_job(ops[i].key, ops[i].in, ops[i].count);
+            j.elem0 = elems;
+            elems += (int)ops[i].count;
+            rj.push_back(j);
+        }
+        if (!rj.empty()) {
+            rc = dmalloc((void **)&b->d_rjobs, rj.size() * sizeof(RangeJob), &b->info.workspace_bytes);
+            if (rc) return rc;
+            hipError_t he = hipMemcpy(b->d_rjobs, rj.data(), rj.size() * sizeof(RangeJob), hipMemcpyHostToDevice);
+            if (he != hipSuccess) return hip_fail(he, "hipMemcpy");
+            b->range.jobs = b->d_rjobs;
+            b->range.njobs = (int)rj.size();
+            b->range.total = elems;
         }
         hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");

@@ -12,6 +12,7 @@
 #include "capi_internal.hpp"
 #include "emul.hpp"
 #include "jobs.hpp"
+#include "range.hpp"
 #include "rnsrsa_host.h"
 
 using namespace rnsrsa;
@@ -375,7 +376,7 @@ extern "C" {
 
 const char *rns_last_error(void) { return g_err.c_str(); }
 
-int rns_abi_version(void) { return 3; }
+int rns_abi_version(void) { return 4; }
 
 int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out) {
     if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");
@@ -595,6 +596,13 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
             }
             rc = RNS_OK;
         }
+        key->h_n.assign(n, n + n_limbs);
+        if ((rc = upload(key->h_n, &key->d_n))) return rc;
+        {
+            hipError_t he = hipMalloc((void **)&key->d_status, sizeof(unsigned long long));
+            if (he == hipSuccess) he = hipMemset(key->d_status, 0, sizeof(unsigned long long));
+            if (he != hipSuccess) return hip_fail(he, "status word");
+        }
         key->h_e.assign(e, e + e_limbs);
         if (d) key->h_d.assign(d, d + n_limbs);
         if ((rc = upload(key->h_e, &key->d_e))) return rc;
@@ -674,7 +682,9 @@ int rsa_encrypt(const rsa_key *key, const uint32_t *m, uint32_t *c, size_t batch
     if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
     if (!key->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
     const rns_ctx *x = key->n;
-    int rc = run_modexp(x, nullptr, entry_of(x), nullptr, m, x->plan.L, key->d_e, nullptr, (int)key->e_limbs, 0, c,
+    int rc = check_inputs(key, m, batch, (hipStream_t)hip_stream);
+    if (!rc)
+        rc = run_modexp(x, nullptr, entry_of(x), nullptr, m, x->plan.L, key->d_e, nullptr, (int)key->e_limbs, 0, c,
                         nullptr, x->plan.L, batch, (hipStream_t)hip_stream);
     return rc ? rc : ok();
 }
@@ -689,7 +699,9 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
         if (!key->d_d) return fail(RNS_EINVAL, "key has no private exponent");
         if (!key->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
         const rns_ctx *x = key->n;
-        int rc = run_modexp(x, nullptr, entry_of(x), nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
+        int rc = check_inputs(key, c, batch, s);
+        if (!rc)
+            rc = run_modexp(x, nullptr, entry_of(x), nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
                             nullptr, x->plan.L, batch, s);
         return rc ? rc : ok();
     }
@@ -697,6 +709,7 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
     Scratch ws;  // [m_p | m_q] per element
     int rc = scratch_alloc(ws, batch * 2 * key->half * sizeof(uint32_t), s);
     if (rc) return rc;
+    if ((rc = check_inputs(key, c, batch, s))) return rc;
     if ((rc = crt_halves(key, c, (uint32_t *)ws.p, batch, s))) return rc;
     if ((rc = crt_combine(key, (uint32_t *)ws.p, m, batch, s))) return rc;
     return ok();
@@ -708,7 +721,8 @@ int rsa_crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t 
     if (!c || !mpq) return fail(RNS_EINVAL, "null buffer");
     if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
     if (!key->has_crt) return fail(RNS_EINVAL, "key has no CRT parts");
-    int rc = crt_halves(key, c, mpq, batch, (hipStream_t)hip_stream);
+    int rc = check_inputs(key, c, batch, (hipStream_t)hip_stream);
+    if (!rc) rc = crt_halves(key, c, mpq, batch, (hipStream_t)hip_stream);
     return rc ? rc : ok();
 }
 

@@ -67,7 +67,10 @@ struct rns_plan {
 
 struct rsa_key {
     size_t n_limbs = 0, e_limbs = 0, half = 0;
+    std::vector<uint32_t> h_n;                    // host copy of n
     std::vector<uint32_t> h_e, h_dp, h_dq, h_d;   // host copies of the exponents
+    uint32_t *d_n = nullptr;                      // n on the device (input range check)
+    unsigned long long *d_status = nullptr;       // inputs >= n seen since the last rsa_key_status
     rns_ctx *n = nullptr;
     uint32_t *d_e = nullptr, *d_d = nullptr;
     bool has_crt = false;
@@ -81,8 +84,10 @@ struct rsa_key {
         delete n;
         delete p;
         delete q;
-        for (uint32_t *x : {d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_mcentry_p, d_mcentry_q, d_gentry, d_qlimbs})
+        for (uint32_t *x : {d_n, d_e, d_d, d_dp, d_dq, d_centry_p, d_centry_q, d_mcentry_p, d_mcentry_q, d_gentry,
+                            d_qlimbs})
             if (x) hipFree(x);
+        if (d_status) hipFree(d_status);
     }
 };
 

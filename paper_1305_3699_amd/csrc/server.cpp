@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "jobs.hpp"
+#include "range.hpp"
 
 using namespace rnsrsa;
 using namespace rnsrsa::api;
@@ -95,6 +96,7 @@ struct rsa_server {
     std::vector<const rsa_key *> keys;
     size_t budget = kDefaultBudget;
     size_t max_ops = 16384;
+    size_t max_pending = 0;      // 0: no limit on requests waiting for admission
     std::vector<Slot> slots;
     ~rsa_server() {
         for (Slot &s : slots) {
@@ -271,6 +273,7 @@ int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_serve
     }
     if (opts && opts->hbm_budget) s->budget = opts->hbm_budget;
     if (opts && opts->max_dispatch_ops) s->max_ops = opts->max_dispatch_ops;
+    if (opts) s->max_pending = opts->max_pending;
     const int inflight = (opts && opts->max_inflight > 0) ? opts->max_inflight : 8;
     if (inflight > 32) return fail(RNS_EINVAL, "max_inflight above 32");
     configure_pool_once();
@@ -299,8 +302,11 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
         if (r.kind == RSA_OP_DECRYPT && !k->has_crt && !k->d_d) return fail(RNS_EINVAL, "key has no private exponent");
         if ((r.kind == RSA_OP_ENCRYPT || !k->has_crt) && !k->n)
             return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
+        if (!host_below_n(k, r.in))
+            return fail(RNS_ERANGE, "request " + std::to_string(i) + ": input not below n (raw RSA works on [0, n))");
         need[i] = op_bytes(k, r.kind, 1);
-        if (need[i] > srv->budget) return fail(RNS_EINVAL, "a request exceeds the device-memory budget");
+        if (need[i] > srv->budget)
+            return fail(RNS_EBUSY, "request " + std::to_string(i) + " alone exceeds the device-memory admission budget");
     }
     std::vector<double> lat(n, 0.0);
     // pending requests, one FIFO per kernel-shape class
@@ -313,7 +319,7 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
     }
     std::vector<std::deque<size_t>> pending(class_id.size());
     size_t n_pending = 0;
-    size_t next = 0, done = 0, dispatches = 0, ops_sum = 0, inflight_bytes = 0, peak_bytes = 0;
+    size_t next = 0, done = 0, dispatches = 0, ops_sum = 0, inflight_bytes = 0, peak_bytes = 0, rejected = 0;
     int inflight = 0, peak_inflight = 0;
     const auto t0 = std::chrono::steady_clock::now();
     double last_done = 0;
@@ -322,9 +328,16 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
         bool progress = false;
         const double now = now_s(t0);
         while (next < n && reqs[next].arrival <= now) {
-            pending[(size_t)cls[next]].push_back(next);
+            if (srv->max_pending && n_pending >= srv->max_pending) {
+                // admission queue full: the request is refused (load shedding)
+                lat[next] = -1.0;
+                rejected++;
+                done++;
+            } else {
+                pending[(size_t)cls[next]].push_back(next);
+                n_pending++;
+            }
             next++;
-            n_pending++;
         }
         // retire finished dispatches
         for (Slot &sl : srv->slots) {
@@ -413,20 +426,26 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
     if (latency) std::copy(lat.begin(), lat.end(), latency);
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->completed = done;
+        stats->completed = done - rejected;
+        stats->rejected = rejected;
         stats->dispatches = dispatches;
         stats->elapsed = n ? last_done - reqs[0].arrival : 0;
-        std::vector<double> s = lat;
+        std::vector<double> s;
+        for (double v : lat)
+            if (v >= 0) s.push_back(v);
         std::sort(s.begin(), s.end());
-        if (n) {
-            stats->p50_latency = s[(n - 1) / 2];
-            stats->p99_latency = s[std::min(n - 1, (size_t)((double)(n - 1) * 0.99 + 0.5))];
-            stats->max_latency = s[n - 1];
+        const size_t m = s.size();
+        if (m) {
+            stats->p50_latency = s[(m - 1) / 2];
+            stats->p99_latency = s[std::min(m - 1, (size_t)((double)(m - 1) * 0.99 + 0.5))];
+            stats->max_latency = s[m - 1];
         }
         stats->mean_dispatch_ops = dispatches ? (double)ops_sum / (double)dispatches : 0;
         stats->peak_inflight_bytes = peak_bytes;
         stats->peak_inflight = peak_inflight;
     }
+    if (rejected)
+        return fail(RNS_EBUSY, std::to_string(rejected) + " request(s) refused: admission queue full (max_pending)");
     return ok();
 }
 

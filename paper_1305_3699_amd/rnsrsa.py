@@ -15,7 +15,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "librnsrsa.so")
+# RNSRSA_SANITIZED=1 selects the host-sanitizer build (build.py --sanitize)
+LIB_PATH = os.path.join(_HERE, "_lib", "librnsrsa_san.so" if os.environ.get("RNSRSA_SANITIZED") == "1"
+                        else "librnsrsa.so")
 
 RNS_OK = 0
 STATUS_NAMES = {0: "RNS_OK", -1: "RNS_EINVAL", -2: "RNS_ERANGE", -3: "RNS_EFACTOR", -4: "RNS_ENOMEM",
@@ -66,11 +68,12 @@ OP_DECRYPT = 1
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int),
-                ("max_dispatch_ops", ctypes.c_size_t)]
+                ("max_dispatch_ops", ctypes.c_size_t), ("max_pending", ctypes.c_size_t)]
 
 
 class ServerStats(ctypes.Structure):
-    _fields_ = [("completed", ctypes.c_size_t), ("dispatches", ctypes.c_size_t), ("elapsed", ctypes.c_double),
+    _fields_ = [("completed", ctypes.c_size_t), ("rejected", ctypes.c_size_t), ("dispatches", ctypes.c_size_t),
+                ("elapsed", ctypes.c_double),
                 ("p50_latency", ctypes.c_double), ("p99_latency", ctypes.c_double),
                 ("max_latency", ctypes.c_double), ("mean_dispatch_ops", ctypes.c_double),
                 ("peak_inflight_bytes", ctypes.c_size_t), ("peak_inflight", ctypes.c_int)]
@@ -101,6 +104,7 @@ _SIGNATURES = {
     "rsa_encrypt": ([_P, _P, _P, _S, _P], _I),
     "rsa_decrypt": ([_P, _P, _P, _S, _I, _P], _I),
     "rsa_crt_halves": ([_P, _P, _P, _S, _P], _I),
+    "rsa_key_status": ([_P, _P, _P], _I),
     "rsa_crt_combine": ([_P, _P, _P, _S, _P], _I),
     "rsa_batch_create": ([_P, _S, _P, _P, _P], _I),
     "rsa_batch_run": ([_P, _P], _I),
@@ -125,7 +129,7 @@ _SIGNATURES = {
 _lib_handle = None
 
 
-ABI_VERSION = 3           # rns_opts / rns_info layout of include/rnsrsa.h
+ABI_VERSION = 4           # rns_opts / rns_info layout of include/rnsrsa.h
 
 
 def lib():
@@ -387,6 +391,15 @@ class RsaKey:
         return out
 
 
+    def status(self, stream=None) -> int:
+        """rsa_key_status: synchronises the stream, returns the number of
+        inputs not below n seen since the last call (and clears it)."""
+        nb = ctypes.c_size_t(0)
+        rc = lib().rsa_key_status(self._h, ctypes.byref(nb), _stream_handle(stream))
+        if rc not in (0, -2):
+            _check(rc)
+        return int(nb.value)
+
     def verify_crt(self, c, m, stream=None) -> int:
         """rsa_crt_verify: recomputes m^e mod n for every row and compares it
         with c; failing rows of m are zeroed.  Returns their number (0: all
@@ -551,21 +564,35 @@ class RsaServer:
     """Request server over resident keys (rsa_server_*): continuous batching
     of RSA operations admitted by device-memory budget."""
 
-    def __init__(self, keys, hbm_budget: int = 0, max_inflight: int = 0, max_dispatch_ops: int = 0):
+    def __init__(self, keys, hbm_budget: int = 0, max_inflight: int = 0, max_dispatch_ops: int = 0,
+                 max_pending: int = 0):
         self._keys = list(keys)
         arr = (ctypes.c_void_p * len(self._keys))(*[k._h.value for k in self._keys])
-        o = ServerOpts(hbm_budget, max_inflight, max_dispatch_ops)
+        o = ServerOpts(hbm_budget, max_inflight, max_dispatch_ops, max_pending)
         h = ctypes.c_void_p()
         _check(lib().rsa_server_create(arr, len(self._keys), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
 
-    def replay(self, key_index, kind, arrival, messages: np.ndarray):
+    def replay(self, key_index, kind, arrival, messages: np.ndarray, allow_refused: bool = False):
         """Open-loop replay.  key_index, kind, arrival (seconds, non-decreasing):
         length-n sequences; messages: uint32 [n, W] host array, row i holding
         request i's input in its first n_limbs(key) limbs.  Returns (outputs
-        [n, W] uint32, latency [n] seconds, stats dict)."""
+        [n, W] uint32, latency [n] seconds (-1: refused by max_pending), stats
+        dict).  With refused requests the call raises RnsError(RNS_EBUSY)
+        unless allow_refused."""
         n = len(key_index)
+        if len(kind) != n or len(arrival) != n:
+            raise ValueError("key_index, kind and arrival must have the same length")
         msgs = np.ascontiguousarray(messages, dtype=np.uint32)
+        if msgs.ndim != 2 or msgs.shape[0] < n:
+            raise ValueError("messages must be a 2-D array with at least %d rows" % n)
+        kidx = np.asarray(key_index, dtype=np.int64)
+        if n and (kidx.min() < 0 or kidx.max() >= len(self._keys)):
+            raise ValueError("key index out of range")
+        if n:
+            need = max(self._keys[int(j)].L for j in np.unique(kidx))
+            if msgs.shape[1] < need:
+                raise ValueError("message rows hold %d limbs; the keys used need %d" % (msgs.shape[1], need))
         outs = np.zeros_like(msgs)
         req = np.zeros(n, dtype=REQUEST_DTYPE)
         req["key"] = np.asarray(key_index, dtype=np.int32)
@@ -576,8 +603,10 @@ class RsaServer:
         req["out"] = outs.ctypes.data + stride * np.arange(n, dtype=np.uint64)
         lat = np.zeros(n, dtype=np.float64)
         st = ServerStats()
-        _check(lib().rsa_server_replay(self._h, req.ctypes.data_as(ctypes.c_void_p), n,
-                                       lat.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+        rc = lib().rsa_server_replay(self._h, req.ctypes.data_as(ctypes.c_void_p), n,
+                                     lat.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+        if not (rc == -7 and allow_refused and st.rejected):
+            _check(rc)
         stats = {f: getattr(st, f) for f, _ in ServerStats._fields_}
         return outs, lat, stats
 

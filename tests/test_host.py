@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(rnsrsa.exported_symbols())
-    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 3
+    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 4
 
 
 def _check_bounds(plan, N, L):
@@ -403,3 +403,38 @@ def test_batch_and_server_argument_errors():
     op = rnsrsa.RsaOp(None, 0, None, None, 1)
     assert lib.rsa_batch_create(ctypes.byref(op), 1, None, None, ctypes.byref(h)) == -1   # null key
     assert rnsrsa.REQUEST_DTYPE.itemsize == 32
+    assert lib.rsa_key_status(None, None, None) == -1                            # null key
+    # the server options and statistics keep the header's layout
+    assert ctypes.sizeof(rnsrsa.ServerOpts) == 32 and ctypes.sizeof(rnsrsa.ServerStats) == 80
+
+
+class _FakeKey:
+    def __init__(self, L):
+        self.L = L
+
+
+def _fake_server(limbs):
+    srv = rnsrsa.RsaServer.__new__(rnsrsa.RsaServer)
+    srv._keys = [_FakeKey(L) for L in limbs]
+    srv._h = None
+    return srv
+
+
+def test_server_replay_shape_checks():
+    """RsaServer.replay checks its arrays before the library reads them: one
+    message row per request, rows as wide as the widest key used, matching
+    sequence lengths, key indices in range."""
+    srv = _fake_server([32, 64])
+    arr = np.zeros(3)
+    with pytest.raises(ValueError):
+        srv.replay([0, 1, 0], [0, 0], arr, np.zeros((3, 64), np.uint32))      # kind too short
+    with pytest.raises(ValueError):
+        srv.replay([0, 1, 0], [0, 0, 0], arr[:2], np.zeros((3, 64), np.uint32))   # arrival too short
+    with pytest.raises(ValueError):
+        srv.replay([0, 1, 0], [0, 0, 0], arr, np.zeros((2, 64), np.uint32))   # too few rows
+    with pytest.raises(ValueError):
+        srv.replay([0, 1, 0], [0, 0, 0], arr, np.zeros((3, 32), np.uint32))   # rows narrower than key 1
+    with pytest.raises(ValueError):
+        srv.replay([0, 2, 0], [0, 0, 0], arr, np.zeros((3, 64), np.uint32))   # no key 2
+    with pytest.raises(ValueError):
+        srv.replay([0, 1, 0], [0, 0, 0], arr, np.zeros(64, np.uint32))        # not 2-D

@@ -268,6 +268,31 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
                 void *hip_stream);
 
 /*
+ * rsa_decrypt_noalloc -- rsa_decrypt for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same launches and results as rsa_decrypt with the
+ * same arguments, but the window tables and the CRT intermediates live in a
+ * fixed array of RSA_NOALLOC_SCRATCH_BYTES bytes that the library holds on
+ * each device it runs on (one copy per device, from first use until the
+ * process ends).  The call makes no device allocation.
+ *   Limit: a batch whose scratch exceeds the array returns RNS_EINVAL with
+ *   the bytes it needs, before anything is enqueued.  Scratch per element:
+ *   the window table of each exponentiation (2^w entries of the kernel's
+ *   residue slots, a little over 2k+1 words, rounded up to whole workgroup
+ *   tiles), two of them for CRT, plus 8 * half_limbs bytes of CRT
+ *   intermediates.  RSA-2048 CRT (k = 33): about 43 KB per ciphertext at
+ *   window 6 and 22 KB at window 5, i.e. up to about 1,500 and 3,000
+ *   ciphertexts per call.
+ *   Sharing: every call on one device uses the same array, which keeps the
+ *   last call's contents; calls that overlap on one device (two streams,
+ *   two threads) race and give wrong results.  Serialise them.
+ * Errors as rsa_decrypt.
+ */
+#define RSA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int rsa_decrypt_noalloc(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch, int use_crt,
+                        void *hip_stream);
+
+/*
  * rsa_key_status -- the input range status of a key (Sec. 3.3: raw RSA on
  * integers below n).  Synchronises hip_stream, then reads and clears the
  * key's device count of inputs >= n enqueued by rsa_encrypt, rsa_decrypt,

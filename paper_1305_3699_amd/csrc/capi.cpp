@@ -246,9 +246,25 @@ MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev) {
     return 2 * tiles * (size_t)sh.W < 3 * (size_t)simds ? alt : sh;
 }
 
+// Kernel shape of a plain launch of njobs jobs of `batch` elements on c0.
+static MfmaShape plain_shape(const rns_ctx *c0, int njobs, size_t batch) {
+    MfmaShape sh = c0->mshape;
+    if (!c0->group_req) sh = auto_tile(sh, (size_t)mfma_tiles(sh, batch) * njobs, c0->device);
+    return sh;
+}
+
+size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch) {
+    if (c0->engine == RNS_ENGINE_MATRIX) {
+        const MfmaShape sh = plain_shape(c0, njobs, batch);
+        return modexp_mfma_table_words(sh, c0->window, (size_t)mfma_tiles(sh, batch) * njobs) * sizeof(uint32_t);
+    }
+    const BaseSet &bs = *c0->plan.base;
+    return modexp_table_words(bs.K, bs.W, c0->window, (batch + 63) / 64 * njobs) * sizeof(uint32_t);
+}
+
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
-               uint32_t *out1, int out_stride, size_t batch, hipStream_t s) {
+               uint32_t *out1, int out_stride, size_t batch, hipStream_t s, uint32_t *table_buf) {
     const BaseSet &bs = *c0->plan.base;
     const int njobs = c1 ? 2 : 1;
     ModexpParams P{};
@@ -261,8 +277,7 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
     P.window = c0->window;
     P.batch = (int)batch;
     if (c0->engine == RNS_ENGINE_MATRIX) {
-        MfmaShape sh = c0->mshape;
-        if (!c0->group_req) sh = auto_tile(sh, (size_t)mfma_tiles(sh, batch) * njobs, c0->device);
+        const MfmaShape sh = plain_shape(c0, njobs, batch);
         ModexpMfmaLaunch a{};
         const int per_job = mfma_tiles(sh, batch);
         for (int j = 0; j < njobs; j++) {
@@ -288,17 +303,20 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
         a.tiles = per_job * njobs;
         a.max_window = c0->window;
         Scratch table;
-        int rc = scratch_alloc(table, modexp_mfma_table_words(sh, a.max_window, (size_t)a.tiles) * sizeof(uint32_t), s);
-        if (rc) return rc;
-        a.table = (uint32_t *)table.p;
+        if (!table_buf) {
+            int rc = scratch_alloc(table, modexp_scratch_bytes(c0, njobs, batch), s);
+            if (rc) return rc;
+        }
+        a.table = table_buf ? table_buf : (uint32_t *)table.p;
         hipError_t e = launch_modexp_mfma(sh, a, s);
         if (e != hipSuccess) return hip_fail(e, "modexp (matrix cores) launch");
         return RNS_OK;
     }
-    const size_t wgs = (batch + 63) / 64 * njobs;
     Scratch table;
-    int rc = scratch_alloc(table, modexp_table_words(bs.K, bs.W, c0->window, wgs) * sizeof(uint32_t), s);
-    if (rc) return rc;
+    if (!table_buf) {
+        int rc = scratch_alloc(table, modexp_scratch_bytes(c0, njobs, batch), s);
+        if (rc) return rc;
+    }
     ModexpLaunch a{};
     a.bc = c0->d_base;
     a.mc[0] = c0->d_mod;
@@ -310,7 +328,7 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
     a.in = in;
     a.out[0] = out0;
     a.out[1] = out1 ? out1 : out0;
-    a.table = (uint32_t *)table.p;
+    a.table = table_buf ? table_buf : (uint32_t *)table.p;
     a.P.in_limbs = in_limbs;
     a.P.in_stride = in_limbs;
     a.P.L = c0->plan.L;
@@ -330,11 +348,11 @@ Limbs limbs_of(const uint32_t *p, size_t n) { return bn_from_ptr(p, n); }
 const uint32_t *entry_of(const rns_ctx *c) { return c->engine == RNS_ENGINE_MATRIX ? c->d_mentry : c->d_entry; }
 
 // Both half-size exponentiations of a CRT decryption in one launch.
-int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s) {
+int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s, uint32_t *table) {
     const int L = (int)key->half;
     const bool m = key->p->engine == RNS_ENGINE_MATRIX;
     return run_modexp(key->p, key->q, m ? key->d_mcentry_p : key->d_centry_p, m ? key->d_mcentry_q : key->d_centry_q,
-                      c, (int)key->n_limbs, key->d_dp, key->d_dq, L, 0, mpq, mpq + L, 2 * L, batch, s);
+                      c, (int)key->n_limbs, key->d_dp, key->d_dq, L, 0, mpq, mpq + L, 2 * L, batch, s, table);
 }
 
 // Garner recombination over the p-modulus tables.

@@ -112,9 +112,17 @@ MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev);
 // base, default engine and tile).  Owned by the caller (delete).
 int make_context(const Limbs &N, int L, rns_ctx **out);
 // One or two exponentiation jobs sharing their inputs (the plain launch).
+// table_buf: device scratch of modexp_scratch_bytes(c0, njobs, batch) bytes
+// for the window tables, or null to allocate it stream-ordered.
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
-               uint32_t *out1, int out_stride, size_t batch, hipStream_t s);
+               uint32_t *out1, int out_stride, size_t batch, hipStream_t s, uint32_t *table_buf = nullptr);
+// Window-table bytes of a plain launch of njobs (1 or 2) jobs of `batch`
+// elements on c0 (same base, window and tile for both jobs).
+size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch);
+// Both halves of a CRT decryption in one launch into mpq (table as run_modexp).
+int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s,
+               uint32_t *table = nullptr);
 
 }  // namespace api
 }  // namespace rnsrsa

@@ -103,6 +103,7 @@ _SIGNATURES = {
     "rsa_key_info": ([_P, _I, _P], _I),
     "rsa_encrypt": ([_P, _P, _P, _S, _P], _I),
     "rsa_decrypt": ([_P, _P, _P, _S, _I, _P], _I),
+    "rsa_decrypt_noalloc": ([_P, _P, _P, _S, _I, _P], _I),
     "rsa_crt_halves": ([_P, _P, _P, _S, _P], _I),
     "rsa_key_status": ([_P, _P, _P], _I),
     "rsa_crt_combine": ([_P, _P, _P, _S, _P], _I),
@@ -388,6 +389,14 @@ class RsaKey:
             out = torch.empty_like(c)
         _check(lib().rsa_decrypt(self._h, _dev_ptr(c, B, self.L, "c"), _dev_ptr(out, B, self.L, "out"), B,
                                  1 if use_crt else 0, _stream_handle(stream)))
+        return out
+
+    def decrypt_noalloc(self, c, out, use_crt: bool = True, stream=None):
+        """rsa_decrypt_noalloc: decrypt into the caller's out ([B, n_limbs])
+        with the library's fixed device scratch (no allocation anywhere)."""
+        B = c.shape[0]
+        _check(lib().rsa_decrypt_noalloc(self._h, _dev_ptr(c, B, self.L, "c"), _dev_ptr(out, B, self.L, "out"), B,
+                                         1 if use_crt else 0, _stream_handle(stream)))
         return out
 
 

@@ -74,6 +74,12 @@ struct MShp {
     static constexpr bool C_LDS = KSTEPS > 9;
     static constexpr int C_WORDS = C_LDS ? W * MT * 4 * 8 : 0;
     static constexpr int LDS_WORDS = WORK_WORDS + A2_WORDS + C_WORDS;
+    // Each wave's second operand of the next window multiplication is
+    // prefetched from the window table into LDS while the squarings before it
+    // run: [SLOTS][64] words per wave, wherever that still fits the 160 KiB
+    // a workgroup may hold (every shape but the 513-channel one).
+    static constexpr int PF_WORDS = W * SLOTS * 64;
+    static constexpr bool PREFETCH = (size_t)(LDS_WORDS + PF_WORDS) * 4 <= 160 * 1024;
 };
 
 template <int MT, int NT>
@@ -344,6 +350,35 @@ __device__ __forceinline__ void mstate_load(const gu32 *__restrict__ p, MState<M
     for (int nt = 0; nt < NT; nt++) a.r[nt] = p[(2 * MT * NT + nt) * 64];
 }
 
+// The same in LDS (p = this wave's buffer + lane): each wave reads and
+// writes only its own buffer, so program order (and, after the prefetch,
+// vmem_drain) orders the accesses.
+template <int MT, int NT>
+__device__ __forceinline__ void mstate_store_lds(uint32_t *p, const MState<MT, NT> &a) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            p[(mt * NT + nt) * 64] = a.b[mt][nt];
+            p[(MT * NT + mt * NT + nt) * 64] = a.p[mt][nt];
+        }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) p[(2 * MT * NT + nt) * 64] = a.r[nt];
+}
+
+template <int MT, int NT>
+__device__ __forceinline__ void mstate_load_lds(const uint32_t *p, MState<MT, NT> &a) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            a.b[mt][nt] = p[(mt * NT + nt) * 64];
+            a.p[mt][nt] = p[(MT * NT + mt * NT + nt) * 64];
+        }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) a.r[nt] = p[(2 * MT * NT + nt) * 64];
+}
+
 // y = 1 in the kept representation: 2^32 mod m in B, 2^32 M^-1 mod m' in B'
 // (read from the table when needed rather than held in registers).
 template <int K, int W, int MT, int NT>
@@ -363,11 +398,29 @@ __device__ __forceinline__ void mstate_unit(const MConstOf<K, W, MT, NT> &C,
     for (int nt = 0; nt < NT; nt++) y.r[nt] = 1u;
 }
 
-// Limb l of a shared (wave-uniform) exponent.  The builtin returns int: the
-// limb is taken back as unsigned before any widening (a sign extension would
-// fill the upper half of a 64-bit window with ones).
+// Limb l of a shared (wave-uniform) exponent, through the scalar unit: read
+// through the constant address space at a uniform index it is a scalar load
+// (its wait is on the scalar counter, so it never waits for the vector
+// memory operations in flight, such as the operand prefetch).
+typedef const __attribute__((address_space(4))) uint32_t ku32;
 __device__ __forceinline__ uint32_t mexp_limb(const gu32 *__restrict__ e, int l) {
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)e[l]);
+    return ((ku32 *)e)[__builtin_amdgcn_readfirstlane(l)];
+}
+
+// Wait until every vector memory operation of this wave has completed
+// (s_waitcnt vmcnt(0): on this target the immediate holds vmcnt in bits 3:0
+// and 15:14, expcnt in 6:4, lgkmcnt in 11:8; the others stay at their maximum).
+__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// One row of the operand prefetch: lane l's word src[l] lands in LDS at
+// dst[l] without passing through registers (global_load_lds_dword; M0 holds
+// the wave-uniform LDS byte address of dst).  Issued as inline assembly so the
+// compiler adds no waits of its own for it: its only reader waits with
+// vmem_drain() first, and vector loads complete in issue order, so the
+// compiler's counts for its own loads stay valid.
+__device__ __forceinline__ void lds_dma_row(const gu32 *src, uint32_t *dst) {
+    const uint32_t m0v = (uint32_t)(size_t)(__attribute__((address_space(3))) void *)dst;
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off" ::"s"(m0v), "v"(src) : "memory");
 }
 
 // Bit i of a shared exponent.
@@ -446,10 +499,12 @@ __device__ __forceinline__ void mfma_exit_tail(const gu32 *__restrict__ mb, cons
 }
 
 // One tile (16*NT elements) of exponentiation job J, elements
-// [e0, e0 + 16*NT) of the job, with window table slot `slot` of the launch.
+// [e0, e0 + 16*NT) of the job, with window table slot `slot` of the launch;
+// ylds: the operand prefetch buffer (S::PF_WORDS words, if S::PREFETCH).
 template <int K, int W, int MT, int NT>
 __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t *__restrict__ lds,
-                                                 uint32_t *__restrict__ table, size_t slot, int max_window) {
+                                                 uint32_t *__restrict__ table, size_t slot, int max_window,
+                                                 uint32_t *__restrict__ ylds) {
     using S = MShp<K, W, MT, NT>;
     uint32_t *buf1 = lds;
     uint32_t *buf2 = lds + S::NM * S::BROW;
@@ -596,29 +651,41 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
 
     // Exponent schedule.  Shared exponent: left-to-right sliding windows of
     // at most w bits that start and end with a set bit, over a table of the
-    // odd powers x, x^3, ..., x^(2^w - 1) (built with x^2, kept in slot 2);
-    // the windows are found on the scalar unit.  Per-element exponents: fixed
-    // w-bit digits over the full table x^0 .. x^(2^w - 1).  The control picks
-    // where the next product's second operand comes from; it is fetched at
-    // the top of the loop, so it is not live across iterations.
+    // odd powers x, x^3, ..., x^(2^w - 1) (built with x^2); the windows are
+    // found on the scalar unit.  Per-element exponents: fixed w-bit digits
+    // over the full table x^0 .. x^(2^w - 1).  The control picks where the
+    // next product's second operand comes from.  Squarings take their own
+    // copy of the product (no operand copy).  With the prefetch buffer, the
+    // constant operand of the table build (x^2, or x for per-element
+    // exponents) stays in it, and the table entry of each window
+    // multiplication is copied into it when the window is found, one or more
+    // squarings ahead (Y_PREF_DMA waits for that copy).  Every other operand
+    // load is drained where it is issued, so a product never waits for vector
+    // memory and the copy in flight overlaps the squarings.
     const bool shared_exp = J.exp_stride == 0;
     const int nbits = 32 * J.exp_limbs;
     const int nd = (nbits + w - 1) / w;
     enum { ENTRY, SQX, BUILD, MAIN, EXIT };
-    enum { Y_SQUARE, Y_UNIT, Y_TABLE, Y_ELEM };
+    enum { Y_SQUARE, Y_UNIT, Y_TABLE, Y_ELEM, Y_PREF, Y_PREF_DMA };
+    uint32_t *yb = ylds + (size_t)wave * S::SLOTS * 64;   // this wave's prefetch buffer, [slot][lane]
     int phase = ENTRY, j = 2, di = 0, s = 0;
     int bitpos = -1, sq = 0;
     uint32_t dm = 0;
     int ysrc = Y_UNIT, yidx = 0;
     for (;;) {
-        {
+        if (ysrc == Y_SQUARE) {
+            mfma_mm<K, W, MT, NT>(C, a, a, buf1, buf2, wave, lane, true);
+        } else {
             MState<MT, NT> y;
-            if (ysrc == Y_SQUARE) {
-                y = a;
-            } else if (ysrc == Y_UNIT) {
+            if (ysrc == Y_UNIT) {
                 mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
+                vmem_drain();
             } else if (ysrc == Y_TABLE) {
                 mstate_load<MT, NT>(tw + (size_t)yidx * estride, y);
+                vmem_drain();
+            } else if (ysrc == Y_PREF || ysrc == Y_PREF_DMA) {
+                if (ysrc == Y_PREF_DMA) vmem_drain();   // the entry copied at the window's start has landed
+                mstate_load_lds<MT, NT>(yb + lane, y);
             } else {
                 // per-element exponents: each lane slot loads the entry of its own element
 #pragma unroll
@@ -634,6 +701,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
                     }
                     y.r[nt] = pe[(2 * MT * NT + nt) * 64];
                 }
+                vmem_drain();
             }
             mfma_mm<K, W, MT, NT>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
         }
@@ -647,24 +715,34 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
                 } else {
                     phase = BUILD;
                     j = 2;
-                    ysrc = Y_TABLE;
-                    yidx = 1;
+                    if (S::PREFETCH) {
+                        mstate_store_lds<MT, NT>(yb + lane, a);  // x, the build's constant operand
+                        ysrc = Y_PREF;
+                    } else {
+                        ysrc = Y_TABLE;
+                        yidx = 1;
+                    }
                 }
                 continue;
             }
         } else if (phase == SQX) {
-            mstate_store<MT, NT>(tw + 2 * estride, a);           // x^2, slot 2 (even: unused by the windows)
+            if (S::PREFETCH) {
+                mstate_store_lds<MT, NT>(yb + lane, a);          // x^2, the build's constant operand
+            } else {
+                mstate_store<MT, NT>(tw + 2 * estride, a);       // x^2, slot 2 (even: unused by the windows)
+            }
             mstate_load<MT, NT>(tw + estride, a);
+            vmem_drain();
             phase = BUILD;
             j = 3;
-            ysrc = Y_TABLE;
+            ysrc = S::PREFETCH ? Y_PREF : Y_TABLE;
             yidx = 2;
             continue;
         } else if (phase == BUILD) {
             mstate_store<MT, NT>(tw + (size_t)j * estride, a);  // T[j] = T[j - step] * (x^2 or x)
             j += shared_exp ? 2 : 1;
             if (j < T) {
-                ysrc = Y_TABLE;
+                ysrc = S::PREFETCH ? Y_PREF : Y_TABLE;
                 yidx = shared_exp ? 2 : 1;
                 continue;
             }
@@ -684,13 +762,14 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
             } else {
                 mstate_load<MT, NT>(tw, a);
             }
+            vmem_drain();
         }
         if (shared_exp) {
             if (sq > 0) {                                          // squarings of the current window
                 ysrc = Y_SQUARE;
                 sq--;
             } else if (dm) {                                       // its multiplication
-                ysrc = Y_TABLE;
+                ysrc = S::PREFETCH ? Y_PREF_DMA : Y_TABLE;
                 yidx = (int)dm;
                 dm = 0;
             } else if (bitpos < 0) {
@@ -701,6 +780,11 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
                 if (mexp_bit(ex, bitpos)) {
                     int low;
                     dm = mexp_window(ex, J.exp_limbs, bitpos, w, &low);
+                    if (S::PREFETCH) {
+                        const gu32 *src = tw + (size_t)dm * estride;
+#pragma unroll
+                        for (int r = 0; r < S::SLOTS; r++) lds_dma_row(src + r * 64, yb + r * 64);
+                    }
                     sq = bitpos - low;
                     bitpos = low - 1;
                 } else {
@@ -852,6 +936,7 @@ template <int K, int W, int MT, int NT>
 __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A) {
     using S = MShp<K, W, MT, NT>;
     __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t ylds[S::PREFETCH ? S::PF_WORDS : 1];
     const int tile = blockIdx.x;
     MJob J;
     if (A.jobs) {
@@ -864,7 +949,7 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A)
     } else {
         J = (A.njobs > 1 && tile >= A.inl[1].tile0) ? A.inl[1] : A.inl[0];
     }
-    modexp_mfma_tile<K, W, MT, NT>(J, (tile - J.tile0) * S::NM, lds, A.table, blockIdx.x, A.max_window);
+    modexp_mfma_tile<K, W, MT, NT>(J, (tile - J.tile0) * S::NM, lds, A.table, blockIdx.x, A.max_window, ylds);
 }
 
 template <int K, int W, int MT, int NT>

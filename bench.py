@@ -409,6 +409,7 @@ def run_mixed(args, keys, ops) -> dict:
                      "ms_p50": round(statistics.median(ms), 3), "ms_p99": round(ms[-1], 3)}
     same = all(torch.equal(out_p, out_b) for _, _, _, out_p, out_b, _ in items)
     info = batch.info
+    classes = batch.classes
     batch.close()
     threads = cpu_threads()
     t0 = time.perf_counter()
@@ -437,6 +438,9 @@ def run_mixed(args, keys, ops) -> dict:
         "launches_per_run": {"batched": info["launches"] + info["garner_launches"],
                              "plain": len(items) + sum(1 for o in ops if o.kind == "decrypt")},
         "graph": True,
+        "autotuned": [{key: c[key] for key in ("k", "waves", "group", "exp_bits", "window", "window_offset", "jobs",
+                                               "launch_ms")} for c in classes],
+        "tuning_launches": info["tuning_launches"],
         "create_s": round(create_s, 2),
         "workspace_mb": round(info["workspace_bytes"] / 2 ** 20, 1),
     }

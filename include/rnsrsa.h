@@ -138,7 +138,7 @@ typedef struct rsa_key rsa_key;
  * is valid until the next library call on this thread. */
 const char *rns_last_error(void);
 
-/* ABI version of this header (currently 4). */
+/* ABI version of this header (currently 5). */
 int rns_abi_version(void);
 
 /*
@@ -372,11 +372,18 @@ int rsa_crt_verify(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t ba
  * new data by writing into the same buffers.  Keys must outlive the batch.
  *
  * Tuning (rsa_batch_opts, NULL = defaults):
- *   autotune     1: for each kernel shape class, time the candidate tiles
- *                (elements per workgroup) on the device at creation and keep
- *                the faster (cached per process); 0: each launch's tile
- *                chosen as for rns_opts.group = 0 (keys set up with an
- *                explicit group keep it).
+ *   autotune     1: at creation, for each kernel shape class, time the whole
+ *                group launch (outputs to scratch) with each candidate tile
+ *                (16 or 32 elements per workgroup) and keep the fastest; then,
+ *                for each exponent length in the class, time the window
+ *                offsets -1 and +1 from every job's product-minimising window
+ *                and keep one that is at least 1% faster.  The choices are
+ *                cached per process and also used by later batches and by
+ *                the request server.  The base size k is not a tuning
+ *                dimension: every job runs on the smallest base its modulus
+ *                fits (see rsa_batch_classes for what was chosen).  0: each
+ *                launch's tile chosen as for rns_opts.group = 0 (keys set up
+ *                with an explicit group keep it), windows minimise products.
  *   use_graph    1: capture into a hipGraph at creation (default 1; not
  *                used when some key runs on the channel engine).
  *   window       0: per job, the window width minimising the number of
@@ -407,7 +414,9 @@ typedef struct rsa_batch_info {
     int garner_launches;     /* grouped Garner launches per run (one per base shape of CRT halves) */
     size_t workspace_bytes;  /* device memory held by the batch */
     size_t modmuls;          /* RNS Montgomery products per element, summed over elements */
+    int tuning_launches;     /* group launches the autotuner timed at creation */
 } rsa_batch_info;
+
 
 typedef struct rsa_batch rsa_batch;
 
@@ -415,6 +424,24 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
                      rsa_batch **out);
 int rsa_batch_run(rsa_batch *b, void *hip_stream);
 int rsa_batch_info_get(const rsa_batch *b, rsa_batch_info *info);
+/*
+ * What the batch runs, per (kernel shape class, exponent length): one entry
+ * per class in launch order.  out: host array of cap entries (may be NULL
+ * with cap = 0 to count); *n receives the number of classes.
+ */
+typedef struct rsa_batch_class {
+    int k;               /* channels per base */
+    int waves;           /* wavefronts per workgroup */
+    int group;           /* elements per workgroup (the tile) */
+    int exp_bits;        /* exponent length of the class's jobs (32 x limbs) */
+    int window;          /* window width of the class's most expensive job */
+    int window_offset;   /* offset from each job's product-minimising window */
+    int jobs;            /* exponentiation jobs of this exponent length */
+    int tuned;           /* 1 when the autotuner chose tile and window offset */
+    double launch_ms;    /* autotune: measured time of the whole group launch */
+} rsa_batch_class;
+
+int rsa_batch_classes(const rsa_batch *b, rsa_batch_class *out, size_t cap, size_t *n);
 /* Waits for the batch's device work, then releases it. */
 void rsa_batch_free(rsa_batch *b);
 

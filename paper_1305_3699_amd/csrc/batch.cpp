@@ -11,6 +11,8 @@
 // is captured into a hipGraph at creation.
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <string>
 #include <memory>
 #include <new>
 #include <vector>
@@ -38,6 +40,7 @@ struct rsa_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     rsa_batch_info info{};
+    std::vector<float> group_ms;        // autotune: time of each group's launch as tuned (ms)
     ~rsa_batch() {
         hipDeviceSynchronize();
         if (exec) hipGraphExecDestroy(exec);
@@ -96,75 +99,154 @@ int enqueue(rsa_batch *b, hipStream_t s) {
     return RNS_OK;
 }
 
-// Times each candidate tile of a group's shape class on copies of its most
-// expensive job (outputs to scratch) and returns the faster NT.
-int tune_tile(const JobGroup &g, const std::vector<MLayout> &cands, int *nt_out) {
-    const PlannedJob &heavy = *std::max_element(
-        g.jobs.begin(), g.jobs.end(), [](const PlannedJob &a, const PlannedJob &b) { return a.cost < b.cost; });
-    const int copies = std::max(1, (int)(16384 / std::max(1, heavy.j.batch)));
-    const size_t out_words = (size_t)copies * heavy.j.batch * heavy.j.L;
-    uint32_t *d_out = nullptr;
-    MJob *d_jobs = nullptr;
-    uint32_t *d_table = nullptr;
-    hipEvent_t t0 = nullptr, t1 = nullptr;
+// Times launches of one exponentiation group as it would run (every job,
+// outputs redirected to scratch so the caller's buffers are not written) for
+// the autotuner.  The scratch grows as needed and is released by release().
+struct GroupTimer {
     hipStream_t s = nullptr;
-    int rc = RNS_OK;
-    float best = 0;
-    *nt_out = cands[0].NT;
-    auto cleanup = [&] {
-        if (d_out) hipFree(d_out);
-        if (d_jobs) hipFree(d_jobs);
-        if (d_table) hipFree(d_table);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    uint32_t *out = nullptr, *table = nullptr;
+    MJob *jobs = nullptr;
+    size_t out_words = 0, table_words = 0, njobs = 0;
+    int launches = 0;
+
+    int init() {
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&t0);
+        if (e == hipSuccess) e = hipEventCreate(&t1);
+        return e == hipSuccess ? RNS_OK : hip_fail(e, "autotune set-up");
+    }
+    void release() {
+        if (out) hipFree(out);
+        if (table) hipFree(table);
+        if (jobs) hipFree(jobs);
         if (t0) hipEventDestroy(t0);
         if (t1) hipEventDestroy(t1);
         if (s) hipStreamDestroy(s);
-    };
-    hipError_t e = hipMalloc((void **)&d_out, out_words * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc((void **)&d_jobs, (size_t)copies * sizeof(MJob));
-    if (e == hipSuccess) e = hipEventCreate(&t0);
-    if (e == hipSuccess) e = hipEventCreate(&t1);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "autotune set-up");
     }
-    for (const MLayout &sh : cands) {
-        std::vector<MJob> js(copies, heavy.j);
-        const int per = mfma_tiles(sh, (size_t)heavy.j.batch);
-        for (int c = 0; c < copies; c++) {
-            js[c].out = d_out + (size_t)c * heavy.j.batch * heavy.j.L;
-            js[c].out_stride = heavy.j.L;
-            js[c].tile0 = c * per;
+    template <class T>
+    static hipError_t grow(T **p, size_t *have, size_t need) {
+        if (need <= *have) return hipSuccess;
+        if (*p) hipFree(*p);
+        *p = nullptr;
+        *have = 0;
+        hipError_t e = hipMalloc((void **)p, need * sizeof(T));
+        if (e == hipSuccess) *have = need;
+        return e;
+    }
+    // Best of `reps` launch times of g (its shape, windows and tile order) in ms.
+    int time(const JobGroup &g, int reps, float *best) {
+        std::vector<MJob> js;
+        size_t words = 0;
+        for (const PlannedJob &J : g.jobs) words += (size_t)J.j.batch * J.j.out_stride;
+        hipError_t e = grow(&out, &out_words, words);
+        if (e == hipSuccess) e = grow(&table, &table_words, g.table_words());
+        if (e == hipSuccess) e = grow(&jobs, &njobs, g.jobs.size());
+        if (e != hipSuccess) return fail(RNS_ENOMEM, std::string("autotune scratch: ") + hipGetErrorString(e));
+        size_t off = 0;
+        for (const PlannedJob &J : g.jobs) {
+            js.push_back(J.j);
+            js.back().out = out + off;
+            off += (size_t)J.j.batch * J.j.out_stride;
         }
-        ModexpMfmaLaunch a{};
-        a.jobs = d_jobs;
-        a.njobs = copies;
-        a.tiles = per * copies;
-        a.max_window = heavy.j.window;
-        if (d_table) hipFree(d_table);
-        d_table = nullptr;
-        e = hipMalloc((void **)&d_table, modexp_mfma_table_words(sh, a.max_window, (size_t)a.tiles) * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMemcpy(d_jobs, js.data(), js.size() * sizeof(MJob), hipMemcpyHostToDevice);
-        a.table = d_table;
-        float ms = 0;
-        for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
+        if ((e = hipMemcpy(jobs, js.data(), js.size() * sizeof(MJob), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy");
+        *best = 0;
+        for (int rep = 0; rep < reps; rep++) {
+            float ms = 0;
             if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
-            if ((e = launch_modexp_mfma(sh, a, s)) != hipSuccess) break;
+            if ((e = launch_group(g, jobs, table, s)) != hipSuccess) break;
             if ((e = hipEventRecord(t1, s)) != hipSuccess) break;
             if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
-            e = hipEventElapsedTime(&ms, t0, t1);
+            if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+            launches++;
+            if (*best == 0 || ms < *best) *best = ms;
         }
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "autotune run");
-            break;
-        }
-        if (best == 0 || ms < best) {
-            best = ms;
-            *nt_out = sh.NT;
-        }
+        return e == hipSuccess ? RNS_OK : hip_fail(e, "autotune run");
     }
-    cleanup();
-    return rc;
+};
+
+// Autotuner of one exponentiation group: first the tile (elements per
+// workgroup) among the shapes of its class, with every job at the window
+// that minimises its product count; then, for each exponent length in the
+// group (longest total work first), the window offset -1 / 0 / +1 from each
+// job's own best, kept when it is at least 1% faster.  Each candidate is
+// timed on the whole group (best of 3 launches).  Choices already made in
+// this process for the class are reused without timing.
+int tune_group(JobGroup &g, bool fixed_window, GroupTimer &tm, float *ms_out) {
+    constexpr int kReps = 3;
+    std::vector<MLayout> cands;
+    for (int nt : {1, 2}) {
+        MfmaShape sh;
+        if (mfma_shape_for(g.shape.K, sh, 16 * nt) && sh.W == g.shape.W && sh.MT == g.shape.MT && sh.NT == nt)
+            cands.push_back(sh);
+    }
+    float best = 0;
+    int rc = RNS_OK;
+    const int cached_nt = tuned_nt(g.shape);
+    if (cands.size() > 1 && !cached_nt) {
+        MLayout pick = g.shape;
+        for (const MLayout &c : cands) {
+            JobGroup trial = g;
+            trial.shape = c;
+            finish_group(trial);
+            float ms = 0;
+            if ((rc = tm.time(trial, kReps, &ms))) return rc;
+            if (best == 0 || ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        g.shape = pick;
+        set_tuned_nt(g.shape, g.shape.NT);
+    } else if (cached_nt) {
+        for (const MLayout &c : cands)
+            if (c.NT == cached_nt) g.shape = c;
+    }
+    finish_group(g);
+    g.auto_tile = false;
+    if (!fixed_window) {
+        // exponent lengths of the group, by total products (largest first)
+        std::map<int, size_t> work;
+        for (const PlannedJob &J : g.jobs) work[J.j.exp_limbs] += J.cost * (size_t)J.j.batch;
+        std::vector<std::pair<size_t, int>> order;
+        for (auto &kv : work) order.push_back({kv.second, kv.first});
+        std::sort(order.rbegin(), order.rend());
+        for (auto &o : order) {
+            const int el = o.second;
+            bool known = false;
+            int dw = tuned_dw(g.shape, el, &known);
+            if (!known) {
+                if (best == 0 && (rc = tm.time(g, kReps, &best))) return rc;
+                dw = 0;
+                for (int cand : {-1, 1}) {
+                    JobGroup trial = g;
+                    bool changed = false;
+                    for (PlannedJob &J : trial.jobs)
+                        if (J.j.exp_limbs == el) {
+                            const int before = J.j.window;
+                            set_job_window(J, cand);
+                            changed = changed || J.j.window != before;
+                        }
+                    if (!changed) continue;
+                    finish_group(trial);
+                    float ms = 0;
+                    if ((rc = tm.time(trial, kReps, &ms))) return rc;
+                    if (ms < 0.99f * best) {
+                        best = ms;
+                        dw = cand;
+                    }
+                }
+                set_tuned_dw(g.shape, el, dw);
+            }
+            for (PlannedJob &J : g.jobs)
+                if (J.j.exp_limbs == el) set_job_window(J, dw);
+        }
+        finish_group(g);
+    }
+    if (best == 0 && (rc = tm.time(g, kReps, &best))) return rc;
+    *ms_out = best;
+    return RNS_OK;
 }
 
 }  // namespace
@@ -200,24 +282,24 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
         }
         if ((rc = plan_jobs(pops, fixed_w, b->plan))) return rc;
 
-        // tile choice, device job tables, window tables, streams
+        // tile and window choice, device job tables, window tables, streams
+        if (autotune) {
+            GroupTimer tm;
+            rc = tm.init();
+            for (JobGroup &g : b->plan.groups) {
+                if (rc) break;
+                float ms = 0;
+                rc = tune_group(g, fixed_w != 0, tm, &ms);
+                if (!rc) b->group_ms.push_back(ms);
+            }
+            b->info.tuning_launches = tm.launches;
+            tm.release();
+            if (rc) return rc;
+            b->plan.modmuls = 0;
+            for (const JobGroup &g : b->plan.groups)
+                for (const PlannedJob &J : g.jobs) b->plan.modmuls += J.cost * (size_t)J.j.batch;
+        }
         for (JobGroup &g : b->plan.groups) {
-            std::vector<MLayout> cands;
-            for (int nt : {1, 2}) {
-                MfmaShape sh;
-                if (mfma_shape_for(g.shape.K, sh, 16 * nt) && sh.W == g.shape.W && sh.MT == g.shape.MT && sh.NT == nt)
-                    cands.push_back(sh);
-            }
-            if (autotune && cands.size() > 1) {
-                int nt = tuned_nt(g.shape);
-                if (!nt) {
-                    if ((rc = tune_tile(g, cands, &nt))) return rc;
-                    set_tuned_nt(g.shape, nt);
-                }
-                for (const MLayout &c : cands)
-                    if (c.NT == nt) g.shape = c;
-                finish_group(g);
-            }
             std::vector<MJob> js;
             for (const PlannedJob &J : g.jobs) js.push_back(J.j);
             MJob *dj = nullptr;
@@ -329,6 +411,34 @@ int rsa_batch_run(rsa_batch *b, void *hip_stream) {
 int rsa_batch_info_get(const rsa_batch *b, rsa_batch_info *info) {
     if (!b || !info) return fail(RNS_EINVAL, "null argument");
     *info = b->info;
+    return ok();
+}
+
+int rsa_batch_classes(const rsa_batch *b, rsa_batch_class *out, size_t cap, size_t *n) {
+    if (!b || !n || (cap && !out)) return fail(RNS_EINVAL, "null argument");
+    size_t i = 0;
+    for (size_t gi = 0; gi < b->plan.groups.size(); gi++) {
+        const JobGroup &g = b->plan.groups[gi];
+        std::map<int, std::vector<const PlannedJob *>> by_len;   // exponent limbs -> jobs
+        for (const PlannedJob &J : g.jobs) by_len[J.j.exp_limbs].push_back(&J);
+        for (auto it = by_len.rbegin(); it != by_len.rend(); ++it, ++i) {
+            if (i >= cap) continue;
+            const PlannedJob *heavy = *std::max_element(
+                it->second.begin(), it->second.end(),
+                [](const PlannedJob *x, const PlannedJob *y) { return x->cost < y->cost; });
+            rsa_batch_class &c = out[i];
+            c.k = g.shape.K;
+            c.waves = g.shape.W;
+            c.group = g.shape.NM();
+            c.exp_bits = 32 * it->first;
+            c.window = heavy->j.window;
+            c.window_offset = heavy->j.window - heavy->w0;
+            c.jobs = (int)it->second.size();
+            c.tuned = gi < b->group_ms.size() ? 1 : 0;
+            c.launch_ms = gi < b->group_ms.size() ? b->group_ms[gi] : 0.0;
+        }
+    }
+    *n = i;
     return ok();
 }
 

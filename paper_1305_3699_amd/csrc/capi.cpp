@@ -394,7 +394,7 @@ extern "C" {
 
 const char *rns_last_error(void) { return g_err.c_str(); }
 
-int rns_abi_version(void) { return 4; }
+int rns_abi_version(void) { return 5; }
 
 int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out) {
     if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");

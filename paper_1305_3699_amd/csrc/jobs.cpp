@@ -48,7 +48,25 @@ int best_window(const std::vector<uint32_t> &e, int fixed) {
 namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, int> g_tuned_nt;
+std::map<std::tuple<int, int, int, int>, int> g_tuned_dw;
 }  // namespace
+
+int tuned_dw(const MLayout &s, int exp_limbs, bool *known) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned_dw.find(std::make_tuple(s.K, s.W, s.MT, exp_limbs));
+    *known = it != g_tuned_dw.end();
+    return *known ? it->second : 0;
+}
+
+void set_tuned_dw(const MLayout &s, int exp_limbs, int dw) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned_dw[std::make_tuple(s.K, s.W, s.MT, exp_limbs)] = dw;
+}
+
+void set_job_window(PlannedJob &J, int dw) {
+    J.j.window = std::min(6, std::max(1, J.w0 + dw));
+    J.cost = mm_count(*J.hexp, J.j.window);
+}
 
 int tuned_nt(const MLayout &s) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -83,8 +101,11 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
         J.j.out_stride = out_stride;
         J.j.exp_limbs = (int)hx.size();
         J.j.exp_stride = 0;
-        J.j.window = best_window(hx, fixed_w);
-        J.cost = mm_count(hx, J.j.window);
+        J.w0 = best_window(hx, fixed_w);
+        J.hexp = &hx;
+        bool known = false;
+        const int dw = fixed_w ? 0 : tuned_dw(c->mshape, (int)hx.size(), &known);
+        set_job_window(J, dw);
         P.modmuls += J.cost * count;
         P.jobs++;
         const MLayout &sh = c->mshape;

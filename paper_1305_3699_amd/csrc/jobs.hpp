@@ -35,7 +35,9 @@ struct PlannedOp {
 
 struct PlannedJob {
     MJob j;
-    size_t cost;  // Montgomery products per element
+    size_t cost;                          // Montgomery products per element
+    int w0 = 1;                           // window with the fewest products for the exponent
+    const std::vector<uint32_t> *hexp = nullptr;   // host copy of the exponent (owned by the key)
 };
 
 // Jobs of one matrix-core kernel shape: one launch.
@@ -87,6 +89,13 @@ void finish_group(JobGroup &g);
 // Per-process tile choice per (K, W, MT) from the batch autotuner (0: none).
 int tuned_nt(const MLayout &s);
 void set_tuned_nt(const MLayout &s, int nt);
+// Per-process window offset from the batch autotuner for the jobs of shape
+// class (K, W, MT) with exponents of exp_limbs limbs: the window is
+// clamp(w0 + offset, 1, 6); *known = false when none was tuned.
+int tuned_dw(const MLayout &s, int exp_limbs, bool *known);
+void set_tuned_dw(const MLayout &s, int exp_limbs, int dw);
+// Window of job J with offset dw from its own best; updates J.j.window and J.cost.
+void set_job_window(PlannedJob &J, int dw);
 
 // Enqueue one group's launch with device job table d_jobs and window table.
 hipError_t launch_group(const JobGroup &g, const MJob *d_jobs, uint32_t *table, hipStream_t s);

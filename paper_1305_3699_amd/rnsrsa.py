@@ -59,7 +59,14 @@ class BatchOpts(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int), ("jobs", ctypes.c_int), ("garner_launches", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_size_t), ("modmuls", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("modmuls", ctypes.c_size_t),
+                ("tuning_launches", ctypes.c_int)]
+
+
+class BatchClass(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("waves", ctypes.c_int), ("group", ctypes.c_int), ("exp_bits", ctypes.c_int),
+                ("window", ctypes.c_int), ("window_offset", ctypes.c_int), ("jobs", ctypes.c_int),
+                ("tuned", ctypes.c_int), ("launch_ms", ctypes.c_double)]
 
 
 OP_ENCRYPT = 0
@@ -110,6 +117,7 @@ _SIGNATURES = {
     "rsa_batch_create": ([_P, _S, _P, _P, _P], _I),
     "rsa_batch_run": ([_P, _P], _I),
     "rsa_batch_info_get": ([_P, _P], _I),
+    "rsa_batch_classes": ([_P, _P, _S, _P], _I),
     "rsa_batch_free": ([_P], None),
     "rsa_server_create": ([_P, _S, _P, _P], _I),
     "rsa_server_replay": ([_P, _P, _S, _P, _P], _I),
@@ -130,7 +138,7 @@ _SIGNATURES = {
 _lib_handle = None
 
 
-ABI_VERSION = 4           # rns_opts / rns_info layout of include/rnsrsa.h
+ABI_VERSION = 5           # rns_opts / rns_info layout of include/rnsrsa.h
 
 
 def lib():
@@ -555,7 +563,20 @@ class RsaBatch:
         inf = BatchInfo()
         _check(lib().rsa_batch_info_get(self._h, ctypes.byref(inf)))
         return {"launches": inf.launches, "jobs": inf.jobs, "garner_launches": inf.garner_launches,
-                "workspace_bytes": inf.workspace_bytes, "modmuls": inf.modmuls}
+                "workspace_bytes": inf.workspace_bytes, "modmuls": inf.modmuls,
+                "tuning_launches": inf.tuning_launches}
+
+    @property
+    def classes(self) -> list:
+        """rsa_batch_classes: per (kernel shape, exponent length) class, the
+        base size, waves, tile, window and whether the autotuner chose them."""
+        n = ctypes.c_size_t(0)
+        _check(lib().rsa_batch_classes(self._h, None, 0, ctypes.byref(n)))
+        arr = (BatchClass * max(1, n.value))()
+        _check(lib().rsa_batch_classes(self._h, arr, n.value, ctypes.byref(n)))
+        return [{"k": c.k, "waves": c.waves, "group": c.group, "exp_bits": c.exp_bits, "window": c.window,
+                 "window_offset": c.window_offset, "jobs": c.jobs, "tuned": bool(c.tuned),
+                 "launch_ms": round(c.launch_ms, 4)} for c in arr[:n.value]]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -619,6 +619,12 @@ def test_batched_mixed_sizes(use_graph, autotune):
                  use_graph=use_graph)
     info = b.info
     assert info["jobs"] == sum(2 if o.kind == "decrypt" else 1 for o, *_ in items)
+    classes = b.classes
+    assert sum(c["jobs"] for c in classes) == info["jobs"]
+    for c in classes:
+        assert c["tuned"] == autotune and c["group"] in (16, 32) and 1 <= c["window"] <= 6
+        assert c["window_offset"] in ((-1, 0, 1) if autotune else (0,))
+        assert c["exp_bits"] in (32, 512, 1024, 1536, 2048)
     for rep in range(2):                      # a graph is replayed; results must not change
         for *_, out in items:
             out.zero_()

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(rnsrsa.exported_symbols())
-    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 4
+    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 5
 
 
 def _check_bounds(plan, N, L):
@@ -400,6 +400,8 @@ def test_batch_and_server_argument_errors():
     h = ctypes.c_void_p()
     assert lib.rsa_server_create(None, 0, None, ctypes.byref(h)) == -1          # no keys
     assert lib.rsa_batch_create(None, 0, None, None, None) == -1                # null handle
+    n = ctypes.c_size_t(7)
+    assert lib.rsa_batch_classes(None, None, 0, ctypes.byref(n)) == -1           # null batch
     op = rnsrsa.RsaOp(None, 0, None, None, 1)
     assert lib.rsa_batch_create(ctypes.byref(op), 1, None, None, ctypes.byref(h)) == -1   # null key
     assert rnsrsa.REQUEST_DTYPE.itemsize == 32

@@ -93,10 +93,10 @@ enum rns_prime_range {
  *               the channel engine (or RNS_EUNSUPPORTED if the matrix engine
  *               was requested or k = 513, which has no channel kernel).
  *               Full-range draws at k = 257 usually fail it.
- *   engine      rns_engine (0 = auto).  rns_mont_mul_batch and the Garner
- *               step of CRT decryption always use the channel kernels;
- *               k = 513 runs on the matrix engine only (the channel engine
- *               returns RNS_EUNSUPPORTED there).
+ *   engine      rns_engine (0 = auto).  The Garner step of CRT decryption
+ *               always uses the channel kernels; k = 513 runs on the matrix
+ *               engine only (the channel engine returns RNS_EUNSUPPORTED
+ *               there).
  *   group       matrix-core engine: preferred elements per workgroup, 16 or
  *               32, used by every launch (a k without a kernel of that size
  *               uses its default).  0: the default for k, except that a
@@ -216,7 +216,10 @@ int rns_modexp_jobs(const rns_job *jobs, size_t njobs, void *hip_stream);
  *              0..k-1 are B, k..2k-1 are B', 2k is the redundant 2^32 channel.
  *              Each input must be the residue vector of one integer below
  *              (k+1)N; out may alias x or y.
- * Runs the channel kernels: RNS_EUNSUPPORTED for k = 513.
+ * Runs on the context's engine: the matrix cores by default (each element
+ * converted into the kernel's kept representation and back around one
+ * product), the channel kernels when the context asked for them (no channel
+ * kernel for k = 513: RNS_EUNSUPPORTED).  Both give the same residues.
  */
 int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint32_t *out,
                        size_t batch, void *hip_stream);
@@ -270,8 +273,10 @@ int rsa_decrypt(const rsa_key *key, const uint32_t *c, uint32_t *m, size_t batch
 /*
  * rsa_decrypt_noalloc -- rsa_decrypt for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
- * forbid hipMalloc): the same launches and results as rsa_decrypt with the
- * same arguments, but the window tables and the CRT intermediates live in a
+ * forbid hipMalloc): the same kernels and results as rsa_decrypt with the
+ * same arguments (a batch too small to fill the GPU is spread over extra
+ * workgroups only while their window tables fit), but the window tables and
+ * the CRT intermediates live in a
  * fixed array of RSA_NOALLOC_SCRATCH_BYTES bytes that the library holds on
  * each device it runs on (one copy per device, from first use until the
  * process ends).  The call makes no device allocation.

@@ -113,8 +113,9 @@ def build(jobs: int | None = None, verbose: bool = False, sanitize: bool = False
         src = os.path.join(build_dir, "mshape_%d_%d_%d_%d.hip" % (k, w, mt, nt))
         text = ('#include "kernels_mfma.hpp"\nnamespace rnsrsa {\n'
                 "template hipError_t launch_modexp_mfma_t<%d, %d, %d, %d>(const ModexpMfmaLaunch &, hipStream_t);\n"
+                "template hipError_t launch_montmul_mfma_t<%d, %d, %d, %d>(const MontMulMfmaLaunch &, hipStream_t);\n"
                 "template int mfma_blocks_per_cu_t<%d, %d, %d, %d>();\n"
-                "}\n" % (k, w, mt, nt, k, w, mt, nt))
+                "}\n" % (k, w, mt, nt, k, w, mt, nt, k, w, mt, nt))
         if not os.path.exists(src) or open(src).read() != text:
             with open(src, "w") as f:
                 f.write(text)

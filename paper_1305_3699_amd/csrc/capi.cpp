@@ -224,39 +224,55 @@ int check_opts(const rns_opts *o) {
 namespace rnsrsa {
 namespace api {
 
-// Launch one or two exponentiation jobs sharing the inputs.
-MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev) {
+int device_simds(int dev) {
     static std::mutex mu;
     static std::map<int, int> simds_of;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = simds_of.find(dev);
+    if (it == simds_of.end()) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            return 0;
+        it = simds_of.emplace(dev, 4 * cus).first;
+    }
+    return it->second;
+}
+
+MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev) {
     if (sh.NT != 2) return sh;
     MfmaShape alt;
     if (!mfma_shape_for(sh.K, alt, 16) || alt.NT != 1 || alt.W != sh.W || alt.MT != sh.MT) return sh;
-    int simds = 0;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = simds_of.find(dev);
-        if (it == simds_of.end()) {
-            int cus = 0;
-            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-                return sh;
-            it = simds_of.emplace(dev, 4 * cus).first;
-        }
-        simds = it->second;
-    }
+    const int simds = device_simds(dev);
+    if (!simds) return sh;
     return 2 * tiles * (size_t)sh.W < 3 * (size_t)simds ? alt : sh;
 }
 
-// Kernel shape of a plain launch of njobs jobs of `batch` elements on c0.
-static MfmaShape plain_shape(const rns_ctx *c0, int njobs, size_t batch) {
+int spread_tile_elems(const MfmaShape &sh, size_t tiles, int dev) {
+    const int simds = device_simds(dev);
+    int e = sh.NM();
+    while (simds && e > kMinTileElems && tiles * (size_t)sh.W < (size_t)simds) {
+        e /= 2;
+        tiles *= 2;
+    }
+    return e == sh.NM() ? 0 : e;
+}
+
+// Kernel shape and elements per tile of a plain launch of njobs jobs of
+// `batch` elements on c0 (spread: a small launch may use fewer elements per
+// tile, i.e. more workgroups and window tables).
+static MfmaShape plain_shape(const rns_ctx *c0, int njobs, size_t batch, bool spread, int *tile_elems) {
     MfmaShape sh = c0->mshape;
     if (!c0->group_req) sh = auto_tile(sh, (size_t)mfma_tiles(sh, batch) * njobs, c0->device);
+    *tile_elems = spread ? spread_tile_elems(sh, (size_t)mfma_tiles(sh, batch) * njobs, c0->device) : 0;
     return sh;
 }
 
-size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch) {
+size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch, bool spread) {
     if (c0->engine == RNS_ENGINE_MATRIX) {
-        const MfmaShape sh = plain_shape(c0, njobs, batch);
-        return modexp_mfma_table_words(sh, c0->window, (size_t)mfma_tiles(sh, batch) * njobs) * sizeof(uint32_t);
+        int te = 0;
+        const MfmaShape sh = plain_shape(c0, njobs, batch, spread, &te);
+        return modexp_mfma_table_words(sh, c0->window, (size_t)mfma_job_tiles(sh, batch, te) * njobs) *
+               sizeof(uint32_t);
     }
     const BaseSet &bs = *c0->plan.base;
     return modexp_table_words(bs.K, bs.W, c0->window, (batch + 63) / 64 * njobs) * sizeof(uint32_t);
@@ -264,7 +280,7 @@ size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch) {
 
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
-               uint32_t *out1, int out_stride, size_t batch, hipStream_t s, uint32_t *table_buf) {
+               uint32_t *out1, int out_stride, size_t batch, hipStream_t s, uint32_t *table_buf, bool spread) {
     const BaseSet &bs = *c0->plan.base;
     const int njobs = c1 ? 2 : 1;
     ModexpParams P{};
@@ -277,9 +293,10 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
     P.window = c0->window;
     P.batch = (int)batch;
     if (c0->engine == RNS_ENGINE_MATRIX) {
-        const MfmaShape sh = plain_shape(c0, njobs, batch);
+        int te = 0;
+        const MfmaShape sh = plain_shape(c0, njobs, batch, spread, &te);
         ModexpMfmaLaunch a{};
-        const int per_job = mfma_tiles(sh, batch);
+        const int per_job = mfma_job_tiles(sh, batch, te);
         for (int j = 0; j < njobs; j++) {
             const rns_ctx *c = j ? c1 : c0;
             MJob &J = a.inl[j];
@@ -298,13 +315,14 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
             J.exp_stride = exp_stride;
             J.window = c0->window;
             J.tile0 = j * per_job;
+            J.tile_elems = te;
         }
         a.njobs = njobs;
         a.tiles = per_job * njobs;
         a.max_window = c0->window;
         Scratch table;
         if (!table_buf) {
-            int rc = scratch_alloc(table, modexp_scratch_bytes(c0, njobs, batch), s);
+            int rc = scratch_alloc(table, modexp_scratch_bytes(c0, njobs, batch, spread), s);
             if (rc) return rc;
         }
         a.table = table_buf ? table_buf : (uint32_t *)table.p;
@@ -348,11 +366,12 @@ Limbs limbs_of(const uint32_t *p, size_t n) { return bn_from_ptr(p, n); }
 const uint32_t *entry_of(const rns_ctx *c) { return c->engine == RNS_ENGINE_MATRIX ? c->d_mentry : c->d_entry; }
 
 // Both half-size exponentiations of a CRT decryption in one launch.
-int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s, uint32_t *table) {
+int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s, uint32_t *table,
+               bool spread) {
     const int L = (int)key->half;
     const bool m = key->p->engine == RNS_ENGINE_MATRIX;
     return run_modexp(key->p, key->q, m ? key->d_mcentry_p : key->d_centry_p, m ? key->d_mcentry_q : key->d_centry_q,
-                      c, (int)key->n_limbs, key->d_dp, key->d_dq, L, 0, mpq, mpq + L, 2 * L, batch, s, table);
+                      c, (int)key->n_limbs, key->d_dp, key->d_dq, L, 0, mpq, mpq + L, 2 * L, batch, s, table, spread);
 }
 
 // Garner recombination over the p-modulus tables.
@@ -565,6 +584,22 @@ int rns_mont_mul_batch(rns_ctx *ctx, const uint32_t *x, const uint32_t *y, uint3
     if (!x || !y || !out) return fail(RNS_EINVAL, "null buffer");
     if (batch > (size_t)INT32_MAX - 64) return fail(RNS_EINVAL, "batch too large");
     const BaseSet &bs = *ctx->plan.base;
+    if (ctx->engine == RNS_ENGINE_MATRIX) {
+        MfmaShape sh = ctx->mshape;
+        if (!ctx->group_req) sh = auto_tile(sh, (size_t)mfma_tiles(sh, batch), ctx->device);
+        MontMulMfmaLaunch a{};
+        a.mb = ctx->d_mbase;
+        a.mk = ctx->d_mkey;
+        a.x = x;
+        a.y = y;
+        a.out = out;
+        a.batch = (int)batch;
+        a.tile_elems = spread_tile_elems(sh, (size_t)mfma_tiles(sh, batch), ctx->device);
+        a.tiles = mfma_job_tiles(sh, batch, a.tile_elems);
+        hipError_t e = launch_montmul_mfma(sh, a, (hipStream_t)hip_stream);
+        if (e != hipSuccess) return hip_fail(e, "montmul (matrix cores) launch");
+        return ok();
+    }
     if (!channel_kernel(bs.K, bs.W)) return fail(RNS_EUNSUPPORTED, "no single-product kernel for this k");
     MontMulLaunch a{ctx->d_base, ctx->d_mod, x, y, out, (int)batch};
     hipError_t e = launch_montmul(bs.K, bs.W, a, (hipStream_t)hip_stream);

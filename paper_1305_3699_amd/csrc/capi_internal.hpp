@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,11 @@ namespace api {
 
 // Entry table of a context for its own L-limb inputs.
 const uint32_t *entry_of(const rns_ctx *c);
+// The device copy of a base set's matrix-engine table: uploads `blob` on the
+// first request per (base set, device); resident_mfma_base returns it if it
+// is already there (else null).
+int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const std::vector<uint32_t> &blob, uint32_t **out);
+uint32_t *resident_mfma_base(const BaseSet *bs);
 // Garner recombination of [m_p | m_q] rows into m (n_limbs limbs).
 int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s);
 // The Garner launch arguments of that recombination.
@@ -108,21 +114,34 @@ GarnerLaunch garner_launch_of(const rsa_key *key, const uint32_t *mpq, uint32_t 
 // wins; above it the 32-element tile's shared constant loads do (measured for
 // k = 17 .. 129).  Shapes without that alternative are returned unchanged.
 MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev);
+// SIMDs of device dev (4 per compute unit), cached; 0 if unknown.
+int device_simds(int dev);
+// Elements per tile for a matrix-core launch of `tiles` full tiles of shape
+// sh on device dev: 0 (all 16*NT columns) unless the launch would leave
+// SIMDs without a wave; then the largest of 16*NT/2, /4, ... down to
+// kMinTileElems that gives every SIMD a wave.  A workgroup's time does not
+// depend on how many of its columns are real, so on an underfilled GPU
+// spreading the elements over more workgroups shortens the launch.
+int spread_tile_elems(const MfmaShape &sh, size_t tiles, int dev);
 // A context for odd modulus N of L limbs with the default options (smallest
 // base, default engine and tile).  Owned by the caller (delete).
 int make_context(const Limbs &N, int L, rns_ctx **out);
 // One or two exponentiation jobs sharing their inputs (the plain launch).
-// table_buf: device scratch of modexp_scratch_bytes(c0, njobs, batch) bytes
-// for the window tables, or null to allocate it stream-ordered.
+// table_buf: device scratch of modexp_scratch_bytes(c0, njobs, batch, spread)
+// bytes for the window tables, or null to allocate it stream-ordered.
+// spread: a launch too small to give every SIMD a wave may use fewer
+// elements per workgroup (more workgroups, more window-table scratch).
 int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const uint32_t *E1, const uint32_t *in,
                int in_limbs, const uint32_t *x0, const uint32_t *x1, int exp_limbs, int exp_stride, uint32_t *out0,
-               uint32_t *out1, int out_stride, size_t batch, hipStream_t s, uint32_t *table_buf = nullptr);
+               uint32_t *out1, int out_stride, size_t batch, hipStream_t s, uint32_t *table_buf = nullptr,
+               bool spread = true);
 // Window-table bytes of a plain launch of njobs (1 or 2) jobs of `batch`
 // elements on c0 (same base, window and tile for both jobs).
-size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch);
-// Both halves of a CRT decryption in one launch into mpq (table as run_modexp).
+size_t modexp_scratch_bytes(const rns_ctx *c0, int njobs, size_t batch, bool spread = true);
+// Both halves of a CRT decryption in one launch into mpq (table and spread as
+// run_modexp).
 int crt_halves(const rsa_key *key, const uint32_t *c, uint32_t *mpq, size_t batch, hipStream_t s,
-               uint32_t *table = nullptr);
+               uint32_t *table = nullptr, bool spread = true);
 
 }  // namespace api
 }  // namespace rnsrsa

@@ -180,11 +180,15 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
 void finish_group(JobGroup &g) {
     std::stable_sort(g.jobs.begin(), g.jobs.end(),
                      [](const PlannedJob &x, const PlannedJob &y) { return x.cost > y.cost; });
+    size_t full = 0;
+    for (const PlannedJob &J : g.jobs) full += (size_t)mfma_tiles(g.shape, (size_t)J.j.batch);
+    const int te = spread_tile_elems(g.shape, full, g.device);
     g.tiles = 0;
     g.max_window = 1;
     for (PlannedJob &J : g.jobs) {
         J.j.tile0 = g.tiles;
-        g.tiles += mfma_tiles(g.shape, (size_t)J.j.batch);
+        J.j.tile_elems = te;
+        g.tiles += mfma_job_tiles(g.shape, (size_t)J.j.batch, te);
         g.max_window = std::max(g.max_window, J.j.window);
     }
 }

@@ -72,14 +72,16 @@ struct MontMulLaunch {
 // One exponentiation job of the matrix-core kernel: `batch` elements
 // out[i] = in[i]^exp mod N with the tables of one modulus: mb the
 // key-independent table and mk the per-modulus table (plan_mfma.hpp), E the
-// entry table of in_limbs rows.  tile0 is the job's first tile (group of
-// 16*NT elements) in its launch.
+// entry table of in_limbs rows.  tile0 is the job's first tile in its
+// launch; each tile serves tile_elems consecutive elements (0: all 16*NT
+// columns of the workgroup; fewer spread a small job over more workgroups,
+// the other columns computing values that are not stored).
 struct MJob {
     const uint32_t *mb, *mk, *E, *exp, *in;
     uint32_t *out;
     int batch, in_limbs, in_stride, L, out_stride, exp_limbs, exp_stride, window;
     int tile0;
-    int unused;
+    int tile_elems;
 };
 
 // A launch of the matrix-core kernel: njobs jobs of one shape, from the
@@ -93,12 +95,28 @@ struct ModexpMfmaLaunch {
     uint32_t *table;     // scratch: modexp_mfma_table_words(shape, max_window, tiles) words
 };
 
+// One RNS Montgomery product per element on the matrix cores (the
+// standalone product): residues channel-major, [2K+1][batch], plain.
+struct MontMulMfmaLaunch {
+    const uint32_t *mb, *mk;
+    const uint32_t *x, *y;
+    uint32_t *out;
+    int batch;
+    int tiles;        // workgroups launched
+    int tile_elems;   // elements per workgroup (0: 16*NT)
+};
+
 size_t modexp_table_words(int K, int W, int window, size_t workgroups);
 size_t modexp_mfma_table_words(const MLayout &shape, int max_window, size_t workgroups);
 int mfma_tiles(const MLayout &shape, size_t elements);
+// Tiles of a job of `elements` elements at tile_elems per tile (0: 16*NT).
+int mfma_job_tiles(const MLayout &shape, size_t elements, int tile_elems);
+// Fewest elements a tile is given when a small launch is spread out.
+constexpr int kMinTileElems = 4;
 bool mfma_supported(int K);
 int mfma_blocks_per_cu(const MLayout &shape);
 hipError_t launch_modexp_mfma(const MLayout &shape, const ModexpMfmaLaunch &a, hipStream_t s);
+hipError_t launch_montmul_mfma(const MLayout &shape, const MontMulMfmaLaunch &a, hipStream_t s);
 hipError_t launch_modexp(int K, int W, const ModexpLaunch &a, hipStream_t s);
 hipError_t launch_garner(int K, int W, const GarnerLaunch &a, hipStream_t s);
 // Grouped Garner steps: `tiles` workgroups over njobs jobs (device table).

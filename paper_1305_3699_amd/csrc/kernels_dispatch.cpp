@@ -26,8 +26,11 @@ template <int K, int W, int MT, int NT>
 hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s);
 template <int K, int W, int MT, int NT>
 int mfma_blocks_per_cu_t();
+template <int K, int W, int MT, int NT>
+hipError_t launch_montmul_mfma_t(const MontMulMfmaLaunch &a, hipStream_t s);
 #define RNSRSA_MSHAPE(k, w, mt, nt) \
     extern template hipError_t launch_modexp_mfma_t<k, w, mt, nt>(const ModexpMfmaLaunch &, hipStream_t); \
+    extern template hipError_t launch_montmul_mfma_t<k, w, mt, nt>(const MontMulMfmaLaunch &, hipStream_t); \
     extern template int mfma_blocks_per_cu_t<k, w, mt, nt>();
 #include "kernel_configs_mfma.inc"
 #undef RNSRSA_MSHAPE
@@ -46,6 +49,11 @@ size_t modexp_mfma_table_words(const MLayout &s, int max_window, size_t workgrou
 
 int mfma_tiles(const MLayout &s, size_t elements) { return (int)((elements + s.NM() - 1) / s.NM()); }
 
+int mfma_job_tiles(const MLayout &s, size_t elements, int tile_elems) {
+    const size_t e = tile_elems > 0 && tile_elems < s.NM() ? (size_t)tile_elems : (size_t)s.NM();
+    return (int)((elements + e - 1) / e);
+}
+
 int mfma_blocks_per_cu(const MLayout &sh) {
 #define RNSRSA_MSHAPE(k, w, mt, nt) \
     if (sh.K == k && sh.W == w && sh.MT == mt && sh.NT == nt) return mfma_blocks_per_cu_t<k, w, mt, nt>();
@@ -57,6 +65,14 @@ int mfma_blocks_per_cu(const MLayout &sh) {
 hipError_t launch_modexp_mfma(const MLayout &sh, const ModexpMfmaLaunch &a, hipStream_t s) {
 #define RNSRSA_MSHAPE(k, w, mt, nt) \
     if (sh.K == k && sh.W == w && sh.MT == mt && sh.NT == nt) return launch_modexp_mfma_t<k, w, mt, nt>(a, s);
+#include "kernel_configs_mfma.inc"
+#undef RNSRSA_MSHAPE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_montmul_mfma(const MLayout &sh, const MontMulMfmaLaunch &a, hipStream_t s) {
+#define RNSRSA_MSHAPE(k, w, mt, nt) \
+    if (sh.K == k && sh.W == w && sh.MT == mt && sh.NT == nt) return launch_montmul_mfma_t<k, w, mt, nt>(a, s);
 #include "kernel_configs_mfma.inc"
 #undef RNSRSA_MSHAPE
     return hipErrorInvalidValue;

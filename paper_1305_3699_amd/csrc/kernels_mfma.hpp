@@ -458,10 +458,16 @@ __device__ __forceinline__ uint32_t mexp_digit(const gu32 *__restrict__ e, int n
     return (uint32_t)(v >> sh) & ((1u << w) - 1u);
 }
 
+// Elements the tile of job J serves: its first tile_elems columns (all 16*NT
+// when tile_elems is 0).
+__device__ __forceinline__ int mjob_tile_elems(const MJob &J, int NM) {
+    return J.tile_elems > 0 && J.tile_elems < NM ? J.tile_elems : NM;
+}
+
 // End of the exit on wave 0, lane n (element n of the tile, message msg):
 // acc holds the L+1 limbs of sum_j xi'_j M'_j; subtracts alpha M', takes the
 // canonical representative mod N by conditional subtractions of N 2^b, and
-// stores the L limbs.
+// stores the L limbs (columns beyond the tile's elements store nothing).
 template <int K, int W, int MT, int NT>
 __device__ __forceinline__ void mfma_exit_tail(const gu32 *__restrict__ mb, const gu32 *__restrict__ mk, uint32_t *acc,
                                                uint32_t *tmp, uint32_t alpha, int L, int n, int msg, const MJob &J,
@@ -494,30 +500,22 @@ __device__ __forceinline__ void mfma_exit_tail(const gu32 *__restrict__ mb, cons
         if (!borrow)
             for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
     }
-    if (msg < J.batch)
+    if (msg < J.batch && n < mjob_tile_elems(J, NM))
         for (int l = 0; l < L; l++) out[(size_t)msg * J.out_stride + l] = acc[l * NM + n];
 }
 
-// One tile (16*NT elements) of exponentiation job J, elements
-// [e0, e0 + 16*NT) of the job, with window table slot `slot` of the launch;
-// ylds: the operand prefetch buffer (S::PF_WORDS words, if S::PREFETCH).
+// Workgroup set-up shared by the kernels of the matrix-core engine: the
+// constant digit rows of both exchange buffers (channel K holds the offset
+// digit 1, the channels after it zero) and the per-lane constants of C (tiles
+// in registers, LDS or global memory, per-slot constants, scalars).
 template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t *__restrict__ lds,
-                                                 uint32_t *__restrict__ table, size_t slot, int max_window,
-                                                 uint32_t *__restrict__ ylds) {
+__device__ __forceinline__ void mfma_setup(const gu32 *__restrict__ mb, const gu32 *__restrict__ mk,
+                                           uint32_t *__restrict__ lds, int wave, int lane,
+                                           MConstOf<K, W, MT, NT> &C) {
     using S = MShp<K, W, MT, NT>;
     uint32_t *buf1 = lds;
     uint32_t *buf2 = lds + S::NM * S::BROW;
-    const gu32 *__restrict__ mb = (const gu32 *)J.mb;
-    const gu32 *__restrict__ mk = (const gu32 *)J.mk;
-    const gu32 *__restrict__ E = (const gu32 *)J.E;
-    const gu32 *__restrict__ ex = (const gu32 *)J.exp;
-    const gu32 *__restrict__ in = (const gu32 *)J.in;
-    gu32 *__restrict__ out = (gu32 *)J.out;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
-
     // constant digit rows: channel K holds the offset digit 1, the rest zero
     for (int i = threadIdx.x; i < S::NM * (S::BROW - K); i += 64 * W) {
         const int n = i / (S::BROW - K), c = K + i % (S::BROW - K);
@@ -527,7 +525,6 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     }
 
     // per-lane constants
-    MConstOf<K, W, MT, NT> C;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
         const size_t sl = (size_t)wave * MT + mt;
@@ -584,6 +581,32 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
         C.kf[b] = 1 << (8 * b);
         asm volatile("" : "+s"(C.kf[b]));
     }
+
+}
+
+// One tile of exponentiation job J: columns n < 16*NT hold elements e0 + n
+// of the job (those with n < mjob_tile_elems(J) are stored), with window
+// table slot `slot` of the launch;
+// ylds: the operand prefetch buffer (S::PF_WORDS words, if S::PREFETCH).
+template <int K, int W, int MT, int NT>
+__device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t *__restrict__ lds,
+                                                 uint32_t *__restrict__ table, size_t slot, int max_window,
+                                                 uint32_t *__restrict__ ylds) {
+    using S = MShp<K, W, MT, NT>;
+    uint32_t *buf1 = lds;
+    uint32_t *buf2 = lds + S::NM * S::BROW;
+    const gu32 *__restrict__ mb = (const gu32 *)J.mb;
+    const gu32 *__restrict__ mk = (const gu32 *)J.mk;
+    const gu32 *__restrict__ E = (const gu32 *)J.E;
+    const gu32 *__restrict__ ex = (const gu32 *)J.exp;
+    const gu32 *__restrict__ in = (const gu32 *)J.in;
+    gu32 *__restrict__ out = (gu32 *)J.out;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+
+    MConstOf<K, W, MT, NT> C;
+    mfma_setup<K, W, MT, NT>(mb, mk, lds, wave, lane, C);
 
     // entry: residues of Z = sum_h X_h Y_h in the kept representation
     MState<MT, NT> a;
@@ -868,7 +891,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
             if (!borrow)
                 for (int l = 0; l <= L; l++) acc[l * NM + n] = tmp[l * NM + n];
         }
-        if (msg < J.batch)
+        if (msg < J.batch && n < mjob_tile_elems(J, NM))
             for (int l = 0; l < L; l++) out[(size_t)msg * J.out_stride + l] = acc[l * NM + n];
     } else {
         __syncthreads();
@@ -949,13 +972,100 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A)
     } else {
         J = (A.njobs > 1 && tile >= A.inl[1].tile0) ? A.inl[1] : A.inl[0];
     }
-    modexp_mfma_tile<K, W, MT, NT>(J, (tile - J.tile0) * S::NM, lds, A.table, blockIdx.x, A.max_window, ylds);
+    modexp_mfma_tile<K, W, MT, NT>(J, (tile - J.tile0) * mjob_tile_elems(J, S::NM), lds, A.table, blockIdx.x,
+                                   A.max_window, ylds);
 }
 
 template <int K, int W, int MT, int NT>
 hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s) {
     if (a.tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT>), dim3((unsigned)a.tiles), dim3(64 * W), 0, s, a);
+    return hipGetLastError();
+}
+
+// One RNS Montgomery product per element on the matrix cores, for the
+// standalone call: residues in and out channel-major ([2K+1][batch]: B, B',
+// then the redundant channel), plain (each lane converts its slots to the
+// kept representation and back with the base table's conversion factors).
+// Workgroup t serves elements [t*E, (t+1)*E), E = A.tile_elems (0: 16*NT).
+template <int K, int W, int MT, int NT>
+__global__ __launch_bounds__(64 * W) void montmul_mfma_kernel(MontMulMfmaLaunch A) {
+    using S = MShp<K, W, MT, NT>;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
+    const gu32 *__restrict__ mb = (const gu32 *)A.mb;
+    const gu32 *__restrict__ mk = (const gu32 *)A.mk;
+    const gu32 *__restrict__ x = (const gu32 *)A.x;
+    const gu32 *__restrict__ y = (const gu32 *)A.y;
+    gu32 *__restrict__ out = (gu32 *)A.out;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    MConstOf<K, W, MT, NT> C;
+    mfma_setup<K, W, MT, NT>(mb, mk, lds, wave, lane, C);
+    const int te = A.tile_elems > 0 && A.tile_elems < S::NM ? A.tile_elems : S::NM;
+    const size_t B = (size_t)A.batch;
+    int elem[NT];
+    bool ok[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        const int n = 16 * nt + (lane & 15);
+        elem[nt] = (int)blockIdx.x * te + n;
+        ok[nt] = n < te && elem[nt] < A.batch;
+    }
+    MState<MT, NT> a, b;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const size_t sl = (size_t)wave * MT + mt;
+        const int ch = wave * S::CH + 4 * mt + g;
+        const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+        const uint32_t inB = mb[S::LY.mmconv() + (sl * 3 + 0) * 64 + lane];
+        const uint32_t inP = mb[S::LY.mmconv() + (sl * 3 + 1) * 64 + lane];
+        const MSlotB sb = C.slotB(mt);
+        const MSlotP sp = C.slotP(mt);
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const bool ld = real && ok[nt];
+            const size_t e = (size_t)elem[nt];
+            a.b[mt][nt] = mulredc(ld ? x[(size_t)ch * B + e] : 0u, inB, sb.m, sb.u);   // x R mod m
+            b.b[mt][nt] = mulredc(ld ? y[(size_t)ch * B + e] : 0u, inB, sb.m, sb.u);
+            a.p[mt][nt] = mulredc(ld ? x[(size_t)(K + ch) * B + e] : 0u, inP, sp.m, sp.u);   // x R M^-1 mod m'
+            b.p[mt][nt] = mulredc(ld ? y[(size_t)(K + ch) * B + e] : 0u, inP, sp.m, sp.u);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        a.r[nt] = ok[nt] ? x[(size_t)2 * K * B + elem[nt]] : 0u;
+        b.r[nt] = ok[nt] ? y[(size_t)2 * K * B + elem[nt]] : 0u;
+    }
+    uint32_t *buf1 = lds;
+    uint32_t *buf2 = lds + S::NM * S::BROW;
+    mfma_mm<K, W, MT, NT>(C, a, b, buf1, buf2, wave, lane, true);
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+        const size_t sl = (size_t)wave * MT + mt;
+        const int ch = wave * S::CH + 4 * mt + g;
+        const bool real = (4 * mt + g != 4 * MT - 1) && ch < K;
+        const uint32_t outP = mb[S::LY.mmconv() + (sl * 3 + 2) * 64 + lane];
+        const MSlotB sb = C.slotB(mt);
+        const MSlotP sp = C.slotP(mt);
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            if (!real || !ok[nt]) continue;
+            const size_t e = (size_t)elem[nt];
+            out[(size_t)ch * B + e] = mulredc(a.b[mt][nt], 1u, sb.m, sb.u);
+            out[(size_t)(K + ch) * B + e] = mulredc(a.p[mt][nt], outP, sp.m, sp.u);
+        }
+    }
+    if (wave == 0 && g == 0)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++)
+            if (ok[nt]) out[(size_t)2 * K * B + elem[nt]] = a.r[nt];
+}
+
+template <int K, int W, int MT, int NT>
+hipError_t launch_montmul_mfma_t(const MontMulMfmaLaunch &a, hipStream_t s) {
+    if (a.tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((montmul_mfma_kernel<K, W, MT, NT>), dim3((unsigned)a.tiles), dim3(64 * W), 0, s, a);
     return hipGetLastError();
 }
 

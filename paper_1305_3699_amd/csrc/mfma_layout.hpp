@@ -76,7 +76,11 @@ struct MLayout {
     constexpr size_t MpL() const { return mplo() + K; }                        // [K][K+1] limbs of M'_j
     constexpr size_t MpF() const { return MpL() + (size_t)K * (K + 1); }        // [K+1] limbs of M'
     constexpr size_t bscal() const { return MpF() + K + 1; }                   // [4] M'^-1, M^-1 mod 2^32
-    constexpr size_t base_size() const { return bscal() + 4; }
+    // [W][MT][3][64] conversions of the standalone product between plain
+    // residues and the kept representation: R^2 mod m (into B), R^2 M^-1 mod m'
+    // (into B'), M mod m' (out of B'; out of B is a REDC by 1)
+    constexpr size_t mmconv() const { return bscal() + 4; }
+    constexpr size_t base_size() const { return mmconv() + (size_t)W * MT * 3 * 64; }
     // per-modulus table
     constexpr size_t a1() const { return 0; }                                  // [W][MT][KSTEPS][64][4] first extension
     constexpr size_t slotC() const { return tiles(); }                         // [W][MT][64] c_i

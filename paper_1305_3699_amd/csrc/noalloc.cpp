@@ -57,15 +57,26 @@ int rsa_decrypt_noalloc(const rsa_key *key, const uint32_t *c, uint32_t *m, size
     hipStream_t s = (hipStream_t)hip_stream;
     const rns_ctx *x = nullptr;
     size_t mpq_bytes = 0, table_bytes = 0;
+    // a small batch is spread over extra workgroups (as rsa_decrypt does)
+    // only while their window tables still fit the array
+    bool spread = true;
     if (use_crt) {
         if (!key->has_crt) return fail(RNS_EINVAL, "key has no CRT parts");
         mpq_bytes = round_up(batch * 2 * key->half * sizeof(uint32_t), 256);
-        table_bytes = modexp_scratch_bytes(key->p, 2, batch);
+        table_bytes = modexp_scratch_bytes(key->p, 2, batch, spread);
+        if (mpq_bytes + table_bytes > kNoallocScratchBytes) {
+            spread = false;
+            table_bytes = modexp_scratch_bytes(key->p, 2, batch, spread);
+        }
     } else {
         if (!key->d_d) return fail(RNS_EINVAL, "key has no private exponent");
         if (!key->n) return fail(RNS_EUNSUPPORTED, "CRT-only key: no context for the full modulus");
         x = key->n;
-        table_bytes = modexp_scratch_bytes(x, 1, batch);
+        table_bytes = modexp_scratch_bytes(x, 1, batch, spread);
+        if (table_bytes > kNoallocScratchBytes) {
+            spread = false;
+            table_bytes = modexp_scratch_bytes(x, 1, batch, spread);
+        }
     }
     if (mpq_bytes + table_bytes > kNoallocScratchBytes)
         return fail(RNS_EINVAL, "batch of " + std::to_string(batch) + " needs " +
@@ -83,12 +94,12 @@ int rsa_decrypt_noalloc(const rsa_key *key, const uint32_t *c, uint32_t *m, size
     if ((rc = check_inputs(key, c, batch, s))) return rc;
     if (!use_crt) {
         rc = run_modexp(x, nullptr, entry_of(x), nullptr, c, x->plan.L, key->d_d, nullptr, (int)key->n_limbs, 0, m,
-                        nullptr, x->plan.L, batch, s, base);
+                        nullptr, x->plan.L, batch, s, base, spread);
         return rc ? rc : ok();
     }
     uint32_t *mpq = base;
     uint32_t *table = base + mpq_bytes / sizeof(uint32_t);
-    if ((rc = crt_halves(key, c, mpq, batch, s, table))) return rc;
+    if ((rc = crt_halves(key, c, mpq, batch, s, table, spread))) return rc;
     if ((rc = crt_combine(key, mpq, m, batch, s))) return rc;
     return ok();
 }

@@ -181,6 +181,16 @@ MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh, bool with_ba
     for (int l = 0; l <= K && l < (int)bs.Mp.size(); l++) out.base[ly.MpF() + l] = bs.Mp[l];
     out.base[ly.bscal() + 0] = inv2_32(bn_low(bs.Mp));
     out.base[ly.bscal() + 1] = inv2_32(bn_low(bs.M));
+    const size_t fc = (size_t)3 * 64;      // [W][MT][3][64]
+    fill_slots(sh, out.base.data() + ly.mmconv() + 0 * 64, fc,
+               [&](int t) -> uint32_t { return okc(t) ? pow2_64_mod(bs.B[t]) : 0; });
+    fill_slots(sh, out.base.data() + ly.mmconv() + 1 * 64, fc, [&](int t) -> uint32_t {
+        if (!okc(t)) return 0;
+        const uint32_t m = bs.Bp[t];
+        return mulmod32(pow2_64_mod(m), invmod32(prod_mod32(bs.B, m), m), m);
+    });
+    fill_slots(sh, out.base.data() + ly.mmconv() + 2 * 64, fc,
+               [&](int t) -> uint32_t { return okc(t) ? prod_mod32(bs.B, bs.Bp[t]) : 0; });
     }
 
     // key: c_i = -N^-1 M_i^-1 mod m_i; "one" = M mod N in the kept representation

@@ -61,14 +61,15 @@ int ensure_pinned(uint32_t **p, size_t *have, size_t need) {
 }
 
 // Device bytes a dispatch needs for `count` requests of one (key, kind),
-// with window tables sized for the widest window (2^6 entries).
+// with window tables sized for the widest window (2^6 entries) and the
+// fewest elements per tile (a small launch is spread over more tiles).
 size_t op_bytes(const rsa_key *k, int kind, size_t count) {
     size_t words = 2 * count * k->n_limbs + op_mpq_words(k, kind, count);
     const bool crt = kind == RSA_OP_DECRYPT && k->has_crt;
     const rns_ctx *ctxs[2] = {crt ? k->p : k->n, crt ? k->q : nullptr};
     for (const rns_ctx *c : ctxs) {
         if (!c || c->engine != RNS_ENGINE_MATRIX) continue;
-        words += modexp_mfma_table_words(c->mshape, 6, (size_t)mfma_tiles(c->mshape, count));
+        words += modexp_mfma_table_words(c->mshape, 6, (size_t)mfma_job_tiles(c->mshape, count, kMinTileElems));
     }
     // job descriptors (two exponentiations and a Garner step at most), plus
     // the alignment of the arena's regions (inputs, outputs, CRT scratch, one

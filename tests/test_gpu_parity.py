@@ -187,19 +187,24 @@ def test_rsa2048_crt_both_engines(engine, group):
 
 
 def _indep_base(k: int, seed: int) -> list:
-    """2k seeded channel primes from [2^32 - 2^24, 2^32) drawn here (B first,
-    then B'), handed to the library through opts.primes, so the expected
-    residues do not depend on the library's own choice of base."""
-    return gen.rns_primes(2 * k, seed=seed, lo=(1 << 32) - (1 << 24))
+    """2k seeded channel primes from [2^32 - 2^24, 2^32 - 2^19) drawn here (B
+    first, then B'), handed to the library through opts.primes, so the
+    expected residues do not depend on the library's own choice of base (the
+    upper end keeps B' primes inside the matrix engine's one-step reduction
+    bound up to k = 513; both engines take such a base)."""
+    return gen.rns_primes(2 * k, seed=seed, lo=(1 << 32) - (1 << 24), hi=(1 << 32) - (1 << 19))
 
 
-def test_mont_mul_matches_definition():
+@pytest.mark.parametrize("engine", [1, 2])
+def test_mont_mul_matches_definition(engine):
+    """The standalone product on both engines (channel kernels, matrix cores)
+    against its definition, 200 elements (12 tiles and a ragged tail)."""
     rng = random.Random(3)
     N = rng.getrandbits(1024) | (1 << 1023) | 1
     k = 33
     pr = _indep_base(k, seed=gen.config_seed(6, 4))
-    ctx = _ctx(N, 32, primes=pr)
-    assert ctx.info["k"] == k and ctx.primes == pr
+    ctx = _ctx(N, 32, primes=pr, engine=engine)
+    assert ctx.info["k"] == k and ctx.primes == pr and ctx.info["engine"] == engine
     B, Bp = pr[:k], pr[k:]
     n = 200
     X = [rng.randrange((k + 1) * N) for _ in range(n - 2)] + [0, (k + 1) * N - 1]
@@ -214,15 +219,16 @@ def test_mont_mul_matches_definition():
     assert np.array_equal(out, want)
 
 
-@pytest.mark.parametrize("k", [97, 129])
-def test_mont_mul_3072_bit(k):
+@pytest.mark.parametrize("k,engine", [(97, 1), (97, 2), (129, 1), (129, 2)])
+def test_mont_mul_3072_bit(k, engine):
     """The standalone product at the modulus size of the modular
-    multiplication benchmark (3072 bits), with 97 and 129 channels."""
+    multiplication benchmark (3072 bits), with 97 and 129 channels, on both
+    engines."""
     rng = random.Random(k)
     N = rng.getrandbits(3072) | (1 << 3071) | 1
     pr = _indep_base(k, seed=gen.config_seed(6, 4) + k)
-    ctx = _ctx(N, 96, primes=pr)
-    assert ctx.info["k"] == k and ctx.primes == pr
+    ctx = _ctx(N, 96, primes=pr, engine=engine)
+    assert ctx.info["k"] == k and ctx.primes == pr and ctx.info["engine"] == engine
     B, Bp = pr[:k], pr[k:]
     n = 70
     X = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [(k + 1) * N - 1]
@@ -277,8 +283,7 @@ def test_modexp_16384_bit():
     """16384-bit moduli on bases of 512 + 1 channels (k = 513, the matrix
     engine alone): 20 bases (a full 16-element tile and a ragged one)
     including 0, 1, N - 1 and 2^16384 - 1 with a 64-bit exponent, and with
-    per-element 40-bit exponents; the channel engine and the single-product
-    kernel refuse this base."""
+    per-element 40-bit exponents; the channel engine refuses this base."""
     from paper_1305_3699_amd import ENGINE_CHANNEL, ENGINE_MATRIX, RnsError
     rng = random.Random(16384)
     N = rng.getrandbits(16384) | (1 << 16383) | 1
@@ -292,9 +297,6 @@ def test_modexp_16384_bit():
     assert np.array_equal(_run_modexp(ctx, bases, ex), oracle.modexp_batch(bases, ex, nl))
     with pytest.raises(RnsError) as err:
         _ctx(N, 512, engine=ENGINE_CHANNEL)
-    assert err.value.status == -8
-    with pytest.raises(RnsError) as err:
-        ctx.mont_mul(_dev(np.zeros((2 * 513 + 1, 1), np.uint32)), _dev(np.zeros((2 * 513 + 1, 1), np.uint32)))
     assert err.value.status == -8
 
 
@@ -371,18 +373,41 @@ def test_probe_alu_rates():
         assert 0.25 * 39.3e12 < v.value <= 1.02 * 39.3e12, (op, v.value)
 
 
-def test_mont_mul_8192_bit():
-    """The standalone product at 8192 bits (k = 257, channel kernels)."""
+@pytest.mark.parametrize("engine", [1, 2])
+def test_mont_mul_8192_bit(engine):
+    """The standalone product at 8192 bits (k = 257) on both engines."""
     rng = random.Random(257)
     N = rng.getrandbits(8192) | (1 << 8191) | 1
     k = 257
     pr = _indep_base(k, seed=gen.config_seed(6, 4) + k)
-    ctx = _ctx(N, 256, primes=pr)
-    assert ctx.info["k"] == k and ctx.primes == pr
+    ctx = _ctx(N, 256, primes=pr, engine=engine)
+    assert ctx.info["k"] == k and ctx.primes == pr and ctx.info["engine"] == engine
     B, Bp = pr[:k], pr[k:]
     n = 70
     X = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [(k + 1) * N - 1]
     Y = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [0]
+
+    def res(vals):
+        return np.array([[v % m for v in vals] for m in B] + [[v % m for v in vals] for m in Bp]
+                        + [[v % (1 << 32) for v in vals]], dtype=np.uint32)
+
+    out = _host(ctx.mont_mul(_dev(res(X)), _dev(res(Y))))
+    assert np.array_equal(out, res([rns_ref.mont_mul(x, y, N, B) for x, y in zip(X, Y)]))
+
+
+def test_mont_mul_16384_bit():
+    """The standalone product at 16384 bits (k = 513, matrix cores only),
+    20 elements: a full 16-element tile and a ragged one."""
+    rng = random.Random(513)
+    N = rng.getrandbits(16384) | (1 << 16383) | 1
+    k = 513
+    pr = _indep_base(k, seed=gen.config_seed(6, 4) + k)
+    ctx = _ctx(N, 512, primes=pr)
+    assert ctx.info["k"] == k and ctx.primes == pr and ctx.info["engine"] == 2
+    B, Bp = pr[:k], pr[k:]
+    n = 20
+    X = [rng.randrange((k + 1) * N) for _ in range(n - 1)] + [(k + 1) * N - 1]
+    Y = [rng.randrange((k + 1) * N) for _ in range(n - 2)] + [0, (k + 1) * N - 1]
 
     def res(vals):
         return np.array([[v % m for v in vals] for m in B] + [[v % m for v in vals] for m in Bp]

@@ -47,7 +47,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           # matrix-core results land in VGPRs (no accumulator-register copies)
           "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-command-line-argument", "-I", INC, "-I", CSRC]
-HOST_SOURCES = ["capi.cpp", "noalloc.cpp", "batch.cpp", "jobs.cpp", "server.cpp", "keygen.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp",
+HOST_SOURCES = ["capi.cpp", "noalloc.cpp", "mr_gpu.cpp", "batch.cpp", "jobs.cpp", "server.cpp", "keygen.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp",
                 "emul_mfma.cpp", "kernels_dispatch.cpp", "verify.cpp", "probe.cpp", "range.cpp"]
 
 

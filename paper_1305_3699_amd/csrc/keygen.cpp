@@ -17,6 +17,7 @@
 #include "bn_host.hpp"
 #include "jobs.hpp"
 #include "kernels_impl.hpp"
+#include "mr_gpu.hpp"
 
 using namespace rnsrsa;
 using namespace rnsrsa::api;
@@ -363,8 +364,15 @@ int rsa_miller_rabin(const uint32_t *cand, size_t count, int limbs, const uint32
             }
             c.d.resize((size_t)L, 0u);
         }
-        // one context per candidate, built on a pool of host threads (each
-        // on the caller's device); errors are reported on this thread
+        // every candidate's tables built on the device when its base runs on
+        // the matrix engine (the default bases do)
+        {
+            const int grc = miller_rabin_gpu(cand, count, L, bases, rounds, verdict, s);
+            if (grc != RNS_EUNSUPPORTED) return grc ? grc : ok();
+        }
+        // otherwise one context per candidate, built on a pool of host
+        // threads (each on the caller's device); errors are reported on this
+        // thread
         int dev = 0;
         hipError_t de = hipGetDevice(&dev);
         if (de != hipSuccess) return hip_fail(de, "hipGetDevice");

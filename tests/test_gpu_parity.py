@@ -804,6 +804,31 @@ def test_miller_rabin_small_cases():
         assert mr(n, bases, limbs) == int(primality.miller_rabin(n, bases))
 
 
+def test_miller_rabin_channel_primes():
+    """Candidates that share a factor with the RNS base the Miller-Rabin
+    step runs on (the default base for candidates of their length, taken
+    here from a context on the largest such value): a channel prime itself
+    (prime), and products with channel primes (composite); mixed into one
+    call with ordinary candidates."""
+    from paper_1305_3699_amd import RnsContext, miller_rabin
+    for limbs in (1, 2):
+        ctx = RnsContext((1 << (32 * limbs)) - 1, limbs)
+        pr = ctx.primes
+        k = len(pr) // 2
+        ctx.close()
+        if limbs == 1:
+            cands = [pr[0], pr[k - 1], pr[k], pr[-1], 4294967291, 4294967279]
+        else:
+            cands = [pr[0] * pr[1], pr[k] * pr[-1], 3 * pr[0], pr[1] * 4294967291,
+                     (1 << 61) - 1, (1 << 64) - 59]
+        rng = random.Random(limbs)
+        bases = [[rng.randrange(2, n - 1) for _ in range(3)] for n in cands]
+        got = miller_rabin(gen.to_limbs(cands, limbs), np.stack([gen.to_limbs(b, limbs) for b in bases]))
+        want = [int(primality.miller_rabin(n, b)) for n, b in zip(cands, bases)]
+        assert [int(v) for v in got] == want
+        assert want[:4] == ([1] * 4 if limbs == 1 else [0] * 4)
+
+
 @pytest.mark.parametrize("bits,count", [(1024, 1500), (2048, 2500)])
 def test_keygen_agrees_with_oracle(bits, count):
     """RSA key generation from two seeded candidate streams: the primes the

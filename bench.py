@@ -32,7 +32,8 @@ PEAK_I8_OPS_PER_S = 5.0e15
 ENGINE_NAMES = {1: "channel", 2: "matrix"}
 KERNEL_SOURCES = ["paper_1305_3699_amd/csrc/kernels_impl.hpp", "paper_1305_3699_amd/csrc/arith.hpp",
                   "paper_1305_3699_amd/csrc/kernel_configs.inc", "paper_1305_3699_amd/csrc/kernels_mfma.hpp",
-                  "paper_1305_3699_amd/csrc/mfma_layout.hpp", "paper_1305_3699_amd/csrc/kernel_configs_mfma.inc"]
+                  "paper_1305_3699_amd/csrc/mfma_layout.hpp", "paper_1305_3699_amd/csrc/kernel_configs_mfma.inc",
+                  "paper_1305_3699_amd/build.py"]
 KERNELS = ("modexp_kernel", "modexp_mfma_kernel", "garner_kernel", "montmul_kernel")
 
 
@@ -571,7 +572,7 @@ def run_modmul_sweep(args) -> list:
             print("modmul k=%d %s" % (k, json.dumps(rows[-1])), file=sys.stderr, flush=True)
         lines.append({"metric": "%d-bit RNS modular multiplications per ms vs operands in flight" % bits,
                       "bits": bits, "k": k, "engine": {1: "channel", 2: "matrix"}[info["engine"]],
-                      "standalone_engine": "channel", "window": info["window"],
+                      "standalone_engine": {1: "channel", 2: "matrix"}[info["engine"]], "window": info["window"],
                       "products_per_exponentiation": mm_exp, "rows": rows})
     return lines
 
@@ -812,7 +813,8 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16384)
-    ap.add_argument("--window", type=int, default=6)
+    ap.add_argument("--window", type=int, default=5,
+                    help="window width of the main workload (5: fastest in the per-width sweep of --configs)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (k = 33 shapes)")
     ap.add_argument("--engine", type=int, default=0, help="0 auto, 1 channel (VALU), 2 matrix cores")
     ap.add_argument("--group", type=int, default=0, help="matrix cores: elements per workgroup (16, 32; 0 default)")

@@ -203,7 +203,7 @@ def run(args, key, ref=None) -> dict:
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs the GPU")
     torch.cuda.set_device(0)
-    opts = {"window": args.window, "engine": args.engine, "group": args.group}
+    opts = {"window": args.window, "engine": args.engine, "group": args.group, "unscaled": args.unscaled}
     if args.waves:
         opts.update(k=33, waves=args.waves)
     rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, **opts)
@@ -311,6 +311,7 @@ def run(args, key, ref=None) -> dict:
             "window": info["window"],
             "engine": ENGINE_NAMES[info["engine"]],
             "group": info["group"],
+            "scaled_b": bool(info["scaled"]),
         },
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "what": "one step (batch of %d)" % B},
         "modexps_per_s": round(2 * value, 1),
@@ -818,6 +819,8 @@ def main(argv=None) -> int:
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (k = 33 shapes)")
     ap.add_argument("--engine", type=int, default=0, help="0 auto, 1 channel (VALU), 2 matrix cores")
     ap.add_argument("--group", type=int, default=0, help="matrix cores: elements per workgroup (16, 32; 0 default)")
+    ap.add_argument("--unscaled", action="store_true",
+                    help="matrix cores: keep the key's B residues unscaled (two REDCs per quotient digit)")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="ciphertexts for the oracle baseline (0: skip)")
     ap.add_argument("--sweep-window", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=5, help="timed runs of the batched-vs-plain mix (0: skip)")

@@ -66,8 +66,8 @@ enum rns_engine {
 
 /* Prime ranges for the channel moduli. */
 enum rns_prime_range {
-    RNS_PRIMES_HIGH = 0,    /* primes in [2^32 - 2^24, 2^32) */
-    RNS_PRIMES_FULL = 1     /* primes in (2^31, 2^32): any 32-bit prime */
+    RNS_PRIMES_HIGH = 0,    /* primes = 3 mod 4 in [2^32 - 2^24, 2^32) */
+    RNS_PRIMES_FULL = 1     /* primes = 3 mod 4 in (2^31, 2^32) */
 };
 
 /*
@@ -103,6 +103,15 @@ enum rns_prime_range {
  *               launch too small to give the GPU 1.5 resident waves per SIMD
  *               with 32-element workgroups takes 16-element ones.
  *               rns_info.group reports the requested or default size.
+ *   unscaled    matrix-core engine, k <= 66: 1 keeps the B residues in the
+ *               plain Montgomery form x 2^32 mod m_i.  0 (default): they
+ *               are kept as x 2^32 s_i mod m_i with s_i^2 = +-c_i 2^-32
+ *               (c_i = -N^-1 M_i^-1 mod m_i), which makes each product's
+ *               quotient digit one modular reduction of the two operands
+ *               instead of two; a key gets that form when such an s_i
+ *               exists for every B prime (always for the drawn bases, whose
+ *               primes are 3 mod 4), and rns_info.scaled reports it.  The
+ *               results are the same either way.
  * Both bases hold k primes; with the redundant channel 2^32 an operand has
  * 2k+1 residues.  A base pair is accepted for modulus N of L limbs when
  *   M >= (k+1)^2 N,  M >= 2^(32L+1),  M' >= (k+1) N,  gcd(N, M) = 1,
@@ -119,6 +128,7 @@ typedef struct rns_opts {
     size_t n_primes;
     int engine;
     int group;
+    int unscaled;
 } rns_opts;
 
 typedef struct rns_info {
@@ -129,6 +139,7 @@ typedef struct rns_info {
     int mod_bits;       /* bit length of N */
     int engine;         /* RNS_ENGINE_CHANNEL or RNS_ENGINE_MATRIX */
     int group;          /* elements served by one workgroup */
+    int scaled;         /* 1: the matrix engine keeps this key's B residues scaled */
 } rns_info;
 
 typedef struct rns_ctx rns_ctx;
@@ -138,7 +149,7 @@ typedef struct rsa_key rsa_key;
  * is valid until the next library call on this thread. */
 const char *rns_last_error(void);
 
-/* ABI version of this header (currently 5). */
+/* ABI version of this header (currently 6). */
 int rns_abi_version(void);
 
 /*

@@ -180,7 +180,7 @@ int choose_engine(const BaseSet &bs, int requested, int group, int *engine) {
     return RNS_OK;
 }
 
-int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx **out) {
+int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx **out, bool allow_scaled = true) {
     std::unique_ptr<rns_ctx> c(new (std::nothrow) rns_ctx);
     if (!c) return fail(RNS_ENOMEM, "out of host memory");
     c->plan = std::move(mp);
@@ -197,12 +197,13 @@ int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx *
         mfma_shape_for(c->plan.base->K, c->mshape, group);
         // the base table is built only when no context has uploaded it yet
         uint32_t *resident = resident_mfma_base(c->plan.base.get());
-        MfmaTables t = make_mfma_tables(c->plan, c->mshape, resident == nullptr);
+        MfmaTables t = make_mfma_tables(c->plan, c->mshape, resident == nullptr, allow_scaled);
         if (resident)
             c->d_mbase = resident;
         else if ((rc = device_mfma_base(c->plan.base, t.base, &c->d_mbase)))
             return rc;
         if ((rc = upload(t.key, &c->d_mkey))) return rc;
+        c->mscaled = t.scaled;
         std::vector<uint32_t> Em = make_mfma_entry_table(c->plan, c->mshape, {c->plan.R2}, c->plan.L);
         if ((rc = upload(Em, &c->d_mentry))) return rc;
     }
@@ -320,6 +321,7 @@ int run_modexp(const rns_ctx *c0, const rns_ctx *c1, const uint32_t *E0, const u
         a.njobs = njobs;
         a.tiles = per_job * njobs;
         a.max_window = c0->window;
+        a.scaled = c0->mscaled && (njobs < 2 || c1->mscaled);
         Scratch table;
         if (!table_buf) {
             int rc = scratch_alloc(table, modexp_scratch_bytes(c0, njobs, batch, spread), s);
@@ -413,7 +415,7 @@ extern "C" {
 
 const char *rns_last_error(void) { return g_err.c_str(); }
 
-int rns_abi_version(void) { return 5; }
+int rns_abi_version(void) { return 6; }
 
 int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_ctx **out) {
     if (!mod || !out || mod_limbs == 0 || mod_limbs > 4096) return fail(RNS_EINVAL, "bad modulus arguments");
@@ -426,7 +428,7 @@ int rns_setup(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts, rns_c
         rc = make_modplan(limbs_of(mod, mod_limbs), (int)mod_limbs, plan_options(opts), mp, err);
         if (rc) return fail(rc, err);
         rc = ctx_from_plan(std::move(mp), window_or_default(opts), opts ? opts->engine : 0, opts ? opts->group : 0,
-                           out);
+                           out, !(opts && opts->unscaled));
         if (rc) return rc;
     } catch (const std::bad_alloc &) {
         return fail(RNS_ENOMEM, "out of host memory");
@@ -447,6 +449,7 @@ int rns_get_info(const rns_ctx *ctx, rns_info *info) {
     info->mod_bits = (int)bn_bits(ctx->plan.N);
     info->engine = ctx->engine;
     info->group = 64;
+    info->scaled = ctx->mscaled ? 1 : 0;
     if (ctx->engine == RNS_ENGINE_MATRIX) {
         info->waves = ctx->mshape.W;
         info->group = ctx->mshape.NM();
@@ -522,7 +525,9 @@ int rns_modexp_jobs(const rns_job *jobs, size_t njobs, void *hip_stream) {
                 g.shape = sh;
                 g.device = dev;
                 g.auto_tile = c->group_req == 0;
+                g.scaled = true;
             }
+            g.scaled = g.scaled && c->mscaled;
             PlannedJob J{};
             J.j.mb = c->d_mbase;
             J.j.mk = c->d_mkey;
@@ -628,6 +633,7 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
         const int window = window_or_default(opts);
         const int engine = opts ? opts->engine : 0;
         const int group = opts ? opts->group : 0;
+        const bool scaled = !(opts && opts->unscaled);
         std::string err;
         {
             ModPlan mp;
@@ -644,7 +650,7 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
             // encryption unsupported
             if (rc) {
                 if (!(rc == RNS_ERANGE && all_crt)) return fail(rc, err);
-            } else if ((rc = ctx_from_plan(std::move(mp), window, engine, group, &key->n))) {
+            } else if ((rc = ctx_from_plan(std::move(mp), window, engine, group, &key->n, scaled))) {
                 if (!(rc == RNS_EUNSUPPORTED && all_crt)) return rc;   // message recorded by ctx_from_plan
             }
             rc = RNS_OK;
@@ -693,8 +699,8 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
                 Epm.resize((size_t)n_limbs * msh.ecols());
                 Eqm.resize((size_t)n_limbs * msh.ecols());
             }
-            if ((rc = ctx_from_plan(std::move(pp), window, engine, group, &key->p))) return rc;
-            if ((rc = ctx_from_plan(std::move(qp), window, engine, group, &key->q))) return rc;
+            if ((rc = ctx_from_plan(std::move(pp), window, engine, group, &key->p, scaled))) return rc;
+            if ((rc = ctx_from_plan(std::move(qp), window, engine, group, &key->q, scaled))) return rc;
             if ((rc = upload(Ep, &key->d_centry_p))) return rc;
             if ((rc = upload(Eq, &key->d_centry_q))) return rc;
             if (key->p->engine == RNS_ENGINE_MATRIX) {
@@ -807,7 +813,7 @@ int rns_plan_create(const uint32_t *mod, size_t mod_limbs, const rns_opts *opts,
         if (p->engine == RNS_ENGINE_MATRIX) {
             MfmaShape sh;
             mfma_shape_for(p->plan.base->K, sh, group);
-            p->mt = make_mfma_tables(p->plan, sh);
+            p->mt = make_mfma_tables(p->plan, sh, true, !(opts && opts->unscaled));
         }
         *out = p.release();
     } catch (const std::bad_alloc &) {
@@ -827,6 +833,7 @@ int rns_plan_info(const rns_plan *plan, rns_info *info) {
     info->mod_bits = (int)bn_bits(plan->plan.N);
     info->engine = plan->engine;
     info->group = 64;
+    info->scaled = plan->mt.scaled ? 1 : 0;
     if (plan->engine == RNS_ENGINE_MATRIX) {
         info->waves = plan->mt.shape.W;
         info->group = plan->mt.shape.NM();

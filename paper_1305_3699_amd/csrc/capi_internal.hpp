@@ -53,6 +53,7 @@ struct rns_ctx {
     uint32_t *d_mbase = nullptr;  // shared, owned by the process-wide cache
     uint32_t *d_mkey = nullptr;
     uint32_t *d_mentry = nullptr;
+    bool mscaled = false;         // the key table holds the scaled form (MfmaTables::scaled)
     ~rns_ctx() {
         for (uint32_t *x : {d_mod, d_entry, d_mkey, d_mentry})
             if (x) hipFree(x);

@@ -18,10 +18,11 @@ void emul_modexp(const ModPlan &mp, const std::vector<uint32_t> &E, int in_limbs
 
 // Host model of the matrix-core kernel (emul_mfma.cpp), same contract.
 // Returns false when a one-REDC step saw an input outside [0, m 2^32), where
-// the kernel's result would be wrong.
+// the kernel's result would be wrong.  scaled: keep the B residues scaled
+// when T holds that form (the kernel's default), else the unscaled form.
 bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
                       const uint32_t *base, const uint32_t *exp, int exp_limbs, size_t exp_stride, int window,
-                      uint32_t *out, size_t batch);
+                      uint32_t *out, size_t batch, bool scaled = true);
 
 // One base extension of the matrix-core kernel (which = 1: first, 2:
 // second) on raw digits xi [batch][K]: the byte partials of every slot row

@@ -21,12 +21,15 @@ struct MCtx {
     const MLayout ly;
     int K;
     // [W][4MT][4 bytes][64*KSTEPS]: the A-row byte b of each slot, per K index
-    std::vector<int16_t> A1, A2;
+    // (A2s: the key's second extension for scaled B residues)
+    std::vector<int16_t> A1, A2, A2s;
+    bool sq;    // B residues kept scaled (x R s_i): the key holds the scaled form
 
-    MCtx(const MfmaTables &t) : T(t), ly(t.shape), K(t.shape.K) {
+    MCtx(const MfmaTables &t, bool scaled) : T(t), ly(t.shape), K(t.shape.K), sq(scaled && t.scaled) {
         const int SW = 4 * ly.MT, KK = 64 * ly.KSTEPS();
         A1.assign((size_t)ly.W * SW * 4 * KK, 0);
         A2.assign((size_t)ly.W * SW * 4 * KK, 0);
+        if (sq) A2s.assign(A2.size(), 0);
         for (int w = 0; w < ly.W; w++)
             for (int s = 0; s < SW; s++)
                 for (int b = 0; b < 4; b++)
@@ -34,6 +37,7 @@ struct MCtx {
                         const size_t at = (((size_t)w * SW + s) * 4 + b) * KK + kap;
                         A1[at] = tile_byte(T.key.data() + ly.a1(), w, s, b, kap);
                         A2[at] = tile_byte(T.base.data() + ly.a2(), w, s, b, kap);
+                        if (sq) A2s[at] = tile_byte(T.key.data() + ly.a2s(), w, s, b, kap);
                     }
     }
     // byte b of slot s's constant at K index kap, read through the hardware
@@ -127,8 +131,9 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
             const uint32_t m = c.slot(ly.slotB(), 3, 0, w, s), u = c.slot(ly.slotB(), 3, 1, w, s);
             const uint32_t ci = c.kslot(ly.slotC(), 1, 0, w, s);
             for (int e = 0; e < NM; e++) {
+                // sigma_i x y c_i: one REDC of the operands when they are scaled
                 const uint32_t t = mulredc(x.b[idx(w, s, e)], y.b[idx(w, s, e)], m, u);
-                const uint32_t xi = mulredc(t, ci, m, u);
+                const uint32_t xi = c.sq ? t : mulredc(t, ci, m, u);
                 if (c.real(w, s)) dig1[(size_t)e * BROW + c.channel(w, s)] = pack_digits(xi);
             }
         }
@@ -152,17 +157,18 @@ void mm(const MCtx &c, MSt &x, const MSt &y, std::vector<uint32_t> &dig1, std::v
         }
     for (int e = 0; e < NM; e++) x.r[e] = rr[e];
     if (!full) return;
+    const std::vector<int16_t> &A2 = c.sq ? c.A2s : c.A2;
     for (int w = 0; w < ly.W; w++) {
         std::vector<uint32_t> alpha(NM);
         for (int e = 0; e < NM; e++) {
-            const int64_t S = extension(c.A2, (size_t)w * SW + SW - 1, dig2, e, KK, BROW, c.K);
+            const int64_t S = extension(A2, (size_t)w * SW + SW - 1, dig2, e, KK, BROW, c.K);
             alpha[e] = ((uint32_t)S - rr[e]) * Mpinv_r;
         }
         for (int s = 0; s < SW; s++) {
             const uint32_t m = c.slot(ly.slotB(), 3, 0, w, s), u = c.slot(ly.slotB(), 3, 1, w, s);
-            const uint32_t nu = c.slot(ly.slotB(), 3, 2, w, s);
+            const uint32_t nu = c.sq ? c.kslot(ly.sqB(), 3, 0, w, s) : c.slot(ly.slotB(), 3, 2, w, s);
             for (int e = 0; e < NM; e++) {
-                const int64_t S = extension(c.A2, (size_t)w * SW + s, dig2, e, KK, BROW, c.K);
+                const int64_t S = extension(A2, (size_t)w * SW + s, dig2, e, KK, BROW, c.K);
                 x.b[idx(w, s, e)] = reduce_offset((uint64_t)alpha[e] * nu, S, m, u, sh);
             }
         }
@@ -181,9 +187,9 @@ uint32_t digit_of(const uint32_t *e, int nlimbs, int nd, int w, int di) {
 
 bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<uint32_t> &E, int in_limbs,
                       const uint32_t *base, const uint32_t *exp, int exp_limbs, size_t exp_stride, int window,
-                      uint32_t *out, size_t batch) {
+                      uint32_t *out, size_t batch, bool scaled) {
     t_in_range = true;
-    const MCtx c(T);
+    const MCtx c(T, scaled);
     const MLayout &ly = c.ly;
     const int K = c.K, SW = 4 * ly.MT, NM = ly.NM(), BROW = ly.BROW(), L = mp.L;
     const int w = window, TT = 1 << w;
@@ -196,8 +202,12 @@ bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
             dig1[(size_t)e * BROW + K] = 1;
             dig2[(size_t)e * BROW + K] = 1;
         }
-        MSt a, unit, one;
-        for (MSt *st : {&a, &unit, &one}) {
+        // unit: y = 1 for the exit product; unit_in for the entry product,
+        // whose first operand comes from the entry table unscaled (with
+        // scaled B residues its B part is sigma_i c_i, so the one-REDC
+        // quotient digit is right and the result comes out scaled)
+        MSt a, unit, unit_in, one;
+        for (MSt *st : {&a, &unit, &unit_in, &one}) {
             st->b.assign((size_t)ly.W * SW * NM, 0);
             st->p.assign((size_t)ly.W * SW * NM, 0);
             st->r.assign(NM, 0);
@@ -218,9 +228,11 @@ bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
                     }
                     a.b[idx(wv, s, e)] = acc_redc(sb, m, u);
                     a.p[idx(wv, s, e)] = acc_redc(sp, mpp, up);
-                    unit.b[idx(wv, s, e)] = 0u - m;
+                    unit.b[idx(wv, s, e)] = c.sq ? c.kslot(ly.sqB(), 3, 1, wv, s) : 0u - m;
                     unit.p[idx(wv, s, e)] = kap;
-                    one.b[idx(wv, s, e)] = c.kslot(ly.one(), 2, 0, wv, s);
+                    unit_in.b[idx(wv, s, e)] = c.sq ? c.kslot(ly.slotC(), 1, 0, wv, s) : 0u - m;
+                    unit_in.p[idx(wv, s, e)] = kap;
+                    one.b[idx(wv, s, e)] = c.sq ? c.kslot(ly.sqB(), 3, 2, wv, s) : c.kslot(ly.one(), 2, 0, wv, s);
                     one.p[idx(wv, s, e)] = c.kslot(ly.one(), 2, 1, wv, s);
                 }
             }
@@ -230,9 +242,10 @@ bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
             for (int l = 0; l < in_limbs; l++) z += (el < batch ? base[el * in_limbs + l] : 0u) * E[(size_t)l * ecols + ecols - 1];
             a.r[e] = z;
             unit.r[e] = 1;
+            unit_in.r[e] = 1;
             one.r[e] = T.key[ly.one() + (size_t)ly.W * ly.MT * 2 * 64];
         }
-        mm(c, a, unit, dig1, dig2, true);
+        mm(c, a, unit_in, dig1, dig2, true);
         std::vector<MSt> tbl(TT);
         tbl[0] = one;
         tbl[1] = a;
@@ -363,7 +376,7 @@ bool emul_modexp_mfma(const ModPlan &mp, const MfmaTables &T, const std::vector<
 bool emul_mfma_extension(const MfmaTables &T, int which, const uint32_t *xi, size_t batch, int64_t *parts,
                          int64_t *value) {
     t_in_range = true;
-    const MCtx c(T);
+    const MCtx c(T, false);
     const MLayout &ly = c.ly;
     const int K = c.K, SW = 4 * ly.MT, BROW = ly.BROW(), KK = 64 * ly.KSTEPS(), rows = ly.W * SW;
     std::vector<uint32_t> dig((size_t)BROW, 0);
@@ -381,7 +394,7 @@ bool emul_mfma_extension(const MfmaTables &T, int which, const uint32_t *xi, siz
 }
 
 void emul_mfma_matrix(const MfmaTables &T, int which, int8_t *A) {
-    const MCtx c(T);
+    const MCtx c(T, false);
     const std::vector<int16_t> &src = which == 1 ? c.A1 : c.A2;
     for (size_t i = 0; i < src.size(); i++) A[i] = (int8_t)src[i];
 }

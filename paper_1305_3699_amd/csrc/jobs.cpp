@@ -117,6 +117,7 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             JobGroup &g = P.groups.back();
             g.shape = sh;
             g.device = c->device;
+            g.scaled = true;
             if (const int nt = tuned_nt(sh)) {
                 MfmaShape t;
                 if (mfma_shape_for(sh.K, t, 16 * nt) && t.W == sh.W && t.MT == sh.MT && t.NT == nt) g.shape = t;
@@ -124,6 +125,7 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             }
         }
         JobGroup &g = P.groups[it->second];
+        g.scaled = g.scaled && c->mscaled;
         if (c->group_req) {
             g.auto_tile = false;
             if (!tuned_nt(sh)) g.shape = sh;
@@ -200,6 +202,7 @@ hipError_t launch_group(const JobGroup &g, const MJob *d_jobs, uint32_t *table, 
     a.tiles = g.tiles;
     a.max_window = g.max_window;
     a.table = table;
+    a.scaled = g.scaled ? 1 : 0;
     return launch_modexp_mfma(g.shape, a, s);
 }
 

@@ -48,6 +48,7 @@ struct JobGroup {
     std::vector<PlannedJob> jobs;
     int tiles = 0;
     int max_window = 1;
+    bool scaled = false;    // every job's key holds the scaled form (the kernel keeps B residues scaled)
     size_t table_words() const { return modexp_mfma_table_words(shape, max_window, (size_t)tiles); }
 };
 

@@ -93,6 +93,7 @@ struct ModexpMfmaLaunch {
     int tiles;           // total tiles of all jobs = workgroups launched
     int max_window;      // window table slots hold 2^max_window entries
     uint32_t *table;     // scratch: modexp_mfma_table_words(shape, max_window, tiles) words
+    int scaled;          // every job's key keeps scaled B residues (MfmaTables::scaled)
 };
 
 // One RNS Montgomery product per element on the matrix cores (the

@@ -231,9 +231,11 @@ __device__ __forceinline__ int mfma_digit_col(int wave, int mt, int g) {
     return real ? ch : S::LY.KCH() + (wave & 3);
 }
 
-// Step (i) of a product: quotient digits xi = x y c_i of the B slots,
-// published as the B operand of the first extension.
-template <int K, int W, int MT, int NT>
+// Step (i) of a product: quotient digits xi = x y c_i of the B slots (times
+// the channel's sign sigma_i), published as the B operand of the first
+// extension.  With the B residues kept scaled (SQ: x R s_i, s_i^2 =
+// sigma_i c_i R^-1) that is one REDC of the two operands, else two.
+template <int K, int W, int MT, int NT, bool SQ = false>
 __device__ __forceinline__ void mfma_publish_xi(const MConstOf<K, W, MT, NT> &C,
                                                 const MState<MT, NT> &x, const MState<MT, NT> &y, uint32_t *buf1,
                                                 int wave, int lane) {
@@ -245,8 +247,8 @@ __device__ __forceinline__ void mfma_publish_xi(const MConstOf<K, W, MT, NT> &C,
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
             const MSlotB sb = C.slotB(mt);
-            const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], sb.m, sb.u);   // x y 2^32
-            const uint32_t xi = mulredc(t, sb.c, sb.m, sb.u);                  // x y c_i
+            const uint32_t t = mulredc(x.b[mt][nt], y.b[mt][nt], sb.m, sb.u);   // x y 2^32, or sigma x y c_i (SQ)
+            const uint32_t xi = SQ ? t : mulredc(t, sb.c, sb.m, sb.u);         // sigma x y c_i
             buf1[(16 * nt + (lane & 15)) * S::BROW + col] = mfma_pack(xi);
         }
     }
@@ -255,13 +257,15 @@ __device__ __forceinline__ void mfma_publish_xi(const MConstOf<K, W, MT, NT> &C,
 // One RNS Montgomery product x <- x*y*M^-1 in the matrix-core layout.  With
 // full == false the second extension is skipped (the caller leaves the RNS
 // from the xi' digits in buf2).  x.r receives the new redundant residue.
-template <int K, int W, int MT, int NT>
+// SQ: B residues kept scaled by s_i (C then holds the scaled second
+// extension and nu, so the result comes out scaled as well).
+template <int K, int W, int MT, int NT, bool SQ = false>
 __device__ __forceinline__ void mfma_mm(const MConstOf<K, W, MT, NT> &C, MState<MT, NT> &x,
                                         const MState<MT, NT> &y, uint32_t *buf1, uint32_t *buf2, int wave, int lane,
                                         bool full) {
     using S = MShp<K, W, MT, NT>;
     const int g = lane >> 4;
-    mfma_publish_xi<K, W, MT, NT>(C, x, y, buf1, wave, lane);
+    mfma_publish_xi<K, W, MT, NT, SQ>(C, x, y, buf1, wave, lane);
     __syncthreads();
 
     // (ii) first extension on the matrix cores: q^'' N M^-1 (scaled) in each B'
@@ -380,17 +384,25 @@ __device__ __forceinline__ void mstate_load_lds(const uint32_t *p, MState<MT, NT
 }
 
 // y = 1 in the kept representation: 2^32 mod m in B, 2^32 M^-1 mod m' in B'
-// (read from the table when needed rather than held in registers).
-template <int K, int W, int MT, int NT>
-__device__ __forceinline__ void mstate_unit(const MConstOf<K, W, MT, NT> &C,
-                                            const gu32 *__restrict__ mb, int wave, int lane, MState<MT, NT> &y) {
+// (read from the table when needed rather than held in registers).  With
+// scaled B residues (SQ) the B part is 2^32 s_i, except for the entry
+// product, whose first operand comes from the entry table unscaled: there
+// sigma_i c_i, so that its quotient digit is still one REDC and its result
+// scaled.
+template <int K, int W, int MT, int NT, bool SQ = false>
+__device__ __forceinline__ void mstate_unit(const MConstOf<K, W, MT, NT> &C, const gu32 *__restrict__ mb,
+                                            const gu32 *__restrict__ mk, bool entry, int wave, int lane,
+                                            MState<MT, NT> &y) {
     using S = MShp<K, W, MT, NT>;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++) {
-        const uint32_t kap = mb[S::LY.slotP() + (((size_t)wave * MT + mt) * 4 + 3) * 64 + lane];
+        const size_t sl = (size_t)wave * MT + mt;
+        const uint32_t kap = mb[S::LY.slotP() + (sl * 4 + 3) * 64 + lane];
+        uint32_t ub = 0u - C.slotB(mt).m;
+        if (SQ) ub = entry ? mk[S::LY.slotC() + sl * 64 + lane] : mk[S::LY.sqB() + (sl * 3 + 1) * 64 + lane];
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            y.b[mt][nt] = 0u - C.slotB(mt).m;
+            y.b[mt][nt] = ub;
             y.p[mt][nt] = kap;
         }
     }
@@ -508,11 +520,14 @@ __device__ __forceinline__ void mfma_exit_tail(const gu32 *__restrict__ mb, cons
 // constant digit rows of both exchange buffers (channel K holds the offset
 // digit 1, the channels after it zero) and the per-lane constants of C (tiles
 // in registers, LDS or global memory, per-slot constants, scalars).
-template <int K, int W, int MT, int NT>
+template <int K, int W, int MT, int NT, bool SQ = false>
 __device__ __forceinline__ void mfma_setup(const gu32 *__restrict__ mb, const gu32 *__restrict__ mk,
                                            uint32_t *__restrict__ lds, int wave, int lane,
                                            MConstOf<K, W, MT, NT> &C) {
     using S = MShp<K, W, MT, NT>;
+    static_assert(!SQ || (S::LY.sq_ok() && !S::A2_GLOBAL && !S::C_LDS), "scaled B residues need per-key tiles in registers or LDS");
+    // second extension's tiles and nu: the base's, or the key's scaled ones
+    const gu32 *__restrict__ a2src = SQ ? mk + S::LY.a2s() : mb + S::LY.a2();
     uint32_t *buf1 = lds;
     uint32_t *buf2 = lds + S::NM * S::BROW;
     const int g = lane >> 4;
@@ -532,16 +547,16 @@ __device__ __forceinline__ void mfma_setup(const gu32 *__restrict__ mb, const gu
         for (int ks = 0; ks < S::KSTEPS; ks++) {
             const size_t ti = ((sl * S::KSTEPS + ks) * 64 + lane) * 4;
             if (!S::A1_GLOBAL) C.A1[mt][ks] = *(gcv4i *)(mk + S::LY.a1() + ti);
-            if (!S::A2_LDS && !S::A2_GLOBAL) C.A2[mt][ks] = *(gcv4i *)(mb + S::LY.a2() + ti);
+            if (!S::A2_LDS && !S::A2_GLOBAL) C.A2[mt][ks] = *(gcv4i *)(a2src + ti);
         }
         if (!S::C_LDS) {
             C.mB[mt] = mb[S::LY.slotB() + (sl * 3 + 0) * 64 + lane];
             C.uB[mt] = mb[S::LY.slotB() + (sl * 3 + 1) * 64 + lane];
             C.mP[mt] = mb[S::LY.slotP() + (sl * 4 + 0) * 64 + lane];
             C.uP[mt] = mb[S::LY.slotP() + (sl * 4 + 1) * 64 + lane];
-            C.nuB[mt] = mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
+            C.nuB[mt] = SQ ? mk[S::LY.sqB() + (sl * 3 + 0) * 64 + lane] : mb[S::LY.slotB() + (sl * 3 + 2) * 64 + lane];
             C.HP[mt] = mb[S::LY.slotP() + (sl * 4 + 2) * 64 + lane];
-            C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
+            if (!SQ) C.cB[mt] = mk[S::LY.slotC() + sl * 64 + lane];
         }
     }
     if (S::C_LDS) {
@@ -565,7 +580,7 @@ __device__ __forceinline__ void mfma_setup(const gu32 *__restrict__ mb, const gu
         // each wave copies its own tiles; it alone reads them, so program
         // order suffices (no barrier)
         mfma_v4i *dst = (mfma_v4i *)(lds + S::WORK_WORDS) + (size_t)wave * MT * S::KSTEPS * 64;
-        gcv4i *src = (gcv4i *)(mb + S::LY.a2()) + (size_t)wave * MT * S::KSTEPS * 64;
+        gcv4i *src = (gcv4i *)a2src + (size_t)wave * MT * S::KSTEPS * 64;
         for (int i = lane; i < MT * S::KSTEPS * 64; i += 64) dst[i] = src[i];
         C.a2lds = dst;
     }
@@ -588,7 +603,7 @@ __device__ __forceinline__ void mfma_setup(const gu32 *__restrict__ mb, const gu
 // of the job (those with n < mjob_tile_elems(J) are stored), with window
 // table slot `slot` of the launch;
 // ylds: the operand prefetch buffer (S::PF_WORDS words, if S::PREFETCH).
-template <int K, int W, int MT, int NT>
+template <int K, int W, int MT, int NT, bool SQ = false>
 __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t *__restrict__ lds,
                                                  uint32_t *__restrict__ table, size_t slot, int max_window,
                                                  uint32_t *__restrict__ ylds) {
@@ -606,7 +621,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     const int g = lane >> 4;
 
     MConstOf<K, W, MT, NT> C;
-    mfma_setup<K, W, MT, NT>(mb, mk, lds, wave, lane, C);
+    mfma_setup<K, W, MT, NT, SQ>(mb, mk, lds, wave, lane, C);
 
     // entry: residues of Z = sum_h X_h Y_h in the kept representation
     MState<MT, NT> a;
@@ -662,7 +677,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
             const size_t sl = (size_t)wave * MT + mt;
 #pragma unroll
             for (int nt = 0; nt < NT; nt++) {
-                one.b[mt][nt] = mk[S::LY.one() + (sl * 2 + 0) * 64 + lane];
+                one.b[mt][nt] = SQ ? mk[S::LY.sqB() + (sl * 3 + 2) * 64 + lane] : mk[S::LY.one() + (sl * 2 + 0) * 64 + lane];
                 one.p[mt][nt] = mk[S::LY.one() + (sl * 2 + 1) * 64 + lane];
             }
         }
@@ -697,11 +712,11 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
     int ysrc = Y_UNIT, yidx = 0;
     for (;;) {
         if (ysrc == Y_SQUARE) {
-            mfma_mm<K, W, MT, NT>(C, a, a, buf1, buf2, wave, lane, true);
+            mfma_mm<K, W, MT, NT, SQ>(C, a, a, buf1, buf2, wave, lane, true);
         } else {
             MState<MT, NT> y;
             if (ysrc == Y_UNIT) {
-                mstate_unit<K, W, MT, NT>(C, mb, wave, lane, y);
+                mstate_unit<K, W, MT, NT, SQ>(C, mb, mk, phase == ENTRY, wave, lane, y);
                 vmem_drain();
             } else if (ysrc == Y_TABLE) {
                 mstate_load<MT, NT>(tw + (size_t)yidx * estride, y);
@@ -726,7 +741,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
                 }
                 vmem_drain();
             }
-            mfma_mm<K, W, MT, NT>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
+            mfma_mm<K, W, MT, NT, SQ>(C, a, y, buf1, buf2, wave, lane, phase != EXIT);
         }
         if (phase == EXIT) break;
         if (phase == ENTRY) {
@@ -955,7 +970,7 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
 // from a counter costs 15-35 more VGPRs per lane here, as the compiler keeps
 // the per-lane addresses of the tile body live across it; the hardware
 // dispatcher refills the CUs as workgroups finish instead.)
-template <int K, int W, int MT, int NT>
+template <int K, int W, int MT, int NT, bool SQ>
 __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A) {
     using S = MShp<K, W, MT, NT>;
     __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
@@ -972,14 +987,22 @@ __global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A)
     } else {
         J = (A.njobs > 1 && tile >= A.inl[1].tile0) ? A.inl[1] : A.inl[0];
     }
-    modexp_mfma_tile<K, W, MT, NT>(J, (tile - J.tile0) * mjob_tile_elems(J, S::NM), lds, A.table, blockIdx.x,
-                                   A.max_window, ylds);
+    modexp_mfma_tile<K, W, MT, NT, SQ>(J, (tile - J.tile0) * mjob_tile_elems(J, S::NM), lds, A.table, blockIdx.x,
+                                       A.max_window, ylds);
 }
 
 template <int K, int W, int MT, int NT>
 hipError_t launch_modexp_mfma_t(const ModexpMfmaLaunch &a, hipStream_t s) {
+    using S = MShp<K, W, MT, NT>;
     if (a.tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT>), dim3((unsigned)a.tiles), dim3(64 * W), 0, s, a);
+    if constexpr (S::LY.sq_ok() && !S::A2_GLOBAL && !S::C_LDS) {
+        if (a.scaled) {
+            hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT, true>), dim3((unsigned)a.tiles), dim3(64 * W), 0, s,
+                               a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((modexp_mfma_kernel<K, W, MT, NT, false>), dim3((unsigned)a.tiles), dim3(64 * W), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1073,7 +1096,7 @@ hipError_t launch_montmul_mfma_t(const MontMulMfmaLaunch &a, hipStream_t s) {
 template <int K, int W, int MT, int NT>
 int mfma_blocks_per_cu_t() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, modexp_mfma_kernel<K, W, MT, NT>, 64 * W, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, modexp_mfma_kernel<K, W, MT, NT, false>, 64 * W, 0) != hipSuccess)
         return 0;
     return n;
 }

@@ -139,7 +139,9 @@ int exponentiate(const std::vector<Candidate> &cs, const std::vector<size_t> &wh
         if (g.jobs.empty()) {
             g.shape = sh;
             g.device = c->device;
+            g.scaled = true;
         }
+        g.scaled = g.scaled && c->mscaled;
         const std::vector<uint32_t> eh = shared ? std::vector<uint32_t>{shared_exp} : cs[i].d;
         PlannedJob J{};
         J.j.mb = c->d_mbase;

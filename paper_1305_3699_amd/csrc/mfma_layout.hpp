@@ -87,7 +87,19 @@ struct MLayout {
     constexpr size_t one() const { return slotC() + (size_t)W * MT * 64; }     // [W][MT][2][64] + [1]: M mod N
     constexpr size_t Nl() const { return one() + (size_t)W * MT * 2 * 64 + 1; }  // [K] limbs of N
     constexpr size_t kscal() const { return Nl() + K; }                        // [4] N mod 2^32
-    constexpr size_t key_size() const { return kscal() + 4; }
+    // Whether a key of this shape may keep its B residues scaled (x R s_i
+    // instead of x R, with s_i^2 = sigma_i c_i R^-1 mod m_i, sigma_i = +-1):
+    // a product's quotient digit is then one REDC of the two operands.  The
+    // second extension's tiles and nu then carry the factor s_i and become
+    // per key, so only shapes whose tiles sit in registers or LDS (at most
+    // 5 k-steps) take it.
+    constexpr bool sq_ok() const { return KSTEPS() <= 5; }
+    // scaled form (sq_ok shapes): [W][MT][KSTEPS][64][4] second extension
+    // with output row t times s_t, then [W][MT][3][64] nu s, R s (the unit),
+    // (M mod N) R s (one)
+    constexpr size_t a2s() const { return kscal() + 4; }
+    constexpr size_t sqB() const { return a2s() + (sq_ok() ? tiles() : 0); }
+    constexpr size_t key_size() const { return sqB() + (sq_ok() ? (size_t)W * MT * 3 * 64 : 0); }
     // entry table: per input limb [W*4*MT B slots | W*4*MT B' slots | redundant]
     constexpr size_t ecols() const { return (size_t)2 * W * 4 * MT + 1; }
 };

@@ -57,7 +57,9 @@ static std::vector<uint32_t> draw_primes(int K, int range, uint64_t seed, int at
     std::set<uint32_t> seen;
     std::vector<uint32_t> out;
     while ((int)out.size() < 2 * K) {
-        uint32_t c = (uint32_t)(lo + splitmix64(s) % span) | 1u;
+        // primes = 3 mod 4: for each of them one of +-a is a square for any
+        // a != 0, which the matrix engine's scaled B residues rely on
+        uint32_t c = (uint32_t)(lo + splitmix64(s) % span) | 3u;
         if (c <= (1u << 31) || seen.count(c) || !is_prime32(c)) continue;
         seen.insert(c);
         out.push_back(c);

@@ -28,6 +28,10 @@ struct MfmaTables {
     MfmaShape shape;
     std::vector<uint32_t> base;  // key-independent
     std::vector<uint32_t> key;   // per modulus
+    // The key's B residues may be kept scaled (MLayout::sq_ok): every B
+    // channel had a square root s_i of sigma_i c_i R^-1 for sigma_i = 1 or
+    // -1.  Either way the key also serves the unscaled form.
+    bool scaled = false;
 };
 
 // Matrix-core kernel shape for K: the first listed whose workgroup serves
@@ -35,8 +39,9 @@ struct MfmaTables {
 bool mfma_shape_for(int K, MfmaShape &out, int group = 0);
 
 // with_base = false leaves `base` empty (for a base whose table is already
-// resident) and builds the per-modulus part only.
-MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh, bool with_base = true);
+// resident) and builds the per-modulus part only; allow_scaled = false
+// builds the unscaled form only (scaled stays false).
+MfmaTables make_mfma_tables(const ModPlan &mp, const MfmaShape &sh, bool with_base = true, bool allow_scaled = true);
 
 // Entry table: row j = input limb j (value 2^(32 (j mod L)) * Y_(j div L)),
 // columns [B slots | B' slots | redundant], scaled for the representation the

@@ -39,13 +39,13 @@ class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("window", ctypes.c_int), ("waves", ctypes.c_int),
                 ("prime_range", ctypes.c_int), ("prime_seed", ctypes.c_uint64),
                 ("primes", ctypes.POINTER(ctypes.c_uint32)), ("n_primes", ctypes.c_size_t),
-                ("engine", ctypes.c_int), ("group", ctypes.c_int)]
+                ("engine", ctypes.c_int), ("group", ctypes.c_int), ("unscaled", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("waves", ctypes.c_int), ("window", ctypes.c_int),
                 ("mod_limbs", ctypes.c_int), ("mod_bits", ctypes.c_int), ("engine", ctypes.c_int),
-                ("group", ctypes.c_int)]
+                ("group", ctypes.c_int), ("scaled", ctypes.c_int)]
 
 
 class RsaOp(ctypes.Structure):
@@ -138,7 +138,7 @@ _SIGNATURES = {
 _lib_handle = None
 
 
-ABI_VERSION = 5           # rns_opts / rns_info layout of include/rnsrsa.h
+ABI_VERSION = 6           # rns_opts / rns_info layout of include/rnsrsa.h
 
 
 def lib():
@@ -192,11 +192,12 @@ def _host_ptr(a: np.ndarray):
 
 
 def _make_opts(k=0, window=0, waves=0, prime_range=PRIMES_HIGH, prime_seed=0, primes=None, engine=ENGINE_AUTO,
-               group=0):
+               group=0, unscaled=False):
     o = Opts()
     o.k, o.window, o.waves, o.prime_range, o.prime_seed = k, window, waves, prime_range, prime_seed
     o.engine = engine
     o.group = group
+    o.unscaled = 1 if unscaled else 0
     keep = None
     if primes is not None:
         keep = np.ascontiguousarray(primes, dtype=np.uint32)
@@ -228,7 +229,7 @@ def _info(getter, handle, *extra) -> dict:
     inf = Info()
     _check(getter(handle, *extra, ctypes.byref(inf)))
     return {"k": inf.k, "waves": inf.waves, "window": inf.window, "mod_limbs": inf.mod_limbs,
-            "mod_bits": inf.mod_bits, "engine": inf.engine, "group": inf.group}
+            "mod_bits": inf.mod_bits, "engine": inf.engine, "group": inf.group, "scaled": inf.scaled}
 
 
 class RnsContext:

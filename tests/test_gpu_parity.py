@@ -186,6 +186,49 @@ def test_rsa2048_crt_both_engines(engine, group):
     assert np.array_equal(got2, got)
 
 
+@pytest.mark.parametrize("bits", [512, 1024, 2048])
+def test_scaled_and_unscaled_b_residues(bits):
+    """Both forms of the matrix engine's B residues (scaled x R s_i, the
+    default on these bases, and the plain x R on request) on the same
+    inputs: a shared exponent over two groups and a ragged tail,
+    per-element exponents, and one grouped launch that holds a job of each
+    form (it runs the unscaled form on both keys); every output equals the
+    oracle's pow."""
+    from paper_1305_3699_amd import modexp_jobs
+    rng = random.Random(bits + 11)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = bits // 32
+    cs, cu = _ctx(N, L), _ctx(N, L, unscaled=True)
+    assert cs.info["scaled"] == 1 and cu.info["scaled"] == 0
+    bases = gen.to_limbs([rng.getrandbits(bits) for _ in range(37)] + [0, 1, N - 1], L)
+    e = gen.to_limbs(rng.getrandbits(bits) | 1, L)[0]
+    want = oracle.modexp_batch(bases, e, gen.to_limbs(N, L)[0])
+    for c in (cs, cu):
+        assert np.array_equal(_run_modexp(c, bases, e), want)
+    pe = gen.to_limbs([rng.getrandbits(100) for _ in range(40)], 4)
+    want_pe = oracle.modexp_batch(bases, pe, gen.to_limbs(N, L)[0])
+    for c in (cs, cu):
+        assert np.array_equal(_run_modexp(c, bases, pe), want_pe)
+    outs = modexp_jobs([(cs, _dev(bases), _dev(e)), (cu, _dev(bases), _dev(e))])
+    for o in outs:
+        assert np.array_equal(_host(o), want)
+
+
+def test_rsa2048_crt_unscaled():
+    """RSA-2048 CRT and plain decryption with the B residues unscaled
+    (opts.unscaled) equal the oracle and the default (scaled) key."""
+    from paper_1305_3699_amd import RsaKey
+    key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
+    c = gen.uniform_below(key.n, 40, seed=13) + [0, 1, key.n - 1]
+    cl = gen.to_limbs(c, 64)
+    want = oracle.rsa_crt_batch(cl, key.p, key.q, key.dp, key.dq, key.qinv)
+    for unscaled in (True, False):
+        rk = RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, unscaled=unscaled)
+        assert rk.info(1)["scaled"] == (0 if unscaled else 1)
+        assert np.array_equal(_host(rk.decrypt(_dev(cl), use_crt=True)), want)
+        assert np.array_equal(_host(rk.decrypt(_dev(cl), use_crt=False)), want)
+
+
 def _indep_base(k: int, seed: int) -> list:
     """2k seeded channel primes from [2^32 - 2^24, 2^32 - 2^19) drawn here (B
     first, then B'), handed to the library through opts.primes, so the

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(rnsrsa.exported_symbols())
-    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 5
+    assert lib.rns_abi_version() == rnsrsa.ABI_VERSION == 6
 
 
 def _check_bounds(plan, N, L):
@@ -154,6 +154,48 @@ def test_emul_rsa1024_config_round_trip(engine):
     assert oracle.rows_to_ints(c) == [pow(m, key.e, key.n) for m in ms]
     m = p.emul_modexp(c, gen.to_limbs(key.d, 32)[0])
     assert oracle.rows_to_ints(m) == ms
+
+
+def test_scaled_b_residues_selection():
+    """The matrix engine keeps a key's B residues scaled (x R s_i, s_i^2 =
+    +-c_i R^-1 mod m_i) on bases of at most 5 k-steps (k <= 66) when every B
+    prime has such a root: always for the drawn bases (primes = 3 mod 4);
+    never on request (unscaled), on wider bases or on the channel engine."""
+    for bits, want in ((12, 1), (512, 1), (1024, 1), (2048, 1), (3072, 0), (4096, 0)):
+        N = (1 << bits) - 1 if bits > 12 else 3233
+        L = (bits + 31) // 32
+        p = Plan(N, L)
+        assert p.info["scaled"] == want, bits
+        assert all(m % 4 == 3 for m in p.primes)
+        assert Plan(N, L, unscaled=True).info["scaled"] == 0
+        assert Plan(N, L, engine=rnsrsa.ENGINE_CHANNEL).info["scaled"] == 0
+    key = gen.rsa_key(1024, seed=gen.config_seed(1, 1))
+    assert Plan(key.n, 32, prime_range=rnsrsa.PRIMES_FULL, prime_seed=gen.config_seed(1, 4)).info["scaled"] == 1
+
+
+@pytest.mark.parametrize("bits,window,unscaled", [(64, 3, True), (1024, 5, True), (2048, 4, True),
+                                                  (1024, 6, False), (2048, 5, False)])
+def test_emul_modexp_scaled_and_unscaled(bits, window, unscaled):
+    """The matrix engine's model in both forms of the B residues, on the
+    drawn base and on explicit bases with primes = 1 mod 4 among B (which
+    may lack the square roots, then the key keeps the unscaled form), equals
+    the oracle's pow."""
+    rng = random.Random(bits * 3 + window)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = (bits + 31) // 32
+    bases = [rng.getrandbits(32 * L) for _ in range(6)] + [0, 1, N - 1]
+    e = rng.getrandbits(min(bits, 160)) | 1
+    el = gen.to_limbs(e, (e.bit_length() + 31) // 32)[0]
+    want = oracle.modexp_batch(gen.to_limbs(bases, L), el, gen.to_limbs(N, L)[0])
+    p = Plan(N, L, window=window, unscaled=unscaled)
+    assert p.info["engine"] == rnsrsa.ENGINE_MATRIX and p.info["scaled"] == (0 if unscaled else 1)
+    assert np.array_equal(p.emul_modexp(gen.to_limbs(bases, L), el), want)
+    k = p.info["k"]
+    pr = gen.rns_primes(2 * k, seed=bits + window, lo=(1 << 32) - (1 << 24), hi=(1 << 32) - (1 << 19))
+    assert k < 9 or any(m % 4 == 1 for m in pr[:k])
+    q = Plan(N, L, window=window, primes=pr, unscaled=unscaled)
+    assert q.info["engine"] == rnsrsa.ENGINE_MATRIX
+    assert np.array_equal(q.emul_modexp(gen.to_limbs(bases, L), el), want)
 
 
 def test_engine_selection():

@@ -707,12 +707,19 @@ def run_configs(args) -> list:
     k2 = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
     c2 = dev(gen.to_limbs(gen.uniform_below(k2.n, 16384, seed=gen.config_seed(2, 2)), 64))
     row = {"config": "RSA-2048 CRT decryption of 16384 ciphertexts, fixed window width w", "decrypts_per_s": {}}
+    first = None
+    agree = True
     for w in range(1, 7):
         rk = RsaKey(k2.n, k2.e, k2.d, k2.p, k2.q, k2.dp, k2.dq, k2.qinv, window=w)
         out = torch.empty_like(c2)
         ms = timed(lambda: rk.decrypt(c2, use_crt=True, out=out), reps)
         row["decrypts_per_s"][str(w)] = round(16384 / ms * 1e3, 1)
+        torch.cuda.synchronize()
+        if first is None:
+            first = out.clone()
+        agree = agree and bool(torch.equal(out, first))
         rk.close()
+    row["windows_agree"] = agree   # every width's 16384 outputs bit-identical
     lines.append(row)
     # long exponents modulo a 2048-bit n
     k3 = gen.rsa_key(2048, seed=gen.config_seed(3, 1))

@@ -3,6 +3,7 @@
 
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -72,14 +73,18 @@ int upload(const std::vector<uint32_t> &v, uint32_t **out) {
 }
 
 // Device copies of the matrix-core base tables, per (base set, device).
-std::map<std::pair<const BaseSet *, int>, std::pair<std::shared_ptr<const BaseSet>, uint32_t *>> g_dev_mbases;
+// keyed by (base set, device, W, MT): the table's layout depends on the
+// kernel shape's waves and tiles per wave (not on its elements per tile)
+std::map<std::tuple<const BaseSet *, int, int, int>, std::pair<std::shared_ptr<const BaseSet>, uint32_t *>>
+    g_dev_mbases;
 
-int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const std::vector<uint32_t> &blob, uint32_t **out) {
+int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const MLayout &sh, const std::vector<uint32_t> &blob,
+                     uint32_t **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_dev_mu);
-    auto key = std::make_pair(bs.get(), dev);
+    auto key = std::make_tuple(bs.get(), dev, sh.W, sh.MT);
     auto it = g_dev_mbases.find(key);
     if (it != g_dev_mbases.end()) {
         *out = it->second.second;
@@ -94,11 +99,11 @@ int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const std::vector
 }
 
 // The device's copy of a base's matrix-engine table, if one was uploaded.
-uint32_t *resident_mfma_base(const BaseSet *bs) {
+uint32_t *resident_mfma_base(const BaseSet *bs, const MLayout &sh) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(g_dev_mu);
-    auto it = g_dev_mbases.find(std::make_pair(bs, dev));
+    auto it = g_dev_mbases.find(std::make_tuple(bs, dev, sh.W, sh.MT));
     return it == g_dev_mbases.end() ? nullptr : it->second.second;
 }
 
@@ -196,11 +201,11 @@ int ctx_from_plan(ModPlan &&mp, int window, int engine_req, int group, rns_ctx *
     if (c->engine == RNS_ENGINE_MATRIX) {
         mfma_shape_for(c->plan.base->K, c->mshape, group);
         // the base table is built only when no context has uploaded it yet
-        uint32_t *resident = resident_mfma_base(c->plan.base.get());
+        uint32_t *resident = resident_mfma_base(c->plan.base.get(), c->mshape);
         MfmaTables t = make_mfma_tables(c->plan, c->mshape, resident == nullptr, allow_scaled);
         if (resident)
             c->d_mbase = resident;
-        else if ((rc = device_mfma_base(c->plan.base, t.base, &c->d_mbase)))
+        else if ((rc = device_mfma_base(c->plan.base, c->mshape, t.base, &c->d_mbase)))
             return rc;
         if ((rc = upload(t.key, &c->d_mkey))) return rc;
         c->mscaled = t.scaled;

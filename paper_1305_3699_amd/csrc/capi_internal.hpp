@@ -100,10 +100,11 @@ namespace api {
 // Entry table of a context for its own L-limb inputs.
 const uint32_t *entry_of(const rns_ctx *c);
 // The device copy of a base set's matrix-engine table: uploads `blob` on the
-// first request per (base set, device); resident_mfma_base returns it if it
-// is already there (else null).
-int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const std::vector<uint32_t> &blob, uint32_t **out);
-uint32_t *resident_mfma_base(const BaseSet *bs);
+// first request per (base set, device, the shape's waves and tiles per wave);
+// resident_mfma_base returns it if it is already there (else null).
+int device_mfma_base(const std::shared_ptr<const BaseSet> &bs, const MLayout &sh, const std::vector<uint32_t> &blob,
+                     uint32_t **out);
+uint32_t *resident_mfma_base(const BaseSet *bs, const MLayout &sh);
 // Garner recombination of [m_p | m_q] rows into m (n_limbs limbs).
 int crt_combine(const rsa_key *key, const uint32_t *mpq, uint32_t *m, size_t batch, hipStream_t s);
 // The Garner launch arguments of that recombination.

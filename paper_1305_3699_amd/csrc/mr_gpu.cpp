@@ -461,12 +461,12 @@ int mr_base(int L, int dev, MrBase *out) {
     for (uint32_t m : bs.B) fits = fits && mfma_prime_fits(m, bs.K, false);
     for (uint32_t m : bs.Bp) fits = fits && mfma_prime_fits(m, bs.K, true);
     if (!fits) return api::fail(RNS_EUNSUPPORTED, "the base of these candidates has no matrix-engine kernel");
-    uint32_t *resident = api::resident_mfma_base(b.bs.get());
+    uint32_t *resident = api::resident_mfma_base(b.bs.get(), b.sh);
     if (resident) {
         b.d_mbase = resident;
     } else {
         MfmaTables t = make_mfma_tables(mp, b.sh, true);
-        if ((rc = api::device_mfma_base(b.bs, t.base, &b.d_mbase))) return rc;
+        if ((rc = api::device_mfma_base(b.bs, b.sh, t.base, &b.d_mbase))) return rc;
     }
     if ((rc = api::upload(make_mr_consts(bs), &b.d_consts))) return rc;
     cache[key] = b;

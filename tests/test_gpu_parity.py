@@ -566,10 +566,10 @@ def test_rsa1024_config_bit_exact():
     assert oracle.rows_to_ints(m) == ms
 
 
-def _rsa2048():
+def _rsa2048(**opts):
     from paper_1305_3699_amd import RsaKey
     key = gen.rsa_key(2048, seed=gen.config_seed(2, 1))
-    return key, RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv)
+    return key, RsaKey(key.n, key.e, key.d, key.p, key.q, key.dp, key.dq, key.qinv, **opts)
 
 
 def test_rsa2048_crt_decrypt_small():
@@ -583,10 +583,12 @@ def test_rsa2048_crt_decrypt_small():
     assert oracle.rows_to_ints(got[:8]) == [pow(x, key.d, key.n) for x in c[:8]]
 
 
-def test_rsa2048_crt_full_batch_sampled():
-    """The benchmark's launch: 16384 ciphertexts in one CRT decryption.  The
-    oracle checks 48 sampled rows; every row is checked by re-encryption."""
-    key, rk = _rsa2048()
+@pytest.mark.parametrize("window", [1, 2, 3, 4, 5, 6])
+def test_rsa2048_crt_full_batch_sampled(window):
+    """The benchmark's launch at each window width of the per-width sweep:
+    16384 ciphertexts in one CRT decryption.  The oracle checks 48 sampled
+    rows; every row is checked by re-encryption."""
+    key, rk = _rsa2048(window=window)
     B = 16384
     c = gen.uniform_below(key.n, B, seed=gen.config_seed(2, 2))
     cl = gen.to_limbs(c, 64)

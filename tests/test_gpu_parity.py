@@ -214,6 +214,30 @@ def test_scaled_and_unscaled_b_residues(bits):
         assert np.array_equal(_host(o), want)
 
 
+@pytest.mark.parametrize("bits,k", [(64, 3), (128, 5)])
+def test_scaled_b_residues_primes_1_mod_4(bits, k):
+    """The kernel's scaled form on an explicit base whose B primes are all
+    1 mod 4 (roots from the general square-root path; the first seeded draw
+    on which every channel has one): outputs equal the oracle's pow."""
+    from paper_1305_3699_amd import Plan
+    rng = random.Random(bits + 3)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = bits // 32
+    primes = None
+    for seed in range(400):
+        pr = gen.rns_primes(8 * k, seed=seed, lo=(1 << 32) - (1 << 24), hi=(1 << 32) - (1 << 19))
+        B, Bp = [m for m in pr if m % 4 == 1][:k], [m for m in pr if m % 4 == 3][:k]
+        if len(B) == k and len(Bp) == k and Plan(N, L, primes=B + Bp).info["scaled"]:
+            primes = B + Bp
+            break
+    assert primes is not None
+    ctx = _ctx(N, L, primes=primes)
+    assert ctx.info["scaled"] == 1
+    bases = gen.to_limbs([rng.getrandbits(bits) for _ in range(37)] + [0, 1, N - 1, N, (1 << bits) - 1], L)
+    e = gen.to_limbs(rng.getrandbits(bits) | 1, L)[0]
+    assert np.array_equal(_run_modexp(ctx, bases, e), oracle.modexp_batch(bases, e, gen.to_limbs(N, L)[0]))
+
+
 def test_rsa2048_crt_unscaled():
     """RSA-2048 CRT and plain decryption with the B residues unscaled
     (opts.unscaled) equal the oracle and the default (scaled) key."""

@@ -198,6 +198,38 @@ def test_emul_modexp_scaled_and_unscaled(bits, window, unscaled):
     assert np.array_equal(q.emul_modexp(gen.to_limbs(bases, L), el), want)
 
 
+def _scaled_base_1mod4(N: int, L: int, k: int):
+    """An explicit base whose B primes are all 1 mod 4 (square roots by
+    Tonelli-Shanks) and on which the key still takes the scaled form: the
+    first seeded draw where every c_i 2^-32 is a square (probability 2^-k)."""
+    for seed in range(400):
+        pr = gen.rns_primes(8 * k, seed=seed, lo=(1 << 32) - (1 << 24), hi=(1 << 32) - (1 << 19))
+        B = [m for m in pr if m % 4 == 1][:k]
+        Bp = [m for m in pr if m % 4 == 3][:k]
+        if len(B) < k or len(Bp) < k:
+            continue
+        p = Plan(N, L, primes=B + Bp)
+        if p.info["scaled"]:
+            return p
+    raise AssertionError("no scaled base found")
+
+
+@pytest.mark.parametrize("bits,k", [(64, 3), (128, 5)])
+def test_emul_modexp_scaled_primes_1_mod_4(bits, k):
+    """Scaled B residues on primes = 1 mod 4, whose roots come from the
+    general square-root path: the host model equals the oracle's pow."""
+    rng = random.Random(bits + 3)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = bits // 32
+    p = _scaled_base_1mod4(N, L, k)
+    assert p.info["k"] == k and all(m % 4 == 1 for m in p.primes[:k])
+    bases = [rng.getrandbits(bits) for _ in range(20)] + [0, 1, N - 1, N, (1 << bits) - 1]
+    e = rng.getrandbits(bits) | 1
+    el = gen.to_limbs(e, L)[0]
+    want = oracle.modexp_batch(gen.to_limbs(bases, L), el, gen.to_limbs(N, L)[0])
+    assert np.array_equal(p.emul_modexp(gen.to_limbs(bases, L), el), want)
+
+
 def test_engine_selection():
     assert Plan(3233).info["engine"] == rnsrsa.ENGINE_MATRIX          # auto: matrix cores when built
     assert Plan(3233, engine=rnsrsa.ENGINE_CHANNEL).info["engine"] == rnsrsa.ENGINE_CHANNEL

@@ -16,7 +16,9 @@
 // owns slot 4*mt + l/16 of tile mt for elements 16*nt + l%16, which is
 // exactly where the matrix core leaves the outputs of that slot, so the
 // per-channel steps run in place with no transposition.  Channel residues
-// are kept scaled: x*2^32 mod m in B, x*2^32*M^-1 mod m' in B'.
+// are kept scaled: x*2^32 mod m in B, x*2^32*M^-1 mod m' in B'; a key whose
+// tables hold the scaled form (SQ) keeps x*2^32*s_i mod m_i in B instead,
+// with s_i^2 = sigma_i c_i 2^-32, sigma_i = +-1 (see mfma_publish_xi).
 #pragma once
 
 #include "arith.hpp"
@@ -96,8 +98,10 @@ struct MState {
 typedef RNS_GLOBAL uint32_t gu32;
 typedef const RNS_GLOBAL mfma_v4i gcv4i;
 
-// Constants of one slot: its B prime with -m^-1 mod 2^32, nu = -M' R^2 and
-// c = -N^-1 M_i^-1; its B' prime with -m^-1 mod 2^32 and H = M (M'_t)^-1.
+// Constants of one slot: its B prime with -m^-1 mod 2^32, nu = -M' R^2 (times
+// s_i with scaled B residues) and
+// c = sigma_i (-N^-1 M_i^-1) (unused with scaled B residues); its B' prime
+// with -m^-1 mod 2^32 and H = M (M'_t)^-1.
 struct MSlotB {
     uint32_t m, u, nu, c;
 };

@@ -138,9 +138,20 @@ def build(jobs: int | None = None, verbose: bool = False, sanitize: bool = False
     units.sort(key=lambda u: -int(re.search(r"(?:shape|mmul)_(\d+)", u[0]).group(1))
                if re.search(r"(?:shape|mmul)_\d", u[0]) else 0)
     jobs = jobs or min(16, os.cpu_count() or 4)
+
+    def compile_unit(src, obj, flags):
+        try:
+            return _run([HIPCC] + COMMON + extra + flags + ["-c", src, "-o", obj], verbose)
+        except RuntimeError:
+            if not flags:
+                raise
+            # the scheduler choice is a tuning: a unit it fails to compile
+            # takes the default scheduler
+            print("note: %s compiled with the default scheduler" % os.path.basename(src), flush=True)
+            return _run([HIPCC] + COMMON + extra + ["-c", src, "-o", obj], verbose)
+
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(_run, [HIPCC] + COMMON + extra + flags + ["-c", src, "-o", obj], verbose)
-                for src, obj, flags in units]
+        futs = [ex.submit(compile_unit, src, obj, flags) for src, obj, flags in units]
         for f in futs:
             f.result()
     tmp = lib + ".tmp%d" % os.getpid()

@@ -82,6 +82,14 @@ struct MShp {
     // a workgroup may hold (every shape but the 513-channel one).
     static constexpr int PF_WORDS = W * SLOTS * 64;
     static constexpr bool PREFETCH = (size_t)(LDS_WORDS + PF_WORDS) * 4 <= 160 * 1024;
+    // Resident waves per SIMD the register allocation must allow (1: no
+    // constraint).  The 32-element tile at k = 33 keeps both extensions'
+    // tiles in registers (25 KB of LDS per workgroup) and would take 205
+    // VGPRs, i.e. 2 waves per SIMD; held to 168 VGPRs (3 waves, 4 workgroups
+    // and 128 elements per CU) it spills about 70 registers to scratch and
+    // still runs the RSA-2048 CRT launch 6% faster than the 16-element tile
+    // (4 waves per SIMD, 128 VGPRs, spilled in the hot loop: 2.5x slower).
+    static constexpr int WAVES_PER_EU = (K == 33 && NT == 2) ? 3 : 1;
 };
 
 template <int MT, int NT>
@@ -975,7 +983,8 @@ __device__ __forceinline__ void modexp_mfma_tile(const MJob &J, int e0, uint32_t
 // the per-lane addresses of the tile body live across it; the hardware
 // dispatcher refills the CUs as workgroups finish instead.)
 template <int K, int W, int MT, int NT, bool SQ>
-__global__ __launch_bounds__(64 * W) void modexp_mfma_kernel(ModexpMfmaLaunch A) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MShp<K, W, MT, NT>::WAVES_PER_EU)))
+void modexp_mfma_kernel(ModexpMfmaLaunch A) {
     using S = MShp<K, W, MT, NT>;
     __shared__ __attribute__((aligned(16))) uint32_t lds[S::LDS_WORDS];
     __shared__ __attribute__((aligned(16))) uint32_t ylds[S::PREFETCH ? S::PF_WORDS : 1];

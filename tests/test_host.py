@@ -247,7 +247,7 @@ def test_group_selection():
     for g in (16, 32):
         p = Plan(N, 32, group=g)
         assert p.info["engine"] == rnsrsa.ENGINE_MATRIX and p.info["group"] == g
-    assert Plan(N, 32).info["group"] == 16                           # default tile for k = 33
+    assert Plan(N, 32).info["group"] == 32                           # default tile for k = 33
     assert Plan((1 << 4095) + 4095, 128).info["group"] == 32         # default tile for k = 129
     small = (1 << 255) + 4095
     assert Plan(small, 8, group=16).info["group"] == 32              # no 16-element kernel for k = 9

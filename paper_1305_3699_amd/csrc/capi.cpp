@@ -244,13 +244,30 @@ int device_simds(int dev) {
     return it->second;
 }
 
+// Resident workgroups per CU of the exponentiation kernel of shape sh (the
+// occupancy query, once per shape and device; 0 if it fails).
+static int resident_per_cu(const MLayout &sh, int dev) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(sh.K, sh.W, sh.MT, sh.NT, dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) it = cache.emplace(key, mfma_blocks_per_cu(sh)).first;
+    return it->second;
+}
+
 MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev) {
     if (sh.NT != 2) return sh;
     MfmaShape alt;
     if (!mfma_shape_for(sh.K, alt, 16) || alt.NT != 1 || alt.W != sh.W || alt.MT != sh.MT) return sh;
     const int simds = device_simds(dev);
     if (!simds) return sh;
-    return 2 * tiles * (size_t)sh.W < 3 * (size_t)simds ? alt : sh;
+    // the 32-element tile unless its workgroups cannot fill the resident
+    // slots of every CU: then the 16-element tile's twice as many
+    // workgroups give the SIMDs more waves
+    const int per_cu = resident_per_cu(sh, dev);
+    if (per_cu <= 0) return 2 * tiles * (size_t)sh.W < 3 * (size_t)simds ? alt : sh;
+    return tiles < (size_t)(simds / 4) * per_cu ? alt : sh;
 }
 
 int spread_tile_elems(const MfmaShape &sh, size_t tiles, int dev) {

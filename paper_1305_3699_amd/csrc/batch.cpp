@@ -41,6 +41,7 @@ struct rsa_batch {
     hipGraphExec_t exec = nullptr;
     rsa_batch_info info{};
     std::vector<float> group_ms;        // autotune: time of each group's launch as tuned (ms)
+    std::vector<size_t> order;          // exponentiation groups in launch order (longest first)
     ~rsa_batch() {
         hipDeviceSynchronize();
         if (exec) hipGraphExecDestroy(exec);
@@ -78,8 +79,10 @@ int enqueue(rsa_batch *b, hipStream_t s) {
     hipError_t e = hipEventRecord(b->fork, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     // each exponentiation group on its stream, followed there by the Garner
-    // groups that need only its results; the others follow the join on s
-    for (size_t i = 0; i < b->plan.groups.size(); i++) {
+    // groups that need only its results; the others follow the join on s.
+    // The longest group is enqueued first, so its workgroups take their CUs
+    // before the shorter groups' fill the rest.
+    for (size_t i : b->order) {
         if ((e = hipStreamWaitEvent(b->streams[i], b->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         if ((e = launch_group(b->plan.groups[i], b->d_jobs[i], b->d_tables[i], b->streams[i])) != hipSuccess)
             return hip_fail(e, "grouped modexp launch");
@@ -298,6 +301,19 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
             b->plan.modmuls = 0;
             for (const JobGroup &g : b->plan.groups)
                 for (const PlannedJob &J : g.jobs) b->plan.modmuls += J.cost * (size_t)J.j.batch;
+        }
+        // launch order: longest group first, by its tuned launch time, else by
+        // its longest chain of products times the base size
+        {
+            std::vector<std::pair<double, size_t>> key;
+            for (size_t i = 0; i < b->plan.groups.size(); i++) {
+                const JobGroup &g = b->plan.groups[i];
+                double est = 0;
+                for (const PlannedJob &J : g.jobs) est = std::max(est, (double)J.cost * g.shape.K);
+                key.push_back({i < b->group_ms.size() ? (double)b->group_ms[i] : est, i});
+            }
+            std::stable_sort(key.begin(), key.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+            for (auto &kv : key) b->order.push_back(kv.second);
         }
         for (JobGroup &g : b->plan.groups) {
             std::vector<MJob> js;

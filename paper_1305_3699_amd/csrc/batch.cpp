@@ -27,8 +27,8 @@ struct rsa_batch {
     JobPlan plan;
     std::vector<MJob *> d_jobs;
     std::vector<uint32_t *> d_tables;
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> done;
+    std::vector<hipStream_t> streams;   // one per branch
+    std::vector<hipEvent_t> done;       // one per branch
     std::vector<GarnerGroup> ggroups;   // Garner steps, one grouped launch per base shape
     std::vector<GJob *> d_gjobs;
     std::vector<int> gdep;              // the one exponentiation group a Garner group waits for, or -1
@@ -41,7 +41,7 @@ struct rsa_batch {
     hipGraphExec_t exec = nullptr;
     rsa_batch_info info{};
     std::vector<float> group_ms;        // autotune: time of each group's launch as tuned (ms)
-    std::vector<size_t> order;          // exponentiation groups in launch order (longest first)
+    std::vector<std::vector<size_t>> branches;   // exponentiation groups per branch, in launch order
     ~rsa_batch() {
         hipDeviceSynchronize();
         if (exec) hipGraphExecDestroy(exec);
@@ -78,18 +78,22 @@ int dmalloc(void **p, size_t bytes, size_t *total) {
 int enqueue(rsa_batch *b, hipStream_t s) {
     hipError_t e = hipEventRecord(b->fork, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    // each exponentiation group on its stream, followed there by the Garner
-    // groups that need only its results; the others follow the join on s.
-    // The longest group is enqueued first, so its workgroups take their CUs
-    // before the shorter groups' fill the rest.
-    for (size_t i : b->order) {
-        if ((e = hipStreamWaitEvent(b->streams[i], b->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-        if ((e = launch_group(b->plan.groups[i], b->d_jobs[i], b->d_tables[i], b->streams[i])) != hipSuccess)
-            return hip_fail(e, "grouped modexp launch");
-        for (size_t j = 0; j < b->ggroups.size(); j++)
-            if (b->gdep[j] == (int)i && (e = launch_garner_group(b->ggroups[j], b->d_gjobs[j], b->streams[i])) != hipSuccess)
-                return hip_fail(e, "grouped Garner launch");
-        if ((e = hipEventRecord(b->done[i], b->streams[i])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    // each branch's exponentiation groups in turn on its stream, each
+    // followed there by the Garner groups that need only its results; the
+    // others follow the join on s.  Branches are enqueued longest first, so
+    // the longest group's workgroups take their CUs before the shorter
+    // groups' fill the rest.
+    for (size_t br = 0; br < b->branches.size(); br++) {
+        hipStream_t bs = b->streams[br];
+        if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        for (size_t i : b->branches[br]) {
+            if ((e = launch_group(b->plan.groups[i], b->d_jobs[i], b->d_tables[i], bs)) != hipSuccess)
+                return hip_fail(e, "grouped modexp launch");
+            for (size_t j = 0; j < b->ggroups.size(); j++)
+                if (b->gdep[j] == (int)i && (e = launch_garner_group(b->ggroups[j], b->d_gjobs[j], bs)) != hipSuccess)
+                    return hip_fail(e, "grouped Garner launch");
+        }
+        if ((e = hipEventRecord(b->done[br], bs)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
     if ((e = launch_range_check(b->range, s)) != hipSuccess) return hip_fail(e, "range check launch");
     int rc = launch_plain_and_garner(b->plan, s, true, false);
@@ -302,9 +306,15 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
             for (const JobGroup &g : b->plan.groups)
                 for (const PlannedJob &J : g.jobs) b->plan.modmuls += J.cost * (size_t)J.j.batch;
         }
-        // launch order: longest group first, by its tuned launch time, else by
-        // its longest chain of products times the base size
+        // Branches: at most kBranches concurrent streams (the device runs a
+        // few hardware queues, and two streams on one queue serialise in
+        // whatever order they were enqueued).  The groups are taken longest
+        // first (by tuned launch time, else by longest chain of products
+        // times the base size), each onto the branch with the least work so
+        // far, so short groups follow the short ones instead of waiting
+        // behind the longest.
         {
+            constexpr size_t kBranches = 4;
             std::vector<std::pair<double, size_t>> key;
             for (size_t i = 0; i < b->plan.groups.size(); i++) {
                 const JobGroup &g = b->plan.groups[i];
@@ -313,7 +323,24 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
                 key.push_back({i < b->group_ms.size() ? (double)b->group_ms[i] : est, i});
             }
             std::stable_sort(key.begin(), key.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-            for (auto &kv : key) b->order.push_back(kv.second);
+            const size_t nb = std::min(kBranches, key.size());
+            b->branches.assign(nb, {});
+            std::vector<double> load(nb, 0.0);
+            for (auto &kv : key) {
+                const size_t br = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                b->branches[br].push_back(kv.second);
+                load[br] += kv.first;
+            }
+            for (size_t br = 0; br < nb; br++) {
+                hipStream_t gs = nullptr;
+                hipEvent_t ge = nullptr;
+                hipError_t e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+                b->streams.push_back(gs);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+                e = hipEventCreateWithFlags(&ge, hipEventDisableTiming);
+                b->done.push_back(ge);
+                if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+            }
         }
         for (JobGroup &g : b->plan.groups) {
             std::vector<MJob> js;
@@ -328,14 +355,6 @@ int rsa_batch_create(const rsa_op *ops, size_t n_ops, const rsa_batch_opts *opts
             rc = dmalloc((void **)&dt, g.table_words() * sizeof(uint32_t), &b->info.workspace_bytes);
             b->d_tables.push_back(dt);
             if (rc) return rc;
-            hipStream_t gs = nullptr;
-            hipEvent_t ge = nullptr;
-            e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
-            b->streams.push_back(gs);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-            e = hipEventCreateWithFlags(&ge, hipEventDisableTiming);
-            b->done.push_back(ge);
-            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         }
         // Garner steps: one grouped launch per base shape, job tables on the
         // device; a group whose halves all come from one matrix-core

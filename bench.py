@@ -815,6 +815,51 @@ def run_tile_sweep(args) -> list:
     return lines
 
 
+def run_base_sweep(args) -> list:
+    """The base size as a tuning dimension: batches of exponentiations by a
+    full-length exponent modulo a seeded odd modulus, on the smallest base
+    the modulus fits (k_min) and on each larger base the matrix engine has a
+    kernel for (up to 129 channels), default tile, window 5.  The results
+    must not depend on the base; one line per (modulus size, k)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1305_3699_amd import RnsContext
+
+    lines = []
+    for bits, B in ((512, 16384), (1024, 16384), (1536, 8192), (2048, 8192)):
+        rng = random.Random(gen.config_seed(8, bits))
+        N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+        L = bits // 32
+        e = gen.random_exponent(bits, seed=gen.config_seed(8, bits + 1))
+        el = torch.from_numpy(gen.to_limbs(e, L)[0].view(np.int32)).cuda()
+        x = torch.from_numpy(gen.to_limbs([rng.getrandbits(bits - 1) for _ in range(B)], L)
+                             .view(np.int32)).cuda()
+        kmin = RnsContext(N, L, window=5).info["k"]
+        ref = None
+        for k in [k for k in (17, 33, 49, 65, 97, 129) if k >= kmin]:
+            ctx = RnsContext(N, L, k=k, window=5)
+            out = torch.empty_like(x)
+            ctx.modexp(x, el, out=out)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.tile_reps):
+                ctx.modexp(x, el, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out.clone()
+            row = {"modulus_bits": bits, "batch": B, "k": ctx.info["k"], "k_min": kmin,
+                   "group": ctx.info["group"], "ms": round(a.elapsed_time(b) / args.tile_reps, 3),
+                   "same_as_k_min": bool(torch.equal(out, ref))}
+            print("bases %s" % json.dumps(row), file=sys.stderr, flush=True)
+            lines.append(row)
+            ctx.close()
+    return lines
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -842,6 +887,8 @@ def main(argv=None) -> int:
     ap.add_argument("--tile-sweep", action="store_true",
                     help="only the timing of both workgroup tiles per base size (one JSON line per k)")
     ap.add_argument("--tile-reps", type=int, default=3)
+    ap.add_argument("--base-sweep", action="store_true",
+                    help="time exponentiations on the smallest base a modulus fits and on each larger one")
     ap.add_argument("--configs", action="store_true",
                     help="only the other measured configurations (RSA-1024 round trip, windows, long exponents, "
                          "RSA-3072/4096 CRT)")
@@ -882,6 +929,10 @@ def main(argv=None) -> int:
         return 0
     if args.tile_sweep:
         for line in run_tile_sweep(args):
+            print(json.dumps(line), flush=True)
+        return 0
+    if args.base_sweep:
+        for line in run_base_sweep(args):
             print(json.dumps(line), flush=True)
         return 0
     args.served_default = not args.no_served_leg and not args.sweep_window

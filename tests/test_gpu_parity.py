@@ -56,6 +56,22 @@ def _run_modexp(ctx, bases, exp):
     return _host(out)
 
 
+def _oracle_pow(bases, e, N):
+    """b^e mod N for each base, from the oracle: e an int shared by every
+    base, or a list with one exponent per base."""
+    bases = [int(b) for b in bases]
+    nl = lambda v: max(1, (int(v).bit_length() + 31) // 32)
+    bl = oracle.int_to_limbs(0, 1)[None, :] if not bases else np.stack(
+        [oracle.int_to_limbs(b, max(nl(v) for v in bases)) for b in bases])
+    if isinstance(e, (list, tuple)):
+        le = max([nl(v) for v in e] + [1])
+        el = np.stack([oracle.int_to_limbs(int(v), le) for v in e])
+    else:
+        el = oracle.int_to_limbs(int(e), nl(e))
+    out = oracle.modexp_batch(bl, el, oracle.int_to_limbs(N, nl(N)), nthreads=_threads())
+    return oracle.rows_to_ints(out)[:len(bases)]
+
+
 def test_toy_key_all_messages():
     """Encrypt and decrypt every m < 3233 with the textbook key (51 groups of
     64 plus a ragged tail of 33)."""
@@ -94,7 +110,7 @@ def test_edge_exponents():
     for e in (0, 1, 2, 3, 8, 65537, (1 << 64) - 1, (1 << 33) | (1 << 31) | 1, (1 << 63) | (1 << 32) | (1 << 30)):
         el = gen.to_limbs(e, 2)[0]
         got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
-        assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases], e
+        assert oracle.rows_to_ints(got) == _oracle_pow(bases, e, N), e
 
 
 @pytest.mark.parametrize("window", [2, 5, 6])
@@ -109,7 +125,7 @@ def test_windows_across_limbs(window):
     limbs = [rng.getrandbits(32) | (1 << 31) for _ in range(6)]
     e = sum(v << (32 * i) for i, v in enumerate(limbs))
     got = _run_modexp(ctx, gen.to_limbs(bases, 16), gen.to_limbs(e, 6)[0])
-    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
+    assert oracle.rows_to_ints(got) == _oracle_pow(bases, e, N)
 
 
 def test_per_element_exponents():
@@ -120,7 +136,7 @@ def test_per_element_exponents():
     bases = [rng.getrandbits(1024) for _ in range(B)]
     exps = [rng.getrandbits(rng.choice([0, 1, 7, 64, 130])) for _ in range(B)]
     got = _run_modexp(ctx, gen.to_limbs(bases, 32), gen.to_limbs(exps, 5))
-    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b, e in zip(bases, exps)]
+    assert oracle.rows_to_ints(got) == _oracle_pow(bases, exps, N)
 
 
 @pytest.mark.parametrize("window", [1, 2, 3, 4, 5, 6])
@@ -132,7 +148,7 @@ def test_window_invariance(window):
     e = rng.getrandbits(1024)
     el = gen.to_limbs(e, 32)[0]
     got = _run_modexp(ctx, gen.to_limbs(bases, 32), el)
-    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
+    assert oracle.rows_to_ints(got) == _oracle_pow(bases, e, N)
 
 
 @pytest.mark.parametrize("k,waves", [(17, 1), (17, 2), (33, 1), (33, 2), (33, 3), (33, 4), (49, 7), (65, 5)])
@@ -150,7 +166,22 @@ def test_shape_invariance(k, waves):
     e = rng.getrandbits(80)
     el = gen.to_limbs(e, 3)[0]
     got = _run_modexp(ctx, gen.to_limbs(bases, L), el)
-    assert oracle.rows_to_ints(got) == [pow(b, e, N) for b in bases]
+    assert oracle.rows_to_ints(got) == _oracle_pow(bases, e, N)
+
+
+@pytest.mark.parametrize("bits,k", [(512, 33), (512, 65), (1024, 49), (1024, 65), (1024, 97), (1536, 65), (2048, 129)])
+def test_base_size_invariance(bits, k):
+    """A base larger than the smallest one the modulus fits (the matrix
+    engine's kernels for k channels) gives the oracle's results."""
+    rng = random.Random(bits * 1000 + k)
+    N = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    L = bits // 32
+    ctx = _ctx(N, L, k=k)
+    assert ctx.info["k"] == k
+    bases = [rng.getrandbits(bits) for _ in range(40)] + [0, 1, N - 1]
+    e = rng.getrandbits(bits) | (1 << (bits - 1))
+    got = _run_modexp(ctx, gen.to_limbs(bases, L), gen.to_limbs(e, L)[0])
+    assert oracle.rows_to_ints(got) == _oracle_pow(bases, e, N)
 
 
 @pytest.mark.parametrize("bits", [20, 64, 130, 500, 1024, 1500, 2048, 3072, 4096])
@@ -604,7 +635,7 @@ def test_rsa2048_crt_decrypt_small():
     want = oracle.rsa_crt_batch(cl, key.p, key.q, key.dp, key.dq, key.qinv)
     assert np.array_equal(got, want)
     # the definition: c^d mod n
-    assert oracle.rows_to_ints(got[:8]) == [pow(x, key.d, key.n) for x in c[:8]]
+    assert oracle.rows_to_ints(got[:8]) == _oracle_pow(c[:8], key.d, key.n)
 
 
 @pytest.mark.parametrize("window", [1, 2, 3, 4, 5, 6])
@@ -926,7 +957,7 @@ def test_keygen_agrees_with_oracle(bits, count):
     assert np.array_equal(ch, oracle.modexp_batch(ml, gen.to_limbs(65537, 1)[0], gen.to_limbs(key.n, L)[0]))
     assert np.array_equal(_host(key.decrypt(c, use_crt=True)), ml)
     assert np.array_equal(_host(key.decrypt(c, use_crt=False)), ml)
-    assert oracle.rows_to_ints(ch[:2]) == [pow(m, 65537, key.n) for m in msgs[:2]]
+    assert oracle.rows_to_ints(ch[:2]) == _oracle_pow(msgs[:2], 65537, key.n)
     assert pow(pow(msgs[0], 65537, key.n), ref["d"], key.n) == msgs[0]
 
 
@@ -1023,8 +1054,8 @@ def test_rsa_input_range_status():
     assert rk.status() == 0
     c = rk.encrypt(x)
     assert rk.status() == 3 and rk.status() == 0
-    assert oracle.rows_to_ints(_host(c)) == [pow(v, key.e, key.n) for v in vals]
-    want_d = [pow(v, key.d, key.n) for v in vals]
+    assert oracle.rows_to_ints(_host(c)) == _oracle_pow(vals, key.e, key.n)
+    want_d = _oracle_pow(vals, key.d, key.n)
     for use_crt in (True, False):
         m = rk.decrypt(x, use_crt=use_crt)
         assert rk.status() == 3
@@ -1038,7 +1069,7 @@ def test_rsa_input_range_status():
     b.run()
     b.run()
     assert rk.status() == 12 and rk.status() == 0
-    assert oracle.rows_to_ints(_host(outs[0])) == [pow(v, key.e, key.n) for v in vals]
+    assert oracle.rows_to_ints(_host(outs[0])) == _oracle_pow(vals, key.e, key.n)
     assert oracle.rows_to_ints(_host(outs[1])) == want_d
     b.close()
     ok = _dev(gen.to_limbs(vals[6:], L))
@@ -1072,12 +1103,13 @@ def test_served_queue_limit_refuses_requests():
     assert st["rejected"] == n - 8 and st["completed"] == 8
     took = np.nonzero(lat >= 0)[0]
     assert took.size == 8 and np.all(lat[lat < 0] == -1.0)
+    want = _oracle_pow(vals, [key.e if kd == 0 else key.d for kd in kind], key.n)
     for i in range(n):
         got = int.from_bytes(outs[i].astype("<u4").tobytes(), "little")
         if lat[i] < 0:
             assert got == 0
         else:
-            assert got == pow(vals[i], key.e if kind[i] == 0 else key.d, key.n)
+            assert got == want[i]
     srv.close()
 
 

@@ -686,6 +686,8 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
         }
         key->h_e.assign(e, e + e_limbs);
         if (d) key->h_d.assign(d, d + n_limbs);
+        key->wc_e = window_costs(key->h_e);
+        if (d) key->wc_d = window_costs(key->h_d);
         if ((rc = upload(key->h_e, &key->d_e))) return rc;
         if (d && (rc = upload(key->h_d, &key->d_d))) return rc;
         if (all_crt) {
@@ -732,6 +734,8 @@ int rsa_key_load(const uint32_t *n, size_t n_limbs, const uint32_t *e, size_t e_
             if ((rc = upload(Eg, &key->d_gentry))) return rc;
             key->h_dp.assign(dp, dp + half_limbs);
             key->h_dq.assign(dq, dq + half_limbs);
+            key->wc_dp = window_costs(key->h_dp);
+            key->wc_dq = window_costs(key->h_dq);
             if ((rc = upload(key->h_dp, &key->d_dp))) return rc;
             if ((rc = upload(key->h_dq, &key->d_dq))) return rc;
             if ((rc = upload(std::vector<uint32_t>(q, q + half_limbs), &key->d_qlimbs))) return rc;

@@ -35,6 +35,15 @@ int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s);
 // Keep freed stream-ordered blocks in the device pool (once per process).
 void configure_pool_once();
 
+// Montgomery products of an exponentiation by one exponent for each window
+// width (mm[w], w = 1..6) and the width with the fewest, computed once when
+// a key is loaded so that planning a launch does not rescan the exponent.
+struct WindowCosts {
+    size_t mm[7] = {};
+    int best = 1;
+};
+WindowCosts window_costs(const std::vector<uint32_t> &e);
+
 }  // namespace api
 }  // namespace rnsrsa
 
@@ -71,6 +80,7 @@ struct rsa_key {
     size_t n_limbs = 0, e_limbs = 0, half = 0;
     std::vector<uint32_t> h_n;                    // host copy of n
     std::vector<uint32_t> h_e, h_dp, h_dq, h_d;   // host copies of the exponents
+    rnsrsa::api::WindowCosts wc_e, wc_dp, wc_dq, wc_d;   // their products per window width
     uint32_t *d_n = nullptr;                      // n on the device (input range check)
     unsigned long long *d_status = nullptr;       // inputs >= n seen since the last rsa_key_status
     rns_ctx *n = nullptr;

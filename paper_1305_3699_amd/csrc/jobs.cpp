@@ -31,6 +31,15 @@ size_t mm_count(const std::vector<uint32_t> &e, int w) {
     return n;
 }
 
+WindowCosts window_costs(const std::vector<uint32_t> &e) {
+    WindowCosts c;
+    for (int w = 1; w <= 6; w++) {
+        c.mm[w] = mm_count(e, w);
+        if (c.mm[w] < c.mm[c.best]) c.best = w;
+    }
+    return c;
+}
+
 int best_window(const std::vector<uint32_t> &e, int fixed) {
     if (fixed) return fixed;
     int best = 1;
@@ -65,7 +74,7 @@ void set_tuned_dw(const MLayout &s, int exp_limbs, int dw) {
 
 void set_job_window(PlannedJob &J, int dw) {
     J.j.window = std::min(6, std::max(1, J.w0 + dw));
-    J.cost = mm_count(*J.hexp, J.j.window);
+    J.cost = J.wc->mm[J.j.window];
 }
 
 int tuned_nt(const MLayout &s) {
@@ -86,7 +95,8 @@ size_t op_mpq_words(const rsa_key *key, int kind, size_t count) {
 int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
     std::map<std::tuple<int, int, int>, size_t> group_of;
     auto add_job = [&](const rns_ctx *c, const uint32_t *E, const uint32_t *x, const std::vector<uint32_t> &hx,
-                       const uint32_t *in, int in_limbs, uint32_t *o, int out_stride, size_t count) {
+                       const WindowCosts &wc, const uint32_t *in, int in_limbs, uint32_t *o, int out_stride,
+                       size_t count) {
         PlannedJob J{};
         J.j.mb = c->d_mbase;
         J.j.mk = c->d_mkey;
@@ -101,8 +111,8 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
         J.j.out_stride = out_stride;
         J.j.exp_limbs = (int)hx.size();
         J.j.exp_stride = 0;
-        J.w0 = best_window(hx, fixed_w);
-        J.hexp = &hx;
+        J.w0 = fixed_w ? fixed_w : wc.best;
+        J.wc = &wc;
         bool known = false;
         const int dw = fixed_w ? 0 : tuned_dw(c->mshape, (int)hx.size(), &known);
         set_job_window(J, dw);
@@ -144,8 +154,8 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             const int h = (int)k->half;
             if (!o.mpq) return fail(RNS_EINVAL, "no CRT scratch");
             if (k->p->engine == RNS_ENGINE_MATRIX) {
-                add_job(k->p, k->d_mcentry_p, k->d_dp, k->h_dp, o.in, nl, o.mpq, 2 * h, o.count);
-                add_job(k->q, k->d_mcentry_q, k->d_dq, k->h_dq, o.in, nl, o.mpq + h, 2 * h, o.count);
+                add_job(k->p, k->d_mcentry_p, k->d_dp, k->h_dp, k->wc_dp, o.in, nl, o.mpq, 2 * h, o.count);
+                add_job(k->q, k->d_mcentry_q, k->d_dq, k->h_dq, k->wc_dq, o.in, nl, o.mpq + h, 2 * h, o.count);
             } else {
                 P.plain.push_back(PlainJob{k->p, k->q, k->d_centry_p, k->d_centry_q, o.in, k->d_dp, k->d_dq, nl, h,
                                            o.mpq, o.mpq + h, 2 * h, o.count});
@@ -158,8 +168,9 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
             const rns_ctx *c = k->n;
             const uint32_t *x = enc ? k->d_e : k->d_d;
             const std::vector<uint32_t> &hx = enc ? k->h_e : k->h_d;
+            const WindowCosts &wc = enc ? k->wc_e : k->wc_d;
             if (c->engine == RNS_ENGINE_MATRIX) {
-                add_job(c, c->d_mentry, x, hx, o.in, nl, o.out, nl, o.count);
+                add_job(c, c->d_mentry, x, hx, wc, o.in, nl, o.out, nl, o.count);
             } else {
                 P.plain.push_back(PlainJob{c, nullptr, entry_of(c), nullptr, o.in, x, nullptr, nl, (int)hx.size(),
                                            o.out, nullptr, nl, o.count});

@@ -37,7 +37,7 @@ struct PlannedJob {
     MJob j;
     size_t cost;                          // Montgomery products per element
     int w0 = 1;                           // window with the fewest products for the exponent
-    const std::vector<uint32_t> *hexp = nullptr;   // host copy of the exponent (owned by the key)
+    const WindowCosts *wc = nullptr;      // products per window width for the exponent (owned by the key)
 };
 
 // Jobs of one matrix-core kernel shape: one launch.

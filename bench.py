@@ -901,7 +901,8 @@ def main(argv=None) -> int:
     ap.add_argument("--served-rates", type=float, nargs="+", default=[5000.0, 20000.0, 80000.0])
     ap.add_argument("--served-duration", type=float, default=10.0)
     ap.add_argument("--served-warmup", type=float, default=1.0)
-    ap.add_argument("--served-inflight", type=int, default=8)
+    ap.add_argument("--served-inflight", type=int, default=4,
+                    help="dispatch slots of the server (4: one per hardware queue of the process)")
     ap.add_argument("--served-max-ops", type=int, nargs="+", default=[0],
                     help="operations per dispatch at most (0: the server's default, 16384); one run per value")
     ap.add_argument("--calib-copy-mb", type=int, default=0,

@@ -469,9 +469,13 @@ void rsa_batch_free(rsa_batch *b);
  * grouped launches as rsa_batch does, and up to max_inflight dispatches run
  * concurrently on their own streams.
  *
- *   rsa_server_opts  hbm_budget: device bytes in-flight dispatches may hold
- *                    (0 = 64 GiB); max_inflight: concurrent dispatches
- *                    (0 = 8); max_dispatch_ops: requests per dispatch
+ *   rsa_server_opts  hbm_budget: device bytes in-flight dispatches may use
+ *                    (0 = 64 GiB; each dispatch slot also keeps its device
+ *                    arena, up to 1.25 x the largest dispatch it ran, until
+ *                    rsa_server_free); max_inflight: concurrent dispatches
+ *                    (0 = 4, the hardware queues HIP gives a process by
+ *                    default; streams beyond them share queues and
+ *                    serialise); max_dispatch_ops: requests per dispatch
  *                    (0 = 16384); max_pending: requests waiting for
  *                    admission at most (0 = no limit): a request arriving
  *                    while that many wait is refused (load shedding).

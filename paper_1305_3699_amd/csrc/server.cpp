@@ -103,8 +103,8 @@ struct rsa_server {
     std::vector<Slot> slots;
     ~rsa_server() {
         for (Slot &s : slots) {
+            if (s.d_arena) hipFreeAsync(s.d_arena, s.stream);   // stream-ordered, as it was allocated
             if (s.stream) hipStreamSynchronize(s.stream);
-            if (s.d_arena) hipFree(s.d_arena);
             if (s.done) hipEventDestroy(s.done);
             if (s.stream) hipStreamDestroy(s.stream);
             if (s.h_in) hipHostFree(s.h_in);

@@ -256,10 +256,13 @@ static int resident_per_cu(const MLayout &sh, int dev) {
     return it->second;
 }
 
-MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev) {
+MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev, bool small_jobs) {
     if (sh.NT != 2) return sh;
     MfmaShape alt;
     if (!mfma_shape_for(sh.K, alt, 16) || alt.NT != 1 || alt.W != sh.W || alt.MT != sh.MT) return sh;
+    // jobs of a few elements each: the 16-element tile needs hardly more
+    // workgroups, and each does half the work
+    if (small_jobs) return alt;
     const int simds = device_simds(dev);
     if (!simds) return sh;
     // the 32-element tile unless its workgroups cannot fill the resident
@@ -571,13 +574,7 @@ int rns_modexp_jobs(const rns_job *jobs, size_t njobs, void *hip_stream) {
         for (auto &kv : groups) {
             JobGroup &g = kv.second;
             finish_group(g);
-            if (g.auto_tile) {
-                const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, dev);
-                if (t.NT != g.shape.NT) {
-                    g.shape = t;
-                    finish_group(g);
-                }
-            }
+            if (g.auto_tile) retile_group(g, dev);
             // the job table's host copy is released by the stream once copied
             std::unique_ptr<std::vector<MJob>> host(new std::vector<MJob>());
             for (const PlannedJob &J : g.jobs) host->push_back(J.j);

@@ -125,7 +125,7 @@ GarnerLaunch garner_launch_of(const rsa_key *key, const uint32_t *mpq, uint32_t 
 // that the smaller tile's shorter per-wave work (and twice the workgroups)
 // wins; above it the 32-element tile's shared constant loads do (measured for
 // k = 17 .. 129).  Shapes without that alternative are returned unchanged.
-MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev);
+MfmaShape auto_tile(const MfmaShape &sh, size_t tiles, int dev, bool small_jobs = false);
 // SIMDs of device dev (4 per compute unit), cached; 0 if unknown.
 int device_simds(int dev);
 // Elements per tile for a matrix-core launch of `tiles` full tiles of shape

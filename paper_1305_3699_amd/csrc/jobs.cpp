@@ -180,14 +180,22 @@ int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_w, JobPlan &P) {
     }
     for (JobGroup &g : P.groups) {
         finish_group(g);
-        if (!g.auto_tile) continue;
-        const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, g.device);
-        if (t.NT != g.shape.NT) {
-            g.shape = t;
-            finish_group(g);
-        }
+        if (g.auto_tile) retile_group(g, g.device);
     }
     return RNS_OK;
+}
+
+void retile_group(JobGroup &g, int dev) {
+    size_t t32 = 0, t16 = 0;
+    for (const PlannedJob &J : g.jobs) {
+        t32 += ((size_t)J.j.batch + 31) / 32;
+        t16 += ((size_t)J.j.batch + 15) / 16;
+    }
+    const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, dev, 4 * t16 <= 5 * t32);
+    if (t.NT != g.shape.NT) {
+        g.shape = t;
+        finish_group(g);
+    }
 }
 
 void finish_group(JobGroup &g) {

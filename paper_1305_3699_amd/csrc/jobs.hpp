@@ -86,6 +86,10 @@ size_t op_mpq_words(const rsa_key *key, int kind, size_t count);
 int plan_jobs(const std::vector<PlannedOp> &ops, int fixed_window, JobPlan &out);
 // Assign tile0 in cost order and max_window for a group with its final shape.
 void finish_group(JobGroup &g);
+// The group's tile by auto_tile (the 16-element tile also when it needs at
+// most 1.25x the 32-element tile's workgroups: jobs of a few elements), then
+// finish_group again if it changed; g must be finished.
+void retile_group(JobGroup &g, int dev);
 
 // Per-process tile choice per (K, W, MT) from the batch autotuner (0: none).
 int tuned_nt(const MLayout &s);

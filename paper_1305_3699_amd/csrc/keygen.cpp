@@ -164,11 +164,7 @@ int exponentiate(const std::vector<Candidate> &cs, const std::vector<size_t> &wh
     for (auto &kv : groups) {
         JobGroup &g = kv.second;
         finish_group(g);
-        const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, g.device);
-        if (t.NT != g.shape.NT) {
-            g.shape = t;
-            finish_group(g);
-        }
+        retile_group(g, g.device);
         // the job table's host copy lives until the caller synchronises
         host_jobs.emplace_back();
         std::vector<MJob> &js = host_jobs.back();

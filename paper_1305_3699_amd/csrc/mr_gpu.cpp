@@ -562,11 +562,7 @@ int miller_rabin_gpu(const uint32_t *cand, size_t count, int L, const uint32_t *
         }
         if (g.jobs.empty()) break;
         finish_group(g);
-        const MfmaShape t = auto_tile(g.shape, (size_t)g.tiles, dev);
-        if (t.NT != g.shape.NT) {
-            g.shape = t;
-            finish_group(g);
-        }
+        retile_group(g, dev);
         host_jobs.emplace_back();
         std::vector<MJob> &js = host_jobs.back();
         for (const PlannedJob &J : g.jobs) js.push_back(J.j);

@@ -256,6 +256,35 @@ int tune_group(JobGroup &g, bool fixed_window, GroupTimer &tm, float *ms_out) {
     return RNS_OK;
 }
 
+// Per (kernel shape, exponent length) class of a batch: k, waves, tile,
+// window, offset and the tuned launch time; returns the class count (the
+// first `cap` are written).
+size_t batch_classes(const rsa_batch *b, rsa_batch_class *out, size_t cap) {
+    size_t i = 0;
+    for (size_t gi = 0; gi < b->plan.groups.size(); gi++) {
+        const JobGroup &g = b->plan.groups[gi];
+        std::map<int, std::vector<const PlannedJob *>> by_len;   // exponent limbs -> jobs
+        for (const PlannedJob &J : g.jobs) by_len[J.j.exp_limbs].push_back(&J);
+        for (auto it = by_len.rbegin(); it != by_len.rend(); ++it, ++i) {
+            if (i >= cap) continue;
+            const PlannedJob *heavy = *std::max_element(
+                it->second.begin(), it->second.end(),
+                [](const PlannedJob *x, const PlannedJob *y) { return x->cost < y->cost; });
+            rsa_batch_class &c = out[i];
+            c.k = g.shape.K;
+            c.waves = g.shape.W;
+            c.group = g.shape.NM();
+            c.exp_bits = 32 * it->first;
+            c.window = heavy->j.window;
+            c.window_offset = heavy->j.window - heavy->w0;
+            c.jobs = (int)it->second.size();
+            c.tuned = gi < b->group_ms.size() ? 1 : 0;
+            c.launch_ms = gi < b->group_ms.size() ? b->group_ms[gi] : 0.0;
+        }
+    }
+    return i;
+}
+
 }  // namespace
 
 extern "C" {
@@ -451,29 +480,11 @@ int rsa_batch_info_get(const rsa_batch *b, rsa_batch_info *info) {
 
 int rsa_batch_classes(const rsa_batch *b, rsa_batch_class *out, size_t cap, size_t *n) {
     if (!b || !n || (cap && !out)) return fail(RNS_EINVAL, "null argument");
-    size_t i = 0;
-    for (size_t gi = 0; gi < b->plan.groups.size(); gi++) {
-        const JobGroup &g = b->plan.groups[gi];
-        std::map<int, std::vector<const PlannedJob *>> by_len;   // exponent limbs -> jobs
-        for (const PlannedJob &J : g.jobs) by_len[J.j.exp_limbs].push_back(&J);
-        for (auto it = by_len.rbegin(); it != by_len.rend(); ++it, ++i) {
-            if (i >= cap) continue;
-            const PlannedJob *heavy = *std::max_element(
-                it->second.begin(), it->second.end(),
-                [](const PlannedJob *x, const PlannedJob *y) { return x->cost < y->cost; });
-            rsa_batch_class &c = out[i];
-            c.k = g.shape.K;
-            c.waves = g.shape.W;
-            c.group = g.shape.NM();
-            c.exp_bits = 32 * it->first;
-            c.window = heavy->j.window;
-            c.window_offset = heavy->j.window - heavy->w0;
-            c.jobs = (int)it->second.size();
-            c.tuned = gi < b->group_ms.size() ? 1 : 0;
-            c.launch_ms = gi < b->group_ms.size() ? b->group_ms[gi] : 0.0;
-        }
+    try {
+        *n = batch_classes(b, out, cap);
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
     }
-    *n = i;
     return ok();
 }
 

@@ -879,15 +879,19 @@ int rns_emul_modexp(const rns_plan *plan, const uint32_t *base, const uint32_t *
     if (batch == 0) return ok();
     if (!base || !exp || !out || exp_limbs == 0) return fail(RNS_EINVAL, "null buffer or zero exponent limbs");
     if (exp_stride != 0 && exp_stride < exp_limbs) return fail(RNS_EINVAL, "exp_stride below exp_limbs");
-    if (plan->engine == RNS_ENGINE_MATRIX) {
-        std::vector<uint32_t> E = make_mfma_entry_table(plan->plan, plan->mt.shape, {plan->plan.R2}, plan->plan.L);
-        if (!emul_modexp_mfma(plan->plan, plan->mt, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride,
-                              plan->window, out, batch))
-            return fail(RNS_EVERIFY, "a one-step reduction of the matrix-engine model left [0, m 2^32)");
-        return ok();
+    try {
+        if (plan->engine == RNS_ENGINE_MATRIX) {
+            std::vector<uint32_t> E = make_mfma_entry_table(plan->plan, plan->mt.shape, {plan->plan.R2}, plan->plan.L);
+            if (!emul_modexp_mfma(plan->plan, plan->mt, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride,
+                                  plan->window, out, batch))
+                return fail(RNS_EVERIFY, "a one-step reduction of the matrix-engine model left [0, m 2^32)");
+            return ok();
+        }
+        std::vector<uint32_t> E = make_entry_table(plan->plan, {plan->plan.R2}, plan->plan.L);
+        emul_modexp(plan->plan, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride, plan->window, out, batch);
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
     }
-    std::vector<uint32_t> E = make_entry_table(plan->plan, {plan->plan.R2}, plan->plan.L);
-    emul_modexp(plan->plan, E, plan->plan.L, base, exp, (int)exp_limbs, exp_stride, plan->window, out, batch);
     return ok();
 }
 

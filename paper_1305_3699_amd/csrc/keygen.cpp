@@ -323,7 +323,12 @@ int rsa_trial_division(const uint32_t *cand, size_t count, int limbs, int n_prim
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     SmallPrimes sp;
-    int rc = small_primes(dev, &sp);
+    int rc = RNS_OK;
+    try {
+        rc = small_primes(dev, &sp);
+    } catch (const std::bad_alloc &) {
+        rc = fail(RNS_ENOMEM, "out of host memory");
+    }
     if (rc) return rc;
     hipLaunchKernelGGL(trial_division_kernel, dim3((unsigned)count), dim3(kTdThreads), limbs * sizeof(uint32_t),
                        (hipStream_t)hip_stream, cand, limbs, sp.p, sp.inv, n_primes, flags);

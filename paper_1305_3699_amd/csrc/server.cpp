@@ -269,9 +269,7 @@ int dispatch(rsa_server *srv, Slot &sl, const rsa_request *reqs, const std::vect
 
 }  // namespace
 
-extern "C" {
-
-int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_server_opts *opts, rsa_server **out) {
+static int server_create(const rsa_key *const *keys, size_t n_keys, const rsa_server_opts *opts, rsa_server **out) {
     if (!out) return fail(RNS_EINVAL, "null output handle");
     *out = nullptr;
     if (!keys || !n_keys) return fail(RNS_EINVAL, "no keys");
@@ -301,7 +299,7 @@ int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_serve
     return ok();
 }
 
-int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double *latency, rsa_server_stats *stats) {
+static int server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double *latency, rsa_server_stats *stats) {
     if (!srv) return fail(RNS_EINVAL, "null server");
     if (n && !reqs) return fail(RNS_EINVAL, "null request list");
     std::vector<size_t> need(n);
@@ -460,6 +458,30 @@ int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double
     if (rejected)
         return fail(RNS_EBUSY, std::to_string(rejected) + " request(s) refused: admission queue full (max_pending)");
     return ok();
+}
+
+extern "C" {
+
+// No exception crosses the C ABI: host allocation failures become RNS_ENOMEM
+// (after the replay's dispatches in flight have finished).
+int rsa_server_create(const rsa_key *const *keys, size_t n_keys, const rsa_server_opts *opts, rsa_server **out) {
+    try {
+        return server_create(keys, n_keys, opts, out);
+    } catch (const std::bad_alloc &) {
+        return fail(RNS_ENOMEM, "out of host memory");
+    }
+}
+
+int rsa_server_replay(rsa_server *srv, const rsa_request *reqs, size_t n, double *latency, rsa_server_stats *stats) {
+    try {
+        return server_replay(srv, reqs, n, latency, stats);
+    } catch (const std::bad_alloc &) {
+        for (Slot &sl : srv->slots) {
+            hipStreamSynchronize(sl.stream);
+            sl.busy = false;
+        }
+        return fail(RNS_ENOMEM, "out of host memory");
+    }
 }
 
 void rsa_server_free(rsa_server *srv) { delete srv; }

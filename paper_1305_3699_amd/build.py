@@ -57,7 +57,8 @@ ILP_SCHED = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
 # Shapes measured faster with another scheduler: the 32-element tile at
 # k = 33, held to 168 VGPRs, with the memory-clause scheduler (RSA-2048 CRT
 # halves, 16,384 ciphertexts: 3.27 vs 3.66 ms with the iterative ILP one,
-# 3.39 ms with the default; every other shape measured slower with it).
+# 3.39 ms with the default; the other shapes measured slower with it or
+# within noise).
 SCHED_BY_SHAPE = {(33, 3, 3, 2): ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 HOST_SOURCES = ["capi.cpp", "noalloc.cpp", "mr_gpu.cpp", "batch.cpp", "jobs.cpp", "server.cpp", "keygen.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp",
                 "emul_mfma.cpp", "kernels_dispatch.cpp", "verify.cpp", "probe.cpp", "range.cpp"]

@@ -58,8 +58,10 @@ ILP_SCHED = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
 # k = 33, held to 168 VGPRs, with the memory-clause scheduler (RSA-2048 CRT
 # halves, 16,384 ciphertexts: 3.27 vs 3.66 ms with the iterative ILP one,
 # 3.39 ms with the default; the other shapes measured slower with it or
-# within noise).
-SCHED_BY_SHAPE = {(33, 3, 3, 2): ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
+# within noise) and the AMDGPU register-pressure trackers (51 instead of 55
+# spilled registers, 1-2% shorter launches in four alternating runs).
+SCHED_BY_SHAPE = {(33, 3, 3, 2): ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause",
+                                  "-mllvm", "-amdgpu-use-amdgpu-trackers=1"]}
 HOST_SOURCES = ["capi.cpp", "noalloc.cpp", "mr_gpu.cpp", "batch.cpp", "jobs.cpp", "server.cpp", "keygen.cpp", "plan.cpp", "plan_mfma.cpp", "emul.cpp",
                 "emul_mfma.cpp", "kernels_dispatch.cpp", "verify.cpp", "probe.cpp", "range.cpp"]
 
